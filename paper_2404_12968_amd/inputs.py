@@ -1,0 +1,282 @@
+"""Seeded synthetic workloads for lattice data assimilation.
+
+This module only draws inputs: truth fields, observation masks and noisy
+observations.  It holds none of the message-passing arithmetic and none of the
+prior-precision assembly, so both the GPU path and the CPU oracle can take
+their inputs from it without sharing any of the method's code.
+
+Workload shapes follow the paper's experiments: square synthetic grids with
+uniformly random observed cells (Section "Effect of Domain Size and
+Observation Density") and a large global grid observed along satellite ground
+tracks, periodic in longitude (Section "Large-scale Example").  The paper's
+own data (Met Office model output, ERA5 climatology, satellite ephemerides) is
+not public; the track generator below stands in for it.
+
+Random stream: ``numpy.random.default_rng(1000 * k + instance)`` for workload
+number k.  Within one problem the draw order is: truth, observation mask,
+observation noise.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+BC_NEUMANN = 0
+BC_PERIODIC = 1
+BC_DIRICHLET = 2
+
+BC_NAMES = {BC_NEUMANN: "neumann", BC_PERIODIC: "periodic", BC_DIRICHLET: "dirichlet"}
+
+
+@dataclasses.dataclass
+class Problem:
+    """One assimilation instance: grid, prior parameters, observations.
+
+    Cells are row-major, ``cell = y * nx + x``.  ``sigma`` is the observation
+    noise standard deviation; ``var`` (optional) overrides it per observation.
+    ``c`` is the re-weighting constant and ``damping`` the learning rate of
+    the damped update; ``dtype`` is the message-plane precision ("f32"/"f64").
+    """
+
+    name: str
+    nx: int
+    ny: int
+    bc_x: int
+    bc_y: int
+    alpha: int
+    kappa: float
+    tau: float
+    c: float
+    sigma: float
+    cells: np.ndarray
+    y: np.ndarray
+    hx: float = 1.0
+    hy: float = 1.0
+    var: Optional[np.ndarray] = None
+    truth: Optional[np.ndarray] = None
+    dtype: str = "f32"
+    damping: float = 0.5
+    rel_tol: float = 1e-6
+    max_iters: int = 100000
+    fixed_iters: Optional[int] = None
+    check_every: int = 10
+    seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def coverage(self) -> float:
+        return np.unique(self.cells).size / float(self.n)
+
+
+# --------------------------------------------------------------------------
+# truth fields
+# --------------------------------------------------------------------------
+
+def fourier_modes_field(nx: int, ny: int, rng: np.random.Generator,
+                        n_modes: int = 16, max_freq: int = 6) -> np.ndarray:
+    """Sum of ``n_modes`` random plane waves on the grid (shape (ny, nx)).
+
+    Amplitudes a_k ~ N(0, 1/n_modes), integer wave numbers (u_k, v_k) uniform
+    on [-max_freq, max_freq]^2 without (0, 0), phases uniform on [0, 2 pi).
+    Evaluated separably: cos(a + b) = cos a cos b - sin a sin b.
+    """
+    amp = rng.normal(0.0, np.sqrt(1.0 / n_modes), size=n_modes)
+    uv = np.zeros((n_modes, 2), dtype=np.int64)
+    for k in range(n_modes):
+        while True:
+            cand = rng.integers(-max_freq, max_freq + 1, size=2)
+            if cand[0] != 0 or cand[1] != 0:
+                uv[k] = cand
+                break
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    xs = np.arange(nx, dtype=np.float64)[:, None]
+    ys = np.arange(ny, dtype=np.float64)[:, None]
+    ax = 2.0 * np.pi * xs * uv[None, :, 0] / nx          # (nx, K)
+    ay = 2.0 * np.pi * ys * uv[None, :, 1] / ny + phase  # (ny, K)
+    f = (np.cos(ay) * amp) @ np.cos(ax).T - (np.sin(ay) * amp) @ np.sin(ax).T
+    return np.ascontiguousarray(f)
+
+
+def spectral_field(nx: int, ny: int, kappa: float, alpha: int,
+                   rng: np.random.Generator) -> np.ndarray:
+    """Periodic Gaussian random field with a Matern-type spectrum, unit variance.
+
+    Spectral synthesis: white complex noise on the discrete Fourier grid,
+    shaped by the continuous Matern spectral density
+    (kappa^2 + |omega|^2)^(-alpha), omega in radians per cell, then an inverse
+    real FFT.  This stands in for the paper's prior samples of the truth; it
+    does not use the discrete precision operator of the solver.
+    """
+    wx = 2.0 * np.pi * np.fft.rfftfreq(nx)
+    wy = 2.0 * np.pi * np.fft.fftfreq(ny)
+    spec = (kappa * kappa + wy[:, None] ** 2 + wx[None, :] ** 2) ** (-0.5 * alpha)
+    noise = rng.standard_normal((ny, wx.size, 2))
+    coef = (noise[..., 0] + 1j * noise[..., 1]) * spec
+    del noise
+    f = np.fft.irfft2(coef, s=(ny, nx))
+    f -= f.mean()
+    sd = f.std()
+    if sd > 0:
+        f /= sd
+    return np.ascontiguousarray(f)
+
+
+# --------------------------------------------------------------------------
+# observation masks
+# --------------------------------------------------------------------------
+
+def uniform_cells(n: int, frac: float, rng: np.random.Generator) -> np.ndarray:
+    """Distinct cells drawn uniformly at random, ``round(frac * n)`` of them, sorted."""
+    m = int(round(frac * n))
+    m = max(0, min(n, m))
+    cells = rng.choice(n, size=m, replace=False)
+    return np.sort(cells.astype(np.int64))
+
+
+def track_cells(nx: int, ny: int, n_tracks: int, run: int,
+                rng: np.random.Generator) -> np.ndarray:
+    """Union of diagonal satellite-like ground tracks, sorted distinct cells.
+
+    Track j has slope s_j = +-1 and x-offset x0_j uniform on {0..nx-1}; in row
+    y it covers the ``run`` cells starting at (x0_j + s_j*y - run//2) mod nx,
+    wrapping in x like a ground track.
+    """
+    ys = np.arange(ny, dtype=np.int64)
+    out = []
+    for _ in range(n_tracks):
+        s = 1 if rng.integers(0, 2) == 1 else -1
+        x0 = int(rng.integers(0, nx))
+        start = x0 + s * ys - run // 2
+        xs = (start[:, None] + np.arange(run, dtype=np.int64)[None, :]) % nx
+        out.append((ys[:, None] * nx + xs).ravel())
+    if not out:
+        return np.zeros(0, dtype=np.int64)
+    return np.unique(np.concatenate(out))
+
+
+def observe(truth: np.ndarray, cells: np.ndarray, sigma: float,
+            rng: np.random.Generator) -> np.ndarray:
+    """Noisy point observations y = f(cell) + sigma * eps, eps ~ N(0, 1)."""
+    flat = truth.reshape(-1)
+    return flat[cells] + sigma * rng.standard_normal(cells.size)
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+WORKLOADS = ("parity64", "tracks2048", "global8192", "batch256", "warm1024")
+_WORKLOAD_K = {name: k + 1 for k, name in enumerate(WORKLOADS)}
+
+# re-weighting constant by prior order: plain GaBP for the 5-point prior, the
+# paper's selected c = 10 for the 13-point prior (it diverges at c = 1).
+DEFAULT_C = {1: 1.0, 2: 10.0}
+
+
+def parity64(instance: int = 0) -> Problem:
+    """64x64 Neumann lattice, 5-point prior (kappa 0.2), 5 % random cells, FP64."""
+    rng = np.random.default_rng(1000 * 1 + instance)
+    nx = ny = 64
+    truth = fourier_modes_field(nx, ny, rng)
+    cells = uniform_cells(nx * ny, 0.05, rng)
+    sigma = 0.1
+    y = observe(truth, cells, sigma, rng)
+    return Problem("parity64", nx, ny, BC_NEUMANN, BC_NEUMANN, alpha=1, kappa=0.2,
+                   tau=1.0, c=DEFAULT_C[1], sigma=sigma, cells=cells, y=y, truth=truth,
+                   dtype="f64", damping=0.5, rel_tol=1e-10, seed=1000 + instance)
+
+
+def tracks2048(instance: int = 0, n: int = 2048) -> Problem:
+    """2048^2 Neumann lattice, 13-point prior (kappa 0.05), 40 tracks of 4 cells, FP32."""
+    rng = np.random.default_rng(1000 * 2 + instance)
+    truth = spectral_field(n, n, 0.05, 2, rng)
+    cells = track_cells(n, n, 40, 4, rng)
+    sigma = 0.05
+    y = observe(truth, cells, sigma, rng)
+    return Problem("tracks2048", n, n, BC_NEUMANN, BC_NEUMANN, alpha=2, kappa=0.05,
+                   tau=1.0, c=DEFAULT_C[2], sigma=sigma, cells=cells, y=y, truth=truth,
+                   dtype="f32", damping=0.5, fixed_iters=1000, seed=2000 + instance)
+
+
+def global8192(instance: int = 0, nx: int = 8192, ny: int = 4096,
+               keep_truth: bool = False) -> Problem:
+    """8192x4096 global-scale lattice, periodic in x, Neumann in y, 13-point prior
+    (kappa 0.02), 60 tracks of 7 cells (~5 %), FP32 messages, to 1e-6."""
+    rng = np.random.default_rng(1000 * 3 + instance)
+    truth = spectral_field(nx, ny, 0.02, 2, rng)
+    cells = track_cells(nx, ny, 60, 7, rng)
+    sigma = 0.05
+    y = observe(truth, cells, sigma, rng)
+    return Problem("global8192", nx, ny, BC_PERIODIC, BC_NEUMANN, alpha=2, kappa=0.02,
+                   tau=1.0, c=DEFAULT_C[2], sigma=sigma, cells=cells, y=y,
+                   truth=truth if keep_truth else None,
+                   dtype="f32", damping=0.5, rel_tol=1e-6, check_every=10,
+                   seed=3000 + instance)
+
+
+def batch256(count: int = 256, side_lo: int = 64, side_hi: int = 1024) -> List[Problem]:
+    """Uneven batch: square side ~ U{64..1024}, alpha ~ U{1,2}, kappa ~ U[0.02,0.3],
+    observed fraction ~ U[1 %, 20 %] (uniform cells), sigma ~ U[0.02, 0.2]."""
+    out = []
+    for inst in range(count):
+        rng = np.random.default_rng(1000 * 4 + inst)
+        side = int(rng.integers(side_lo, side_hi + 1))
+        alpha = int(rng.integers(1, 3))
+        kappa = float(rng.uniform(0.02, 0.3))
+        frac = float(rng.uniform(0.01, 0.20))
+        sigma = float(rng.uniform(0.02, 0.2))
+        truth = spectral_field(side, side, kappa, alpha, rng)
+        cells = uniform_cells(side * side, frac, rng)
+        y = observe(truth, cells, sigma, rng)
+        out.append(Problem(f"batch256[{inst}]", side, side, BC_NEUMANN, BC_NEUMANN,
+                           alpha=alpha, kappa=kappa, tau=1.0, c=DEFAULT_C[alpha],
+                           sigma=sigma, cells=cells, y=y, truth=None, dtype="f32",
+                           damping=0.5, rel_tol=1e-6, seed=4000 + inst))
+    return out
+
+
+def warm1024(instance: int = 0, n: int = 1024, kappa: Optional[float] = None) -> Problem:
+    """1024^2 Neumann lattice, 13-point prior, kappa ~ U[0.02, 0.3] unless given,
+    16 tracks of 4 cells (~6 %), sigma 0.05, FP32 to 1e-6."""
+    rng = np.random.default_rng(1000 * 5 + instance)
+    k = float(rng.uniform(0.02, 0.3)) if kappa is None else float(kappa)
+    truth = spectral_field(n, n, k, 2, rng)
+    cells = track_cells(n, n, 16, 4, rng)
+    sigma = 0.05
+    y = observe(truth, cells, sigma, rng)
+    return Problem(f"warm1024[{instance}]", n, n, BC_NEUMANN, BC_NEUMANN, alpha=2,
+                   kappa=k, tau=1.0, c=DEFAULT_C[2], sigma=sigma, cells=cells, y=y,
+                   truth=truth, dtype="f32", damping=0.5, rel_tol=1e-6,
+                   seed=5000 + instance)
+
+
+def small_lattice(nx: int, ny: int, alpha: int, *, bc_x: int = BC_NEUMANN,
+                  bc_y: int = BC_NEUMANN, kappa: float = 0.2, tau: float = 1.0,
+                  c: Optional[float] = None, frac: float = 0.05, sigma: float = 0.1,
+                  seed: int = 0, dtype: str = "f64", damping: float = 0.5,
+                  hx: float = 1.0, hy: float = 1.0, tracks: int = 0,
+                  run: int = 3) -> Problem:
+    """Generic small problem for tests: random (or track) cells on any grid/BC."""
+    rng = np.random.default_rng(seed)
+    truth = fourier_modes_field(nx, ny, rng, n_modes=8, max_freq=3)
+    if tracks > 0:
+        cells = track_cells(nx, ny, tracks, run, rng)
+    else:
+        cells = uniform_cells(nx * ny, frac, rng)
+    y = observe(truth, cells, sigma, rng)
+    return Problem(f"small{nx}x{ny}a{alpha}", nx, ny, bc_x, bc_y, alpha=alpha,
+                   kappa=kappa, tau=tau, c=DEFAULT_C[alpha] if c is None else c,
+                   sigma=sigma, cells=cells, y=y, truth=truth, dtype=dtype,
+                   damping=damping, hx=hx, hy=hy, seed=seed)
+
+
+def workload(name: str, instance: int = 0):
+    """Named workload by its name (see WORKLOADS)."""
+    fn = {"parity64": parity64, "tracks2048": tracks2048, "global8192": global8192,
+          "batch256": lambda instance=0: batch256(), "warm1024": warm1024}[name]
+    return fn(instance)
