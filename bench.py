@@ -1,0 +1,222 @@
+"""Benchmark of the lattice GaBP hot path on one MI355X.
+
+One step = one check interval of the solver: 10 flooding iterations of the
+fused message/belief kernel, then the FP64 posterior mean, the FP64 residual
+reduction and its read-back (the unit of work the convergence driver
+repeats).  Default workload: the 8192 x 4096 global-scale lattice (periodic
+in x, zero-flux in y, 13-point prior, kappa 0.02, 60 satellite-like tracks,
+~5 % coverage, FP32 messages, FP64 residual).
+
+Prints one JSON line with whole-job edge-message updates/s, the dominant
+kernel's roofline figures and the oracle's CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edge-message updates/s + HBM GB/s; time to 1e-6 rel. residual, warm vs cold"
+ITERS_PER_STEP = 10
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_iter_global8192_traffic.md")
+
+
+def edge_count(nx, ny, alpha, bcx, bcy):
+    """Directed edges of the lattice graph (pairs with Q_ij != 0)."""
+    from paper_2404_12968_amd.inputs import BC_PERIODIC
+    offs = [(1, 0), (-1, 0), (0, 1), (0, -1)]
+    if alpha == 2:
+        offs += [(2, 0), (-2, 0), (0, 2), (0, -2), (1, 1), (-1, -1), (1, -1), (-1, 1)]
+    total = 0
+    for dx, dy in offs:
+        cx = nx if bcx == BC_PERIODIC else max(0, nx - abs(dx))
+        cy = ny if bcy == BC_PERIODIC else max(0, ny - abs(dy))
+        total += cx * cy
+    return total
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lattice.h"):
+        with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_iter launch from the committed PMC summary, if it was
+    taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_source_digest():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(prob, seconds=10.0):
+    """The FP64 oracle, as it is, on a 2048 x 2048 crop of the same workload
+    (same prior, coverage pattern and noise), timed on all host cores."""
+    from oracle import oracle as O
+    from paper_2404_12968_amd import inputs as I
+    w = min(2048, prob.nx)
+    h = min(2048, prob.ny)
+    x0 = (prob.nx - w) // 2
+    y0 = (prob.ny - h) // 2
+    cx, cy = prob.cells % prob.nx, prob.cells // prob.nx
+    ins = (cx >= x0) & (cx < x0 + w) & (cy >= y0) & (cy < y0 + h)
+    sub = I.Problem("crop", w, h, I.BC_NEUMANN, I.BC_NEUMANN, prob.alpha, prob.kappa, prob.tau,
+                    prob.c, prob.sigma, (cy[ins] - y0) * w + (cx[ins] - x0), prob.y[ins],
+                    dtype="f64")
+    og = O.OracleGaBP.from_problem(sub)
+    og.iterate(2, prob.damping)
+    its = 0
+    t0 = time.perf_counter()
+    while True:
+        og.iterate(2, prob.damping)
+        its += 2
+        el = time.perf_counter() - t0
+        if el >= seconds and its >= 6:
+            break
+    return {"value": og.g.nnz * its / el, "unit": "edge-message updates/s",
+            "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {w}x{h} crop of the workload ({og.g.nnz} directed edges), "
+                      f"{its} iterations after 2 warm-up, {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="global8192", choices=["global8192", "tracks2048"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--solve", action="store_true",
+                    help="also time a cold solve to the workload's tolerance")
+    ap.add_argument("--solve-max-iters", type=int, default=200000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain device copy of known size (PMC byte calibration) and exit")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the lattice would shard into row strips with a halo exchange; not built).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = 1 << 28  # 1 GiB of float32
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return 0
+
+    from paper_2404_12968_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build()
+    from paper_2404_12968_amd import gabp as G
+    from paper_2404_12968_amd import inputs as I
+
+    prob = I.workload(args.workload)
+    E = edge_count(prob.nx, prob.ny, prob.alpha, prob.bc_x, prob.bc_y)
+    N = prob.n
+    esize = 4 if prob.dtype == "f32" else 8
+    # algorithmic bytes of one iteration: read + write every directed message
+    # (precision and information) once, read the two node terms once
+    alg_bytes = 4 * esize * E + 2 * esize * N
+
+    ctx = G.gabp_create_problem(prob, device=dev)
+    stream = ctx.stream
+
+    def step(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        G.gabp_iterate(ctx, ITERS_PER_STEP, prob.damping)
+        if ev1 is not None:
+            ev1.record(stream)
+        return G.gabp_residual(ctx)[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    rel = None
+    for k in range(args.steps):
+        rel = step(*evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iter_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * ITERS_PER_STEP)
+    total_iters = args.steps * ITERS_PER_STEP
+    value = E * total_iters / wall
+    achieved = alg_bytes / (iter_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge-message updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prob.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{prob.name}: {prob.nx}x{prob.ny} lattice, alpha={prob.alpha} "
+                               f"({'13' if prob.alpha == 2 else '5'}-point), kappa={prob.kappa}, "
+                               f"{prob.coverage * 100:.2f}% observed, c={prob.c}, "
+                               f"damping={prob.damping}, {prob.dtype} messages, FP64 residual",
+                   "nodes": N, "directed_edges": E, "iters_per_step": ITERS_PER_STEP,
+                   "parallelism": "single GPU"},
+        "hbm_gbps_algorithmic": achieved,
+        "iter_ms": iter_ms,
+        "rel_residual_after": rel,
+        "roofline": {"bound": "hbm", "kernel": "k_iter", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "traffic": traffic},
+    }
+    if args.solve:
+        ctx2 = G.gabp_create_problem(prob, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, it, r = G.gabp_solve(ctx2, args.solve_max_iters, prob.damping, prob.rel_tol,
+                                 prob.check_every)
+        torch.cuda.synchronize()
+        out["time_to_tol"] = {"tol": prob.rel_tol, "status": G.gabp_status_string(st),
+                              "iterations": it, "seconds": time.perf_counter() - t1,
+                              "rel_residual": r, "start": "cold"}
+        del ctx2
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

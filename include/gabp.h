@@ -1,0 +1,194 @@
+/*
+ * gabp.h -- C ABI of the MI355X (gfx950) lattice Gaussian belief propagation
+ * library for data assimilation on a Gaussian Markov random field.
+ *
+ * Model (paper: Section "Derivation of the Factor Graph", Section "Including
+ * Observations", Appendix "Details on the Finite Difference Discretisation"):
+ *   prior      f ~ N(0, Q^-1),  Q = tau * (kappa^2 I - Delta_h)^alpha, alpha in {1, 2},
+ *              Delta_h the 5-point finite-difference Laplacian on an nx x ny grid
+ *              (alpha = 1 gives a 5-point, alpha = 2 a 13-point precision stencil);
+ *   likelihood y_k ~ N(f[cell_k], s_k^2) at observed grid cells;
+ *   posterior  precision A = Q + H^T R^-1 H, information b = H^T R^-1 y (+ Q f_b).
+ * The library runs damped, re-weighted Gaussian belief propagation with a
+ * flooding schedule (Algorithms 1 and 2, inner procedure; Appendix sections
+ * "Gaussian Setting" and "Re-weighted message updates"; Section "Update
+ * Damping") and returns the posterior mean and approximate marginal variances
+ * (Compute Marginal).
+ *
+ * Conventions
+ *   - Grid cells are row-major, cell = y * nx + x, 0 <= x < nx, 0 <= y < ny.
+ *   - All arrays named "device" live in device memory of the context's GPU.
+ *   - Messages are in information form: a message into node i is the pair
+ *     (Lam, th) standing for exp(-1/2 Lam x^2 + th x).
+ *   - Stencil directions (deg = 4 for alpha = 1, 12 for alpha = 2), offset (dx, dy):
+ *       0 (+1, 0)   1 (-1, 0)   2 (0, +1)   3 (0, -1)
+ *       4 (+2, 0)   5 (-2, 0)   6 (0, +2)   7 (0, -2)
+ *       8 (+1, +1)  9 (-1, -1) 10 (+1, -1) 11 (-1, +1)
+ *     Plane d at cell (x, y) holds the message INTO (x, y) FROM
+ *     (x + dx, y + dy); the opposite direction of d is d ^ 1.  Slots whose
+ *     sender lies outside the grid (non-periodic axes) are always zero.
+ *   - Every call returns a gabp_status; the library never aborts and never
+ *     throws across this interface.  gabp_last_error() gives a text.
+ *   - A context is bound to one device and one stream and is not thread-safe.
+ */
+#ifndef GABP_H
+#define GABP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gabp_ctx gabp_ctx;
+
+typedef enum {
+    GABP_OK = 0,
+    GABP_E_INVALID = 1,       /* an argument is out of its documented range */
+    GABP_E_NOMEM = 2,         /* device or host allocation failed, or workspace too small */
+    GABP_E_DEVICE = 3,        /* a HIP runtime call failed */
+    GABP_E_DIVERGED = 4,      /* non-positive cavity precision, non-finite values, or residual blow-up */
+    GABP_E_NOT_CONVERGED = 5  /* max_iters reached before rel_tol */
+} gabp_status;
+
+typedef enum {
+    GABP_BC_NEUMANN = 0,   /* zero flux: graph Laplacian of the path (not in the paper; see reading) */
+    GABP_BC_PERIODIC = 1,  /* ghost points wrap (Appendix, discretisation) */
+    GABP_BC_DIRICHLET = 2  /* boundary values zero and removed (Appendix, discretisation) */
+} gabp_bc;
+
+typedef enum { GABP_F32 = 0, GABP_F64 = 1 } gabp_dtype;  /* message-plane precision */
+
+/* Grid: nx x ny cells with spacings hx, hy > 0 and one boundary type per axis. */
+typedef struct {
+    int64_t nx, ny;
+    double hx, hy;
+    int32_t bc_x, bc_y;   /* gabp_bc */
+} gabp_grid;
+
+/* Prior Q = tau (kappa^2 I - Delta_h)^alpha (Section "Derivation of the Factor
+ * Graph", the discretised SPDE) and the re-weighting constant c of the
+ * message updates (Appendix, "Re-weighted message updates"); c = 1 is plain
+ * Gaussian belief propagation. */
+typedef struct {
+    int32_t alpha;        /* 1 or 2 */
+    double kappa;         /* > 0 unless an axis is Dirichlet (then >= 0) */
+    double tau;           /* > 0 */
+    double c;             /* != 0, finite */
+} gabp_stencil;
+
+/* Point observations (Section "Including Observations"): y[k] observes cell
+ * cell[k].  Several observations of one cell multiply their likelihoods.
+ * cell and y are device pointers when on_device != 0, else host pointers.
+ * Copied (folded into node terms) at create; the caller keeps ownership. */
+typedef struct {
+    int64_t n;
+    const int64_t *cell;
+    const double *y;
+    int32_t on_device;
+} gabp_obs;
+
+/* Observation noise: variance sigma^2 for every observation, or var[k] when
+ * var != NULL (same memory space as the observations). */
+typedef struct {
+    double sigma;
+    const double *var;
+} gabp_noise;
+
+/* Options.  stream: the hipStream_t every call of the context is ordered on
+ * (NULL = the device's default stream).  workspace: device memory of at least
+ * gabp_workspace_size() bytes, owned by the caller and not freed by the
+ * library (NULL = the library allocates and frees its own).  prior_mean: a
+ * device array of nx*ny FP64 values f_b, or NULL for a zero prior mean. */
+typedef struct {
+    int32_t dtype;        /* gabp_dtype */
+    void *stream;
+    void *workspace;
+    size_t workspace_bytes;
+    const double *prior_mean;
+} gabp_opts;
+
+/* Bytes of device workspace a context needs for this grid, prior order and
+ * message precision: two message buffers (ping-pong) of 2*deg planes, the
+ * node planes and reduction scratch.  INVALID for bad grid/stencil/dtype. */
+gabp_status gabp_workspace_size(const gabp_grid *grid, const gabp_stencil *stencil,
+                                int32_t dtype, size_t *bytes);
+
+/* Build the factor graph of the posterior (Section "Derivation of the Factor
+ * Graph": one node per cell, an edge wherever Q_ij != 0, node factor from
+ * Q_ii and the observations) and set every message to zero (iteration 0).
+ * The off-diagonal precisions are not stored: kernels evaluate them from
+ * (alpha, kappa, tau, h, boundary, position).  Validates every argument
+ * (sizes >= 1; a periodic axis needs >= 3 cells for alpha = 1 and >= 5 for
+ * alpha = 2, where the stencil would alias; finite y and positive noise;
+ * cells in range) and returns INVALID on the first violation.  On success
+ * *out receives a context to be released with gabp_destroy. */
+gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil,
+                        const gabp_obs *obs, const gabp_noise *noise,
+                        const gabp_opts *opts, gabp_ctx **out);
+
+/* Run n_iters flooding iterations (Algorithm 2, inner loop): every new
+ * message is computed from the previous iteration's messages, then damped,
+ * m^t = (1 - damping) m^{t-1} + damping * m~ (Section "Update Damping"),
+ * damping in (0, 1].  Asynchronous on the context's stream.  n then m
+ * iterations give bitwise the same state as n + m.  A divergence is recorded
+ * on the device; the state then stays at the diverged iteration and the next
+ * synchronising call reports GABP_E_DIVERGED. */
+gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping);
+
+/* Iterate in chunks of check_every iterations until the FP64 relative
+ * residual ||A mu - b||_2 / ||b||_2 of the posterior mean is <= rel_tol
+ * (returns OK), max_iters total iterations were run (NOT_CONVERGED), or the
+ * run diverged (DIVERGED: invalid cavity precision, non-finite values, or a
+ * residual more than 1e3 times the first check's).  iters_done and
+ * rel_residual (either may be NULL) receive the iteration count and the last
+ * residual.  Synchronises the stream at every check. */
+gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double rel_tol,
+                       int32_t check_every, int64_t *iters_done, double *rel_residual);
+
+/* FP64 residual of the posterior mean of the current messages: abs = ||A mu - b||_2
+ * and rel = abs / ||b||_2 (rel = abs when b = 0).  Either pointer may be NULL.
+ * Synchronises the stream.  Returns DIVERGED if the run has diverged. */
+gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_residual);
+
+/* Marginals of the current messages (Compute Marginal): belief precision
+ * Lam_i = A_ii + c sum Lam_{k->i}, information th_i = b_i + c sum th_{k->i}
+ * accumulated in FP64; mean[i] = th_i / Lam_i, var[i] = 1 / Lam_i.  mean and
+ * var are caller-owned device arrays of nx*ny FP64 (row-major); either may be
+ * NULL.  Asynchronous on the context's stream. */
+gabp_status gabp_posterior(gabp_ctx *ctx, double *mean, double *var);
+
+/* The paper's early-stopping statistic (Appendix, Early Stop):
+ * mean|m^t - m^{t-1}| / mean|m^2 - m^1| over both components of every
+ * directed message.  Needs t >= 2 reached by gabp_iterate/gabp_solve since
+ * create (else INVALID).  Synchronises the stream. */
+gabp_status gabp_message_change(gabp_ctx *ctx, double *ratio);
+
+/* Copy the current messages out to (get) or in from (set) caller-owned device
+ * arrays prec and info, each deg*ny*nx values of the context's dtype, layout
+ * [deg][ny][nx].  set keeps the iteration counter; slots without a sender are
+ * forced to zero.  Used for checkpoint/resume and warm starts.  Async. */
+gabp_status gabp_get_messages(gabp_ctx *ctx, void *prec, void *info);
+gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info);
+
+/* Iterations applied so far (synchronises; returns DIVERGED with the
+ * diverged iteration if the run diverged). */
+gabp_status gabp_iteration_count(gabp_ctx *ctx, int64_t *iters);
+
+/* Number of stencil directions (4 or 12) of a context. */
+int32_t gabp_num_directions(const gabp_ctx *ctx);
+
+/* Release a context (frees only what the library allocated). NULL is a no-op. */
+void gabp_destroy(gabp_ctx *ctx);
+
+const char *gabp_status_string(gabp_status status);
+
+/* Text of the last error of ctx, or of the last failed create when ctx is NULL. */
+const char *gabp_last_error(const gabp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GABP_H */

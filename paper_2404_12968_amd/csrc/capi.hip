@@ -1,0 +1,538 @@
+// C ABI of the lattice Gaussian belief propagation library (include/gabp.h):
+// argument validation, workspace layout, context state and the host-side
+// drivers (iterate, solve with FP64 residual checks, posterior, checkpoint).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gabp.h"
+#include "internal.h"
+
+using gabp::Lattice;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kNumPartials = 2048;       // workgroups of the residual reduction
+constexpr size_t kAlign = 256;           // byte alignment of rows and planes
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device workspace layout.  Every plane has the same row pitch (elements);
+// message planes are separated by `plane` elements, which adds one 256-byte
+// skew so that the 2*deg concurrent streams do not start on the same HBM
+// channel.
+struct Layout {
+    int32_t pitch = 0;
+    int64_t plane = 0;        // message-plane stride, elements
+    size_t msg[2] = {0, 0};
+    size_t adiag64 = 0, b64 = 0, mu64 = 0, adiag_w = 0, b_w = 0;
+    size_t partials = 0, red = 0, flags = 0, total = 0;
+};
+
+Layout make_layout(int64_t nx, int64_t ny, int deg, size_t esize, bool f32) {
+    Layout l;
+    const size_t row_elems = kAlign / esize;
+    l.pitch = (int32_t)round_up((size_t)nx, row_elems);
+    const size_t node_elems = (size_t)l.pitch * (size_t)ny;
+    l.plane = (int64_t)(round_up(node_elems, row_elems) + row_elems);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = round_up(off + bytes, kAlign);
+        return o;
+    };
+    const size_t buf_bytes = (size_t)(2 * deg) * (size_t)l.plane * esize;
+    l.msg[0] = take(buf_bytes);
+    l.msg[1] = take(buf_bytes);
+    l.adiag64 = take(node_elems * 8);
+    l.b64 = take(node_elems * 8);
+    l.mu64 = take(node_elems * 8);
+    if (f32) {
+        l.adiag_w = take(node_elems * esize);
+        l.b_w = take(node_elems * esize);
+    }
+    l.partials = take((size_t)kNumPartials * 2 * sizeof(double));
+    l.red = take(8 * sizeof(double));
+    l.flags = take(4 * sizeof(uint32_t));
+    l.total = off;
+    return l;
+}
+
+struct HostMirror {
+    double red[8];
+    uint32_t flags[4];
+};
+
+std::string fmt(const char *f, double a = 0, double b = 0) {
+    char buf[256];
+    snprintf(buf, sizeof buf, f, a, b);
+    return buf;
+}
+
+}  // namespace
+
+struct gabp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Lattice L{};
+    int dtype = 0;
+    size_t esize = 4;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    Layout lay;
+    void *msg[2] = {nullptr, nullptr};
+    double *adiag64 = nullptr, *b64 = nullptr, *mu64 = nullptr;
+    void *adiag_w = nullptr, *b_w = nullptr;
+    double *partials = nullptr, *red = nullptr;
+    uint32_t *flags = nullptr;     // [0] diverged-at iteration, [1] input error
+    HostMirror *host = nullptr;    // pinned
+    int64_t iter = 0;
+    bool diverged = false;
+    bool prev_valid = false;       // the other buffer holds m^{iter-1}
+    bool have_ref = false;         // sum |m^2 - m^1| recorded in red[4]
+    std::string err;
+};
+
+namespace {
+
+gabp_status fail(gabp_ctx *ctx, gabp_status st, const std::string &msg) {
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+#define GABP_HIP(ctx, call)                                                               \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((ctx), GABP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+gabp_status check_grid_stencil(const gabp_grid *g, const gabp_stencil *s, int32_t dtype,
+                               std::string &why) {
+    if (!g || !s) return why = "grid and stencil are required", GABP_E_INVALID;
+    if (g->nx < 1 || g->ny < 1) return why = "nx and ny must be >= 1", GABP_E_INVALID;
+    if (!(g->hx > 0) || !(g->hy > 0) || !std::isfinite(g->hx) || !std::isfinite(g->hy))
+        return why = "hx and hy must be positive and finite", GABP_E_INVALID;
+    for (int32_t bc : {g->bc_x, g->bc_y})
+        if (bc < 0 || bc > 2) return why = "unknown boundary type", GABP_E_INVALID;
+    if (s->alpha != 1 && s->alpha != 2) return why = "alpha must be 1 or 2", GABP_E_INVALID;
+    const int64_t minp = s->alpha == 1 ? 3 : 5;
+    if ((g->bc_x == GABP_BC_PERIODIC && g->nx < minp) ||
+        (g->bc_y == GABP_BC_PERIODIC && g->ny < minp))
+        return why = "a periodic axis needs >= 3 cells (alpha 1) or >= 5 (alpha 2)",
+               GABP_E_INVALID;
+    const bool dirichlet = g->bc_x == GABP_BC_DIRICHLET || g->bc_y == GABP_BC_DIRICHLET;
+    if (!std::isfinite(s->kappa) || s->kappa < 0 || (s->kappa == 0 && !dirichlet))
+        return why = "kappa must be > 0 (>= 0 with a Dirichlet axis)", GABP_E_INVALID;
+    if (!(s->tau > 0) || !std::isfinite(s->tau)) return why = "tau must be > 0", GABP_E_INVALID;
+    if (!std::isfinite(s->c) || s->c == 0) return why = "c must be finite and non-zero", GABP_E_INVALID;
+    if (dtype != GABP_F32 && dtype != GABP_F64) return why = "unknown dtype", GABP_E_INVALID;
+    const int64_t pitch = (int64_t)round_up((size_t)g->nx, 64);
+    if (g->nx > (1 << 30) || g->ny > (1 << 30) || pitch * g->ny >= ((int64_t)1 << 31) - 4096)
+        return why = "grid too large for 32-bit in-plane indices", GABP_E_INVALID;
+    return GABP_OK;
+}
+
+Lattice make_lattice(const gabp_grid *g, const gabp_stencil *s, const Layout &lay) {
+    Lattice L{};
+    L.nx = (int32_t)g->nx;
+    L.ny = (int32_t)g->ny;
+    L.pitch = lay.pitch;
+    L.bcx = g->bc_x;
+    L.bcy = g->bc_y;
+    L.alpha = s->alpha;
+    L.deg = s->alpha == 1 ? 4 : 12;
+    L.tiles_x = (int32_t)((g->nx + 63) / 64);
+    L.plane = lay.plane;
+    L.kappa2 = s->kappa * s->kappa;
+    L.tau = s->tau;
+    L.ihx2 = 1.0 / (g->hx * g->hx);
+    L.ihy2 = 1.0 / (g->hy * g->hy);
+    L.c = s->c;
+    L.inv_c = 1.0 / s->c;
+    return L;
+}
+
+gabp_status ctx_ok(gabp_ctx *ctx) {
+    if (!ctx) return GABP_E_INVALID;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return fail(ctx, GABP_E_DEVICE, "hipSetDevice failed");
+    return GABP_OK;
+}
+
+// Copy the device flags (and reduction results) to the pinned mirror, wait,
+// and fold a recorded divergence into the host state.
+gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
+    GABP_HIP(ctx, hipMemcpyAsync(ctx->host->flags, ctx->flags, 4 * sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+    if (with_red)
+        GABP_HIP(ctx, hipMemcpyAsync(ctx->host->red, ctx->red, 8 * sizeof(double),
+                                     hipMemcpyDeviceToHost, ctx->stream));
+    GABP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const uint32_t t = ctx->host->flags[0];
+    if (t != 0u && !ctx->diverged) {
+        ctx->diverged = true;
+        ctx->iter = (int64_t)t;
+    }
+    if (ctx->diverged)
+        return fail(ctx, GABP_E_DIVERGED,
+                    fmt("diverged at iteration %.0f (non-positive cavity precision or non-finite message)",
+                        (double)ctx->iter));
+    return GABP_OK;
+}
+
+const void *cur_msgs(const gabp_ctx *ctx) { return ctx->msg[ctx->iter & 1]; }
+
+}  // namespace
+
+extern "C" {
+
+const char *gabp_status_string(gabp_status st) {
+    switch (st) {
+        case GABP_OK: return "ok";
+        case GABP_E_INVALID: return "invalid argument";
+        case GABP_E_NOMEM: return "out of memory";
+        case GABP_E_DEVICE: return "device error";
+        case GABP_E_DIVERGED: return "diverged";
+        case GABP_E_NOT_CONVERGED: return "not converged";
+    }
+    return "unknown status";
+}
+
+const char *gabp_last_error(const gabp_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+gabp_status gabp_workspace_size(const gabp_grid *grid, const gabp_stencil *stencil,
+                                int32_t dtype, size_t *bytes) {
+    std::string why;
+    gabp_status st = check_grid_stencil(grid, stencil, dtype, why);
+    if (st != GABP_OK) return fail(nullptr, st, why);
+    if (!bytes) return fail(nullptr, GABP_E_INVALID, "bytes is NULL");
+    const int deg = stencil->alpha == 1 ? 4 : 12;
+    const size_t es = dtype == GABP_F32 ? 4 : 8;
+    *bytes = make_layout(grid->nx, grid->ny, deg, es, dtype == GABP_F32).total;
+    return GABP_OK;
+}
+
+int32_t gabp_num_directions(const gabp_ctx *ctx) { return ctx ? ctx->L.deg : 0; }
+
+gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil, const gabp_obs *obs,
+                        const gabp_noise *noise, const gabp_opts *opts, gabp_ctx **out) {
+    if (!out) return fail(nullptr, GABP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const int32_t dtype = opts ? opts->dtype : GABP_F32;
+    std::string why;
+    gabp_status st = check_grid_stencil(grid, stencil, dtype, why);
+    if (st != GABP_OK) return fail(nullptr, st, why);
+    if (!noise) return fail(nullptr, GABP_E_INVALID, "noise is required");
+    if (!noise->var && (!(noise->sigma > 0) || !std::isfinite(noise->sigma)))
+        return fail(nullptr, GABP_E_INVALID, "sigma must be positive and finite");
+    const int64_t nobs = obs ? obs->n : 0;
+    if (nobs < 0) return fail(nullptr, GABP_E_INVALID, "negative observation count");
+    if (nobs > 0 && (!obs->cell || !obs->y))
+        return fail(nullptr, GABP_E_INVALID, "observation arrays are NULL");
+    const int64_t N = grid->nx * grid->ny;
+    const bool obs_dev = obs && obs->on_device;
+    if (nobs > 0 && !obs_dev) {
+        for (int64_t k = 0; k < nobs; ++k) {
+            if (obs->cell[k] < 0 || obs->cell[k] >= N)
+                return fail(nullptr, GABP_E_INVALID, fmt("observation %.0f: cell out of range", (double)k));
+            if (!std::isfinite(obs->y[k]))
+                return fail(nullptr, GABP_E_INVALID, fmt("observation %.0f: y not finite", (double)k));
+            if (noise->var && (!(noise->var[k] > 0) || !std::isfinite(noise->var[k])))
+                return fail(nullptr, GABP_E_INVALID, fmt("observation %.0f: variance not positive", (double)k));
+        }
+    }
+
+    gabp_ctx *ctx = new (std::nothrow) gabp_ctx();
+    if (!ctx) return fail(nullptr, GABP_E_NOMEM, "host allocation failed");
+    auto bail = [&](gabp_status s2) {
+        g_create_error = ctx->err;
+        gabp_destroy(ctx);
+        return s2;
+    };
+    ctx->dtype = dtype;
+    ctx->esize = dtype == GABP_F32 ? 4 : 8;
+    const int deg = stencil->alpha == 1 ? 4 : 12;
+    ctx->lay = make_layout(grid->nx, grid->ny, deg, ctx->esize, dtype == GABP_F32);
+    ctx->L = make_lattice(grid, stencil, ctx->lay);
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        ctx->err = "no HIP device";
+        return bail(GABP_E_DEVICE);
+    }
+    // NULL selects the device's default (null) stream, which is also what
+    // PyTorch's default stream is.
+    ctx->stream = opts ? (hipStream_t)opts->stream : nullptr;
+    if (opts && opts->workspace) {
+        if (opts->workspace_bytes < ctx->lay.total) {
+            ctx->err = fmt("workspace too small: %.0f bytes needed", (double)ctx->lay.total);
+            return bail(GABP_E_NOMEM);
+        }
+        if (((uintptr_t)opts->workspace) % kAlign != 0) {
+            ctx->err = "workspace must be 256-byte aligned";
+            return bail(GABP_E_INVALID);
+        }
+        ctx->ws = (char *)opts->workspace;
+        ctx->ws_bytes = opts->workspace_bytes;
+    } else {
+        if (hipMalloc((void **)&ctx->ws, ctx->lay.total) != hipSuccess) {
+            ctx->ws = nullptr;
+            ctx->err = fmt("hipMalloc of %.0f bytes failed", (double)ctx->lay.total);
+            return bail(GABP_E_NOMEM);
+        }
+        ctx->own_ws = true;
+        ctx->ws_bytes = ctx->lay.total;
+    }
+    if (hipHostMalloc((void **)&ctx->host, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
+        ctx->host = nullptr;
+        ctx->err = "pinned host allocation failed";
+        return bail(GABP_E_NOMEM);
+    }
+    const Layout &lay = ctx->lay;
+    ctx->msg[0] = ctx->ws + lay.msg[0];
+    ctx->msg[1] = ctx->ws + lay.msg[1];
+    ctx->adiag64 = (double *)(ctx->ws + lay.adiag64);
+    ctx->b64 = (double *)(ctx->ws + lay.b64);
+    ctx->mu64 = (double *)(ctx->ws + lay.mu64);
+    if (dtype == GABP_F32) {
+        ctx->adiag_w = ctx->ws + lay.adiag_w;
+        ctx->b_w = ctx->ws + lay.b_w;
+    } else {
+        ctx->adiag_w = ctx->adiag64;
+        ctx->b_w = ctx->b64;
+    }
+    ctx->partials = (double *)(ctx->ws + lay.partials);
+    ctx->red = (double *)(ctx->ws + lay.red);
+    ctx->flags = (uint32_t *)(ctx->ws + lay.flags);
+
+    // Zero everything: both message buffers (slots without a sender stay 0
+    // for ever), the node accumulators and the flags.
+    if (hipMemsetAsync(ctx->ws, 0, lay.total, ctx->stream) != hipSuccess) {
+        ctx->err = "hipMemsetAsync failed";
+        return bail(GABP_E_DEVICE);
+    }
+    int64_t *tmp_cell = nullptr;
+    double *tmp_y = nullptr, *tmp_var = nullptr;
+    const int64_t *d_cell = nullptr;
+    const double *d_y = nullptr, *d_var = nullptr;
+    if (nobs > 0) {
+        if (obs_dev) {
+            d_cell = obs->cell;
+            d_y = obs->y;
+            d_var = noise->var;
+        } else {
+            bool ok = hipMalloc((void **)&tmp_cell, nobs * sizeof(int64_t)) == hipSuccess &&
+                      hipMalloc((void **)&tmp_y, nobs * sizeof(double)) == hipSuccess &&
+                      (!noise->var || hipMalloc((void **)&tmp_var, nobs * sizeof(double)) == hipSuccess);
+            ok = ok &&
+                 hipMemcpyAsync(tmp_cell, obs->cell, nobs * sizeof(int64_t), hipMemcpyHostToDevice,
+                                ctx->stream) == hipSuccess &&
+                 hipMemcpyAsync(tmp_y, obs->y, nobs * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream) == hipSuccess &&
+                 (!noise->var || hipMemcpyAsync(tmp_var, noise->var, nobs * sizeof(double),
+                                                hipMemcpyHostToDevice, ctx->stream) == hipSuccess);
+            if (!ok) {
+                (void)hipStreamSynchronize(ctx->stream);
+                (void)hipFree(tmp_cell);
+                (void)hipFree(tmp_y);
+                (void)hipFree(tmp_var);
+                ctx->err = "staging observations on the device failed";
+                return bail(GABP_E_NOMEM);
+            }
+            d_cell = tmp_cell;
+            d_y = tmp_y;
+            d_var = tmp_var;
+        }
+    }
+    const double s2 = noise->var ? 0.0 : noise->sigma * noise->sigma;
+    hipError_t e = gabp::launch_setup(dtype == GABP_F32 ? 0 : 1, ctx->L, nobs, d_cell, d_y, d_var,
+                                      s2, ctx->adiag64, ctx->b64, opts ? opts->prior_mean : nullptr,
+                                      dtype == GABP_F32 ? ctx->adiag_w : nullptr,
+                                      dtype == GABP_F32 ? ctx->b_w : nullptr, ctx->flags + 1,
+                                      ctx->stream);
+    hipError_t e2 = hipMemcpyAsync(ctx->host->flags, ctx->flags, 4 * sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, ctx->stream);
+    hipError_t e3 = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp_cell);
+    (void)hipFree(tmp_y);
+    (void)hipFree(tmp_var);
+    if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        ctx->err = std::string("setup failed: ") +
+                   hipGetErrorString(e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3));
+        return bail(GABP_E_DEVICE);
+    }
+    if (ctx->host->flags[1] != 0u) {
+        ctx->err = "invalid observation (cell out of range, non-finite value or non-positive "
+                   "variance) or non-finite prior mean";
+        return bail(GABP_E_INVALID);
+    }
+    ctx->iter = 0;
+    *out = ctx;
+    return GABP_OK;
+}
+
+void gabp_destroy(gabp_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->host) (void)hipHostFree(ctx->host);
+    delete ctx;
+}
+
+gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (n_iters < 0) return fail(ctx, GABP_E_INVALID, "n_iters must be >= 0");
+    if (!(damping > 0.0) || !(damping <= 1.0))
+        return fail(ctx, GABP_E_INVALID, "damping must be in (0, 1]");
+    if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
+    if (ctx->iter + n_iters >= (int64_t)UINT32_MAX)
+        return fail(ctx, GABP_E_INVALID, "iteration counter overflow");
+    const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
+    for (int32_t k = 0; k < n_iters; ++k) {
+        const int64_t t = ctx->iter + 1;
+        GABP_HIP(ctx, gabp::launch_iter(dt, ctx->L, ctx->msg[(t - 1) & 1], ctx->msg[t & 1],
+                                        ctx->adiag_w, ctx->b_w, damping, ctx->flags,
+                                        (uint32_t)t, ctx->stream));
+        ctx->iter = t;
+        if (t == 2) {
+            const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
+            GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[0], ctx->msg[1], n, ctx->partials,
+                                                  kNumPartials, ctx->red + 4, ctx->stream));
+            ctx->have_ref = true;
+        }
+    }
+    if (n_iters > 0) ctx->prev_valid = true;
+    return GABP_OK;
+}
+
+gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_residual) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
+    const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
+    GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64, ctx->mu64,
+                                    nullptr, nullptr, ctx->stream));
+    GABP_HIP(ctx, gabp::launch_resid(ctx->L, ctx->mu64, ctx->adiag64, ctx->b64, ctx->partials,
+                                     kNumPartials, ctx->red, ctx->stream));
+    st = sync_flags(ctx, true);
+    if (st != GABP_OK) return st;
+    const double a = std::sqrt(ctx->host->red[0]), b = std::sqrt(ctx->host->red[1]);
+    if (abs_residual) *abs_residual = a;
+    if (rel_residual) *rel_residual = b > 0 ? a / b : a;
+    return GABP_OK;
+}
+
+gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double rel_tol,
+                       int32_t check_every, int64_t *iters_done, double *rel_residual) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (max_iters < 0 || check_every < 1 || !(rel_tol >= 0))
+        return fail(ctx, GABP_E_INVALID, "need max_iters >= 0, check_every >= 1, rel_tol >= 0");
+    double rel = INFINITY, first = -1.0;
+    int64_t run = 0;
+    st = GABP_E_NOT_CONVERGED;
+    while (run < max_iters) {
+        const int32_t k = (int32_t)std::min<int64_t>(check_every, max_iters - run);
+        gabp_status s1 = gabp_iterate(ctx, k, damping);
+        if (s1 != GABP_OK) {
+            st = s1;
+            break;
+        }
+        run += k;
+        s1 = gabp_residual(ctx, &rel, nullptr);
+        if (s1 != GABP_OK) {
+            st = s1;
+            break;
+        }
+        if (!std::isfinite(rel) || (first > 0 && rel > 1e3 * first)) {
+            st = fail(ctx, GABP_E_DIVERGED, fmt("residual blew up to %g at iteration %.0f", rel,
+                                                (double)ctx->iter));
+            break;
+        }
+        if (first < 0) first = rel;
+        if (rel <= rel_tol) {
+            st = GABP_OK;
+            break;
+        }
+    }
+    if (st == GABP_E_NOT_CONVERGED) {
+        if (max_iters == 0) {
+            gabp_status s1 = gabp_residual(ctx, &rel, nullptr);
+            if (s1 != GABP_OK) st = s1;
+            else if (rel <= rel_tol) st = GABP_OK;
+        }
+        if (st == GABP_E_NOT_CONVERGED)
+            fail(ctx, st, fmt("relative residual %g after %.0f iterations", rel, (double)ctx->iter));
+    }
+    if (iters_done) *iters_done = ctx->iter;
+    if (rel_residual) *rel_residual = rel;
+    return st;
+}
+
+gabp_status gabp_posterior(gabp_ctx *ctx, double *mean, double *var) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
+    GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64, nullptr,
+                                    mean, var, ctx->stream));
+    return GABP_OK;
+}
+
+gabp_status gabp_message_change(gabp_ctx *ctx, double *ratio) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (!ratio) return fail(ctx, GABP_E_INVALID, "ratio is NULL");
+    if (!ctx->have_ref || !ctx->prev_valid || ctx->iter < 2)
+        return fail(ctx, GABP_E_INVALID, "needs two consecutive iterations past t = 2");
+    const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
+    const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
+    GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[ctx->iter & 1], ctx->msg[(ctx->iter - 1) & 1],
+                                          n, ctx->partials, kNumPartials, ctx->red + 2, ctx->stream));
+    st = sync_flags(ctx, true);
+    if (st != GABP_OK) return st;
+    const double num = ctx->host->red[2], den = ctx->host->red[4];
+    *ratio = den > 0 ? num / den : (num > 0 ? INFINITY : 0.0);
+    return GABP_OK;
+}
+
+gabp_status gabp_get_messages(gabp_ctx *ctx, void *prec, void *info) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    GABP_HIP(ctx, gabp::launch_msgs_get(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L, cur_msgs(ctx),
+                                        prec, info, ctx->stream));
+    return GABP_OK;
+}
+
+gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
+    GABP_HIP(ctx, gabp::launch_msgs_set(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L,
+                                        ctx->msg[ctx->iter & 1], prec, info, ctx->stream));
+    ctx->prev_valid = false;
+    return GABP_OK;
+}
+
+gabp_status gabp_iteration_count(gabp_ctx *ctx, int64_t *iters) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    st = sync_flags(ctx, false);
+    if (iters) *iters = ctx->iter;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+"""Thin Python binding of the gfx950 library ``libgabp.so`` (C ABI in include/gabp.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  PyTorch provides device memory (workspace, outputs,
+observation arrays) and the stream.  There is no CPU fallback: importing
+this module without the built library raises ImportError.
+
+The functions carry the C names.  Non-OK statuses raise ``GabpError``, except
+that ``gabp_solve`` returns DIVERGED / NOT_CONVERGED as its first result.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgabp.so")
+
+GABP_OK, GABP_E_INVALID, GABP_E_NOMEM, GABP_E_DEVICE, GABP_E_DIVERGED, GABP_E_NOT_CONVERGED = range(6)
+GABP_BC_NEUMANN, GABP_BC_PERIODIC, GABP_BC_DIRICHLET = 0, 1, 2
+GABP_F32, GABP_F64 = 0, 1
+DTYPES = {"f32": GABP_F32, "f64": GABP_F64}
+TORCH_DTYPES = {GABP_F32: torch.float32, GABP_F64: torch.float64}
+
+
+class gabp_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("hx", ctypes.c_double),
+                ("hy", ctypes.c_double), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32)]
+
+
+class gabp_stencil(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_int32), ("kappa", ctypes.c_double), ("tau", ctypes.c_double),
+                ("c", ctypes.c_double)]
+
+
+class gabp_obs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cell", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class gabp_noise(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("var", ctypes.c_void_p)]
+
+
+class gabp_opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("prior_mean", ctypes.c_void_p)]
+
+
+# name -> (argtypes, restype), mirroring include/gabp.h
+_P = ctypes.c_void_p
+_SIGS = {
+    "gabp_workspace_size": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "gabp_create": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "gabp_iterate": ([_P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+    "gabp_solve": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, _P],
+                   ctypes.c_int),
+    "gabp_residual": ([_P, _P, _P], ctypes.c_int),
+    "gabp_posterior": ([_P, _P, _P], ctypes.c_int),
+    "gabp_message_change": ([_P, _P], ctypes.c_int),
+    "gabp_get_messages": ([_P, _P, _P], ctypes.c_int),
+    "gabp_set_messages": ([_P, _P, _P], ctypes.c_int),
+    "gabp_iteration_count": ([_P, _P], ctypes.c_int),
+    "gabp_num_directions": ([_P], ctypes.c_int32),
+    "gabp_destroy": ([_P], None),
+    "gabp_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "gabp_last_error": ([_P], ctypes.c_char_p),
+}
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is not built: run `python -m paper_2404_12968_amd.build`")
+_lib = ctypes.CDLL(_LIB_PATH)
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+LIBRARY_PATH = _LIB_PATH
+EXPORTED = tuple(_SIGS)
+
+
+class GabpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{gabp_status_string(status)}: {message}")
+        self.status = status
+
+
+class Context:
+    """A live gabp_ctx plus the torch buffers it uses (kept alive here)."""
+
+    def __init__(self, handle, workspace, stream, nx, ny, dtype, device):
+        self.handle = handle
+        self.workspace = workspace
+        self.stream = stream
+        self.nx, self.ny = nx, ny
+        self.dtype = dtype
+        self.device = device
+
+    @property
+    def deg(self) -> int:
+        return int(_lib.gabp_num_directions(self.handle))
+
+    def __del__(self):
+        try:
+            gabp_destroy(self)
+        except Exception:
+            pass
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(st: int, ctx: Optional[Context] = None):
+    if st != GABP_OK:
+        raise GabpError(st, gabp_last_error(ctx))
+
+
+def gabp_status_string(status: int) -> str:
+    return _lib.gabp_status_string(int(status)).decode()
+
+
+def gabp_last_error(ctx: Optional[Context] = None) -> str:
+    h = ctx.handle if ctx is not None else None
+    return _lib.gabp_last_error(h).decode()
+
+
+def _grid(nx, ny, hx=1.0, hy=1.0, bc_x=0, bc_y=0):
+    return gabp_grid(int(nx), int(ny), float(hx), float(hy), int(bc_x), int(bc_y))
+
+
+def _stencil(alpha, kappa, tau, c):
+    return gabp_stencil(int(alpha), float(kappa), float(tau), float(c))
+
+
+def gabp_workspace_size(grid: gabp_grid, stencil: gabp_stencil, dtype: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib.gabp_workspace_size(ctypes.byref(grid), ctypes.byref(stencil), int(dtype),
+                                    ctypes.byref(n)))
+    return int(n.value)
+
+
+def gabp_create(grid: gabp_grid, stencil: gabp_stencil, cells: torch.Tensor, y: torch.Tensor,
+                sigma: float, var: Optional[torch.Tensor] = None, dtype: int = GABP_F32,
+                prior_mean: Optional[torch.Tensor] = None, stream=None,
+                device: Optional[torch.device] = None) -> Context:
+    """Create a context.  cells (int64) and y (float64) are CUDA tensors (or
+    numpy arrays, copied to the device here); workspace comes from torch."""
+    device = torch.device(device or "cuda")
+    cells = torch.as_tensor(np.asarray(cells) if not torch.is_tensor(cells) else cells,
+                            dtype=torch.int64).to(device).contiguous()
+    y = torch.as_tensor(np.asarray(y) if not torch.is_tensor(y) else y,
+                        dtype=torch.float64).to(device).contiguous()
+    if var is not None:
+        var = torch.as_tensor(var, dtype=torch.float64).to(device).contiguous()
+    if prior_mean is not None:
+        prior_mean = torch.as_tensor(prior_mean, dtype=torch.float64).to(device).contiguous()
+    nbytes = gabp_workspace_size(grid, stencil, dtype)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    obs = gabp_obs(int(cells.numel()), cells.data_ptr() if cells.numel() else None,
+                   y.data_ptr() if y.numel() else None, 1)
+    noise = gabp_noise(float(sigma), None if var is None else var.data_ptr())
+    opts = gabp_opts(int(dtype), stream.cuda_stream, ws.data_ptr(), nbytes,
+                     None if prior_mean is None else prior_mean.data_ptr())
+    h = ctypes.c_void_p()
+    _check(_lib.gabp_create(ctypes.byref(grid), ctypes.byref(stencil), ctypes.byref(obs),
+                            ctypes.byref(noise), ctypes.byref(opts), ctypes.byref(h)))
+    return Context(h, ws, stream, grid.nx, grid.ny, int(dtype), device)
+
+
+def gabp_create_problem(prob, dtype: Optional[str] = None, stream=None, device=None,
+                        prior_mean=None) -> Context:
+    """gabp_create with the arguments taken from an ``inputs.Problem``."""
+    dt = DTYPES[dtype or prob.dtype]
+    return gabp_create(_grid(prob.nx, prob.ny, prob.hx, prob.hy, prob.bc_x, prob.bc_y),
+                       _stencil(prob.alpha, prob.kappa, prob.tau, prob.c),
+                       prob.cells, prob.y, prob.sigma, var=prob.var, dtype=dt,
+                       prior_mean=prior_mean, stream=stream, device=device)
+
+
+def gabp_iterate(ctx: Context, n_iters: int, damping: float) -> None:
+    _check(_lib.gabp_iterate(ctx.handle, int(n_iters), float(damping)), ctx)
+
+
+def gabp_solve(ctx: Context, max_iters: int, damping: float, rel_tol: float,
+               check_every: int = 10) -> Tuple[int, int, float]:
+    """Returns (status, total iterations, last relative residual)."""
+    it = ctypes.c_int64(0)
+    rel = ctypes.c_double(0.0)
+    st = _lib.gabp_solve(ctx.handle, int(max_iters), float(damping), float(rel_tol),
+                         int(check_every), ctypes.byref(it), ctypes.byref(rel))
+    if st not in (GABP_OK, GABP_E_DIVERGED, GABP_E_NOT_CONVERGED):
+        _check(st, ctx)
+    return int(st), int(it.value), float(rel.value)
+
+
+def gabp_residual(ctx: Context) -> Tuple[float, float]:
+    rel = ctypes.c_double(0.0)
+    ab = ctypes.c_double(0.0)
+    _check(_lib.gabp_residual(ctx.handle, ctypes.byref(rel), ctypes.byref(ab)), ctx)
+    return float(rel.value), float(ab.value)
+
+
+def gabp_posterior(ctx: Context, mean: Optional[torch.Tensor] = None,
+                   var: Optional[torch.Tensor] = None, want_var: bool = True):
+    """Posterior mean and variance as (ny, nx) float64 device tensors."""
+    if mean is None:
+        mean = torch.empty((ctx.ny, ctx.nx), dtype=torch.float64, device=ctx.device)
+    if var is None and want_var:
+        var = torch.empty((ctx.ny, ctx.nx), dtype=torch.float64, device=ctx.device)
+    _check(_lib.gabp_posterior(ctx.handle, _ptr(mean), _ptr(var)), ctx)
+    return mean, var
+
+
+def gabp_message_change(ctx: Context) -> float:
+    r = ctypes.c_double(0.0)
+    _check(_lib.gabp_message_change(ctx.handle, ctypes.byref(r)), ctx)
+    return float(r.value)
+
+
+def gabp_get_messages(ctx: Context):
+    """(prec, info) device tensors of shape (deg, ny, nx) in the context's dtype."""
+    shape = (ctx.deg, ctx.ny, ctx.nx)
+    prec = torch.empty(shape, dtype=TORCH_DTYPES[ctx.dtype], device=ctx.device)
+    info = torch.empty(shape, dtype=TORCH_DTYPES[ctx.dtype], device=ctx.device)
+    _check(_lib.gabp_get_messages(ctx.handle, _ptr(prec), _ptr(info)), ctx)
+    return prec, info
+
+
+def gabp_set_messages(ctx: Context, prec: torch.Tensor, info: torch.Tensor) -> None:
+    shape = (ctx.deg, ctx.ny, ctx.nx)
+    td = TORCH_DTYPES[ctx.dtype]
+    prec = prec.to(device=ctx.device, dtype=td).contiguous()
+    info = info.to(device=ctx.device, dtype=td).contiguous()
+    if tuple(prec.shape) != shape or tuple(info.shape) != shape:
+        raise ValueError(f"messages must have shape {shape}")
+    _check(_lib.gabp_set_messages(ctx.handle, _ptr(prec), _ptr(info)), ctx)
+    ctx._keep = (prec, info)   # alive until the stream has consumed them
+
+
+def gabp_iteration_count(ctx: Context) -> Tuple[int, int]:
+    """(iterations, status): status is GABP_E_DIVERGED after a divergence."""
+    it = ctypes.c_int64(0)
+    st = _lib.gabp_iteration_count(ctx.handle, ctypes.byref(it))
+    if st not in (GABP_OK, GABP_E_DIVERGED):
+        _check(st, ctx)
+    return int(it.value), int(st)
+
+
+def gabp_num_directions(ctx: Context) -> int:
+    return ctx.deg
+
+
+def gabp_destroy(ctx: Context) -> None:
+    if ctx.handle:
+        _lib.gabp_destroy(ctx.handle)
+        ctx.handle = None
