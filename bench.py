@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "edge-message updates/s + HBM GB/s; time to 1e-6 rel. residual, warm vs cold"
 ITERS_PER_STEP = 10
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_iter_global8192_traffic.md")
+PHASE_KERNEL = {"full": "k_iter_direct", "theta": "k_iter_theta"}
 
 
 def edge_count(nx, ny, alpha, bcx, bcy):
@@ -45,20 +46,20 @@ def edge_count(nx, ny, alpha, bcx, bcy):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "lattice.h"):
+    for f in ("iter.hip", "numerics.h", "lattice.h"):
         with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_iter launch from the committed PMC summary, if it was
-    taken on the current kernel source (else None)."""
+def measured_traffic(phase):
+    """HBM bytes per launch of the timed kernel from the committed PMC summary,
+    if it was taken on the current kernel source (else None)."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     text = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
-    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    t = re.search(PHASE_KERNEL[phase] + r"_traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_source_digest():
         return None
     return float(t.group(1))
@@ -142,9 +143,12 @@ def main(argv=None):
     E = edge_count(prob.nx, prob.ny, prob.alpha, prob.bc_x, prob.bc_y)
     N = prob.n
     esize = 4 if prob.dtype == "f32" else 8
-    # algorithmic bytes of one iteration: read + write every directed message
-    # (precision and information) once, read the two node terms once
-    alg_bytes = 4 * esize * E + 2 * esize * N
+    # algorithmic bytes of one iteration.  Full kernel: read + write both
+    # components of every directed message once, read the two node terms.
+    # Information-only kernel (precision messages frozen): read the edge gain
+    # and the information message, write the information message, read b.
+    alg_full = 4 * esize * E + 2 * esize * N
+    alg_theta = 3 * esize * E + esize * N
 
     ctx = G.gabp_create_problem(prob, device=dev)
     stream = ctx.stream
@@ -157,22 +161,44 @@ def main(argv=None):
             ev1.record(stream)
         return G.gabp_residual(ctx)[0]
 
+    def timed(nsteps):
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(nsteps)]
+        t0 = time.perf_counter()
+        r = None
+        for k in range(nsteps):
+            r = step(*evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        it_ms = sum(a.elapsed_time(b) for a, b in evs) / (nsteps * ITERS_PER_STEP)
+        return wall, it_ms, r
+
+    kernels = {}
+    # phase 1: full iteration kernel (precision messages still moving)
+    rpt_full = G.gabp_autotune(ctx, 3, prob.damping)
+    step()
+    if G.gabp_precision_frozen(ctx) < 0:
+        _, ms, _ = timed(3)
+        kernels["full"] = {"iter_ms": ms, "algorithmic_bytes": alg_full,
+                           "gbps": alg_full / (ms * 1e-3) / 1e9, "rows_per_thread": rpt_full}
+    # run on until the precision messages freeze (bounded)
+    while G.gabp_precision_frozen(ctx) < 0 and G.gabp_iteration_count(ctx)[0] < 2000:
+        step()
+    frozen_at = G.gabp_precision_frozen(ctx)
+    phase = "theta" if frozen_at >= 0 else "full"
+    alg_bytes = alg_theta if phase == "theta" else alg_full
+    rpt = G.gabp_autotune(ctx, 3, prob.damping) if phase == "theta" else rpt_full
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    rel = None
-    for k in range(args.steps):
-        rel = step(*evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    iter_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * ITERS_PER_STEP)
+    wall, iter_ms, rel = timed(args.steps)
+    kernels[phase] = {"iter_ms": iter_ms, "algorithmic_bytes": alg_bytes,
+                      "gbps": alg_bytes / (iter_ms * 1e-3) / 1e9, "rows_per_thread": rpt}
     total_iters = args.steps * ITERS_PER_STEP
     value = E * total_iters / wall
     achieved = alg_bytes / (iter_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(phase)
+    kname = "k_iter_theta" if phase == "theta" else "k_iter_direct"
 
     out = {
         "metric": METRIC,
@@ -196,7 +222,10 @@ def main(argv=None):
         "hbm_gbps_algorithmic": achieved,
         "iter_ms": iter_ms,
         "rel_residual_after": rel,
-        "roofline": {"bound": "hbm", "kernel": "k_iter", "achieved": achieved,
+        "timed_phase": {"kernel": kname, "precision_frozen_at_iteration": frozen_at,
+                        "iterations_before_timing": G.gabp_iteration_count(ctx)[0] - total_iters},
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "traffic": traffic},

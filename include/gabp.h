@@ -149,7 +149,12 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
 
 /* FP64 residual of the posterior mean of the current messages: abs = ||A mu - b||_2
  * and rel = abs / ||b||_2 (rel = abs when b = 0).  Either pointer may be NULL.
- * Synchronises the stream.  Returns DIVERGED if the run has diverged. */
+ * Synchronises the stream.  Returns DIVERGED if the run has diverged.
+ * Also tests whether the last iteration left every precision message bitwise
+ * unchanged; the precision recursion involves neither the information
+ * messages nor the data, so they then stay fixed for ever and later
+ * iterations update only the information messages, with precomputed edge
+ * gains (bitwise the same results, 12 instead of 16 bytes per FP32 edge). */
 gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_residual);
 
 /* Marginals of the current messages (Compute Marginal): belief precision
@@ -167,10 +172,24 @@ gabp_status gabp_message_change(gabp_ctx *ctx, double *ratio);
 
 /* Copy the current messages out to (get) or in from (set) caller-owned device
  * arrays prec and info, each deg*ny*nx values of the context's dtype, layout
- * [deg][ny][nx].  set keeps the iteration counter; slots without a sender are
- * forced to zero.  Used for checkpoint/resume and warm starts.  Async. */
+ * [deg][ny][nx] (receiver-indexed, see the conventions above).  get writes 0
+ * in slots without a sender; set ignores them and keeps the iteration
+ * counter.  Used for checkpoint/resume and warm starts.  Async. */
 gabp_status gabp_get_messages(gabp_ctx *ctx, void *prec, void *info);
 gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info);
+
+/* Autotuner: after one untimed iteration, run `trials` iterations with each
+ * tile shape of the active iteration kernel (rows per thread 1, 2, 4, 8),
+ * twice over, time them with HIP events on the context's stream, and keep
+ * the fastest for this context and for later contexts of the same prior
+ * order, dtype and size class in this process.  Every shape computes
+ * bitwise-identical messages, so these are ordinary iterations: the counter
+ * advances by 1 + 8 * trials.  *chosen (may be NULL) receives the rows per
+ * thread.  Synchronises. */
+gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen);
+
+/* Iteration at which the precision messages were found frozen, or -1. */
+gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at);
 
 /* Iterations applied so far (synchronises; returns DIVERGED with the
  * diverged iteration if the run diverged). */

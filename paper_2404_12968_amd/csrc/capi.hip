@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -32,7 +34,8 @@ struct Layout {
     int32_t pitch = 0;
     int64_t plane = 0;        // message-plane stride, elements
     size_t msg[2] = {0, 0};
-    size_t adiag64 = 0, b64 = 0, mu64 = 0, adiag_w = 0, b_w = 0;
+    size_t gain = 0;
+    size_t adiag64 = 0, b64 = 0, mu64 = 0, bel64 = 0, adiag_w = 0, b_w = 0;
     size_t partials = 0, red = 0, flags = 0, total = 0;
 };
 
@@ -51,9 +54,11 @@ Layout make_layout(int64_t nx, int64_t ny, int deg, size_t esize, bool f32) {
     const size_t buf_bytes = (size_t)(2 * deg) * (size_t)l.plane * esize;
     l.msg[0] = take(buf_bytes);
     l.msg[1] = take(buf_bytes);
+    l.gain = take((size_t)deg * (size_t)l.plane * esize);
     l.adiag64 = take(node_elems * 8);
     l.b64 = take(node_elems * 8);
     l.mu64 = take(node_elems * 8);
+    l.bel64 = take(node_elems * 8);
     if (f32) {
         l.adiag_w = take(node_elems * esize);
         l.b_w = take(node_elems * esize);
@@ -89,15 +94,21 @@ struct gabp_ctx {
     bool own_ws = false;
     Layout lay;
     void *msg[2] = {nullptr, nullptr};
+    void *gain = nullptr;          // edge gains once the precision messages froze
     double *adiag64 = nullptr, *b64 = nullptr, *mu64 = nullptr;
+    double *bel64 = nullptr;       // FP64 belief precisions once frozen
     void *adiag_w = nullptr, *b_w = nullptr;
     double *partials = nullptr, *red = nullptr;
-    uint32_t *flags = nullptr;     // [0] diverged-at iteration, [1] input error
+    uint32_t *flags = nullptr;     // [0] diverged-at iteration, [1] input error,
+                                   // [2] precision messages changed in the last iteration
     HostMirror *host = nullptr;    // pinned
+    int rpt = 4;                   // rows per thread of the iteration kernel's tile
     int64_t iter = 0;
     bool diverged = false;
     bool prev_valid = false;       // the other buffer holds m^{iter-1}
     bool have_ref = false;         // sum |m^2 - m^1| recorded in red[4]
+    bool frozen = false;           // precision messages bitwise stationary
+    int64_t frozen_at = -1;
     std::string err;
 };
 
@@ -193,6 +204,17 @@ gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
 }
 
 const void *cur_msgs(const gabp_ctx *ctx) { return ctx->msg[ctx->iter & 1]; }
+
+// Autotuner results, process-wide, keyed by (alpha, dtype, size class).
+std::mutex g_tune_mu;
+std::map<long long, int> g_tune;
+
+long long tune_key(const gabp_ctx *ctx) {
+    const long long n = (long long)ctx->L.nx * ctx->L.ny;
+    int cls = 0;
+    while (cls < 40 && (1LL << (cls + 1)) <= n) ++cls;   // log2 of the node count
+    return ((long long)ctx->L.alpha * 4 + ctx->dtype) * 64 + cls;
+}
 
 }  // namespace
 
@@ -303,9 +325,11 @@ gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil, cons
     const Layout &lay = ctx->lay;
     ctx->msg[0] = ctx->ws + lay.msg[0];
     ctx->msg[1] = ctx->ws + lay.msg[1];
+    ctx->gain = ctx->ws + lay.gain;
     ctx->adiag64 = (double *)(ctx->ws + lay.adiag64);
     ctx->b64 = (double *)(ctx->ws + lay.b64);
     ctx->mu64 = (double *)(ctx->ws + lay.mu64);
+    ctx->bel64 = (double *)(ctx->ws + lay.bel64);
     if (dtype == GABP_F32) {
         ctx->adiag_w = ctx->ws + lay.adiag_w;
         ctx->b_w = ctx->ws + lay.b_w;
@@ -379,6 +403,11 @@ gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil, cons
         return bail(GABP_E_INVALID);
     }
     ctx->iter = 0;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(tune_key(ctx));
+        if (it != g_tune.end()) ctx->rpt = it->second;
+    }
     *out = ctx;
     return GABP_OK;
 }
@@ -404,9 +433,14 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
     for (int32_t k = 0; k < n_iters; ++k) {
         const int64_t t = ctx->iter + 1;
-        GABP_HIP(ctx, gabp::launch_iter(dt, ctx->L, ctx->msg[(t - 1) & 1], ctx->msg[t & 1],
-                                        ctx->adiag_w, ctx->b_w, damping, ctx->flags,
-                                        (uint32_t)t, ctx->stream));
+        if (ctx->frozen)
+            GABP_HIP(ctx, gabp::launch_iter_theta(dt, ctx->rpt, ctx->L, ctx->msg[(t - 1) & 1],
+                                                  ctx->msg[t & 1], ctx->gain, ctx->b_w, damping,
+                                                  ctx->flags, (uint32_t)t, ctx->stream));
+        else
+            GABP_HIP(ctx, gabp::launch_iter(dt, ctx->rpt, ctx->L, ctx->msg[(t - 1) & 1],
+                                            ctx->msg[t & 1], ctx->adiag_w, ctx->b_w, damping,
+                                            ctx->flags, (uint32_t)t, ctx->stream));
         ctx->iter = t;
         if (t == 2) {
             const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
@@ -424,12 +458,29 @@ gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_resid
     if (st != GABP_OK) return st;
     if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
-    GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64, ctx->mu64,
-                                    nullptr, nullptr, ctx->stream));
+    // Did the last iteration leave every precision message bitwise unchanged?
+    const bool probe = !ctx->frozen && ctx->prev_valid && ctx->iter >= 2;
+    if (probe) {
+        GABP_HIP(ctx, hipMemsetAsync(ctx->flags + 2, 0, sizeof(uint32_t), ctx->stream));
+        GABP_HIP(ctx, gabp::launch_bits_differ(dt, ctx->msg[ctx->iter & 1],
+                                               ctx->msg[(ctx->iter - 1) & 1],
+                                               (int64_t)ctx->L.deg * ctx->L.plane, ctx->flags + 2,
+                                               ctx->stream));
+    }
+    GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64,
+                                    ctx->frozen ? ctx->bel64 : nullptr, ctx->mu64, nullptr,
+                                    nullptr, probe ? ctx->bel64 : nullptr, ctx->stream));
     GABP_HIP(ctx, gabp::launch_resid(ctx->L, ctx->mu64, ctx->adiag64, ctx->b64, ctx->partials,
                                      kNumPartials, ctx->red, ctx->stream));
     st = sync_flags(ctx, true);
     if (st != GABP_OK) return st;
+    if (probe && ctx->host->flags[2] == 0u) {
+        // frozen: from now on only the information messages change
+        GABP_HIP(ctx, gabp::launch_gain(dt, ctx->L, cur_msgs(ctx), ctx->adiag_w, ctx->gain,
+                                        ctx->stream));
+        ctx->frozen = true;
+        ctx->frozen_at = ctx->iter;
+    }
     const double a = std::sqrt(ctx->host->red[0]), b = std::sqrt(ctx->host->red[1]);
     if (abs_residual) *abs_residual = a;
     if (rel_residual) *rel_residual = b > 0 ? a / b : a;
@@ -487,8 +538,9 @@ gabp_status gabp_posterior(gabp_ctx *ctx, double *mean, double *var) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
-    GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64, nullptr,
-                                    mean, var, ctx->stream));
+    GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64,
+                                    ctx->frozen ? ctx->bel64 : nullptr, nullptr, mean, var,
+                                    nullptr, ctx->stream));
     return GABP_OK;
 }
 
@@ -524,6 +576,67 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
     GABP_HIP(ctx, gabp::launch_msgs_set(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L,
                                         ctx->msg[ctx->iter & 1], prec, info, ctx->stream));
     ctx->prev_valid = false;
+    ctx->frozen = false;
+    ctx->frozen_at = -1;
+    return GABP_OK;
+}
+
+gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (trials < 1) return fail(ctx, GABP_E_INVALID, "trials must be >= 1");
+    hipEvent_t ev[2];
+    GABP_HIP(ctx, hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return fail(ctx, GABP_E_DEVICE, "hipEventCreate failed");
+    }
+    float best_ms = INFINITY;
+    int best = ctx->rpt;
+    const int saved = ctx->rpt;
+    // one untimed iteration first, then two timed passes over the shapes;
+    // the best time of a shape over both passes counts
+    st = gabp_iterate(ctx, 1, damping);
+    if (st != GABP_OK) {
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        return st;
+    }
+    for (int pass = 0; pass < 2; ++pass)
+    for (int rpt : gabp::kRptChoices) {
+        ctx->rpt = rpt;
+        gabp_status s1 = GABP_OK;
+        if (hipEventRecord(ev[0], ctx->stream) != hipSuccess) s1 = GABP_E_DEVICE;
+        if (s1 == GABP_OK) s1 = gabp_iterate(ctx, trials, damping);
+        if (s1 == GABP_OK && hipEventRecord(ev[1], ctx->stream) != hipSuccess) s1 = GABP_E_DEVICE;
+        if (s1 == GABP_OK && hipEventSynchronize(ev[1]) != hipSuccess) s1 = GABP_E_DEVICE;
+        float ms = 0.f;
+        if (s1 == GABP_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) s1 = GABP_E_DEVICE;
+        if (s1 != GABP_OK) {
+            ctx->rpt = saved;
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            return s1 == GABP_E_DEVICE ? fail(ctx, s1, "autotune timing failed") : s1;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = rpt;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    ctx->rpt = best;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[tune_key(ctx)] = best;
+    }
+    if (chosen) *chosen = best;
+    return sync_flags(ctx, false);
+}
+
+gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at) {
+    if (!ctx || !at) return GABP_E_INVALID;
+    *at = ctx->frozen ? ctx->frozen_at : -1;
     return GABP_OK;
 }
 

@@ -9,12 +9,27 @@
 namespace gabp {
 
 // dtype: 0 = FP32 message planes, 1 = FP64.
-hipError_t launch_iter(int dtype, const Lattice &L, const void *min, void *mout,
+// rpt: rows per thread of the iteration kernel's tile (1, 2, 4 or 8); every
+// choice gives bitwise-identical results.
+constexpr int kRptChoices[] = {1, 2, 4, 8};
+hipError_t launch_iter(int dtype, int rpt, const Lattice &L, const void *m_in, void *m_out,
                        const void *adiag, const void *bw, double eta, uint32_t *flag,
                        uint32_t t, hipStream_t s);
-hipError_t launch_post(int dtype, const Lattice &L, const void *m, const double *adiag64,
-                       const double *b64, double *mu_plane, double *mean, double *var,
+// Information-only iteration with precomputed edge gains (after the
+// precision messages froze), the gain set-up and a bitwise-change test.
+hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m_in,
+                             void *m_out, const void *gain, const void *bw, double eta,
+                             uint32_t *flag, uint32_t t, hipStream_t s);
+hipError_t launch_gain(int dtype, const Lattice &L, const void *m, const void *adiag, void *gain,
                        hipStream_t s);
+hipError_t launch_bits_differ(int dtype, const void *a, const void *b, int64_t n,
+                              uint32_t *flag, hipStream_t s);
+// Marginals: bel64 != NULL selects the frozen-precision variant that reads
+// the belief precisions from bel64; otherwise bel_out (may be NULL) receives
+// them.
+hipError_t launch_post(int dtype, const Lattice &L, const void *m, const double *adiag64,
+                       const double *b64, const double *bel64, double *mu_plane, double *mean,
+                       double *var, double *bel_out, hipStream_t s);
 hipError_t launch_resid(const Lattice &L, const double *mu, const double *adiag64,
                         const double *b64, double *partials, int npart, double *out,
                         hipStream_t s);

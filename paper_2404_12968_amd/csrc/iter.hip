@@ -1,0 +1,342 @@
+// gfx950 iteration kernels of the lattice Gaussian belief propagation
+// library: the full flooding iteration, the edge-gain set-up and the
+// information-only iteration used once the precision messages have frozen.
+//
+// Message storage: two ping-pong buffers, each 2*deg planes (deg precision
+// planes, then deg information planes) of the message precision T, SENDER
+// indexed: plane d at (x, y) is the message FROM (x, y) TO (x, y) + off_d.
+// A sender therefore reads its old outgoing messages (for damping) and
+// writes the new ones at its own, aligned, position; only the incoming
+// messages of a node are read at shifted positions (plane d^1 at the
+// neighbour).  Iteration t reads buffer (t-1)&1 and writes buffer t&1
+// (flooding schedule: every new message depends only on the previous
+// iteration's messages).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "internal.h"
+#include "lattice.h"
+#include "numerics.h"
+
+// Rounding is spelled out: no implicit multiply-add contraction in this file,
+// explicit fused multiply-adds where wanted.  The full iteration and the
+// information-only iteration must round identically to stay bitwise equal.
+#pragma clang fp contract(off)
+
+namespace gabp {
+
+// --------------------------------------------------------------------------
+// One flooding iteration, thread per node.
+//
+// Node i = (x, y) with incoming messages m_{k->i} (plane d^1 at k = i + off_d):
+//   belief  Lam_i = A_ii + c sum_k Lam_{k->i},   th_i = b_i + c sum_k th_{k->i}
+// and for every neighbour j = i + off_d (outgoing i -> j, plane d at i):
+//   cavity  Lam_c = Lam_i - Lam_{j->i},  th_c = th_i - th_{j->i}
+//   gain    g = -(Q_ij/c) / Lam_c
+//   new     Lam~ = g (Q_ij/c) = -(Q_ij/c)^2 / Lam_c,  th~ = g th_c
+//   damped  m^t = (1 - eta) m^{t-1} + eta m~
+// (Appendix "Re-weighted message updates" in information form; Section
+// "Update Damping".)  A cavity precision <= 0 or a non-finite value records t
+// in diverged_at; later launches then return at once, keeping that state.
+// Every load of a node is issued before the first use (~50 in flight per
+// lane).
+// --------------------------------------------------------------------------
+template <typename T, int ALPHA, bool INTERIOR>
+__device__ __forceinline__ void iter_node(const Lattice &L, const T *__restrict__ m_in,
+                                          T *__restrict__ m_out, const T *__restrict__ adiag,
+                                          const T *__restrict__ bw, T eta, bool &bad, int x,
+                                          int y) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    const T c = (T)L.c, keep = (T)1 - eta;
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
+
+    // plane bases are wave-uniform; per-lane offsets stay 32-bit
+    T lin[DEG], tin[DEG], ol[DEG], ot[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        lin[d] = (m_in + (size_t)(d ^ 1) * L.plane)[j[d]];
+        tin[d] = (m_in + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
+    }
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        ol[d] = (m_in + (size_t)d * L.plane)[i];
+        ot[d] = (m_in + (size_t)(DEG + d) * L.plane)[i];
+    }
+    const T a = adiag[i];
+    const T b = bw[i];
+    if (!INTERIOR) {
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) {
+            lin[d] = ok[d] ? lin[d] : (T)0;
+            tin[d] = ok[d] ? tin[d] : (T)0;
+        }
+    }
+    T sl = 0, st = 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        sl += lin[d];
+        st += tin[d];
+    }
+    const T bl = fmadd(c, sl, a);
+    const T bt = fmadd(c, st, b);
+    const T li = ALPHA == 2 ? ell<T>(L, x, y) : (T)0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        const T q = q_over_c<T, ALPHA>(L, d, li, xs[d], ys[d]);
+        const T lc = bl - lin[d];
+        const T tc = bt - tin[d];
+        const T g = edge_gain(q, lc);
+        const T dl = fmadd(eta, g * q, keep * ol[d]);
+        const T dt = fmadd(eta, g * tc, keep * ot[d]);
+        if (ok[d]) {
+            bad |= !(lc > (T)0) || !isfinite(dl) || !isfinite(dt);
+            (m_out + (size_t)d * L.plane)[i] = dl;
+            (m_out + (size_t)(DEG + d) * L.plane)[i] = dt;
+        }
+    }
+}
+
+// One workgroup = 256 threads on a 64 x (4*RPT) tile: lane -> column, wave ->
+// row, each thread walks RPT rows 4 apart.  The tile shape is a tuning knob
+// (gabp_autotune); results do not depend on it.
+template <typename T, int ALPHA, int RPT>
+__global__ __launch_bounds__(256) void k_iter_direct(Lattice L, const T *__restrict__ m_in,
+                                                     T *__restrict__ m_out,
+                                                     const T *__restrict__ adiag,
+                                                     const T *__restrict__ bw, T eta,
+                                                     uint32_t *__restrict__ diverged_at,
+                                                     uint32_t t) {
+    if (*diverged_at != 0u) return;
+    constexpr int TH = 4 * RPT;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+    const int x = tx * 64 + (int)(threadIdx.x & 63u);
+    const int y0 = ty * TH + (int)(threadIdx.x >> 6);
+    const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * TH >= 2 &&
+                          ty * TH + TH + 2 <= L.ny;
+    bool bad = false;
+    if (interior) {
+#pragma unroll 1
+        for (int k = 0; k < RPT; ++k)
+            iter_node<T, ALPHA, true>(L, m_in, m_out, adiag, bw, eta, bad, x, y0 + 4 * k);
+    } else if (x < L.nx) {
+#pragma unroll 1
+        for (int k = 0; k < RPT; ++k)
+            if (y0 + 4 * k < L.ny)
+                iter_node<T, ALPHA, false>(L, m_in, m_out, adiag, bw, eta, bad, x, y0 + 4 * k);
+    }
+    if (bad) *diverged_at = t;
+}
+
+// --------------------------------------------------------------------------
+// Frozen precision messages.  The precision recursion involves neither the
+// information messages nor the data, so once one iteration leaves every
+// precision message bitwise unchanged, all later iterations do too.  From
+// then on the gains g_{i->j} are constants: k_gain stores them once
+// (sender-indexed, plane d at i) and k_iter_theta updates only the
+// information messages, reading 12 bytes per edge instead of 16 (FP32)
+// with results bitwise equal to the full iteration's.
+// --------------------------------------------------------------------------
+template <typename T, int ALPHA>
+__global__ __launch_bounds__(256) void k_gain(Lattice L, const T *__restrict__ m,
+                                              const T *__restrict__ adiag,
+                                              T *__restrict__ gain) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const int tile = (int)blockIdx.x;
+    const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
+    const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
+    if (x >= L.nx || y >= L.ny) return;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+    node_nbrs<DEG, false>(L, x, y, j, xs, ys, ok);
+    T lin[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        const T v = (m + (size_t)(d ^ 1) * L.plane)[j[d]];
+        lin[d] = ok[d] ? v : (T)0;
+    }
+    T sl = 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) sl += lin[d];
+    const T bl = fmadd((T)L.c, sl, adiag[i]);
+    const T li = ALPHA == 2 ? ell<T>(L, x, y) : (T)0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        if (!ok[d]) continue;
+        const T q = q_over_c<T, ALPHA>(L, d, li, xs[d], ys[d]);
+        (gain + (size_t)d * L.plane)[i] = edge_gain(q, bl - lin[d]);
+    }
+}
+
+template <typename T, int ALPHA, bool INTERIOR>
+__device__ __forceinline__ void iter_theta_node(const Lattice &L, const T *__restrict__ m_in,
+                                                T *__restrict__ m_out,
+                                                const T *__restrict__ gain,
+                                                const T *__restrict__ bw, T eta, bool &bad,
+                                                int x, int y) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    const T c = (T)L.c, keep = (T)1 - eta;
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
+    T tin[DEG], ot[DEG], g[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) tin[d] = (m_in + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        ot[d] = (m_in + (size_t)(DEG + d) * L.plane)[i];
+        g[d] = (gain + (size_t)d * L.plane)[i];
+    }
+    const T b = bw[i];
+    if (!INTERIOR) {
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) tin[d] = ok[d] ? tin[d] : (T)0;
+    }
+    T st = 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) st += tin[d];
+    const T bt = fmadd(c, st, b);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        const T tc = bt - tin[d];
+        const T dt = fmadd(eta, g[d] * tc, keep * ot[d]);
+        if (ok[d]) {
+            bad |= !isfinite(dt);
+            (m_out + (size_t)(DEG + d) * L.plane)[i] = dt;
+        }
+    }
+}
+
+template <typename T, int ALPHA, int RPT>
+__global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restrict__ m_in,
+                                                    T *__restrict__ m_out,
+                                                    const T *__restrict__ gain,
+                                                    const T *__restrict__ bw, T eta,
+                                                    uint32_t *__restrict__ diverged_at,
+                                                    uint32_t t) {
+    if (*diverged_at != 0u) return;
+    constexpr int TH = 4 * RPT;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+    const int x = tx * 64 + (int)(threadIdx.x & 63u);
+    const int y0 = ty * TH + (int)(threadIdx.x >> 6);
+    const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * TH >= 2 &&
+                          ty * TH + TH + 2 <= L.ny;
+    bool bad = false;
+    if (interior) {
+#pragma unroll 1
+        for (int k = 0; k < RPT; ++k)
+            iter_theta_node<T, ALPHA, true>(L, m_in, m_out, gain, bw, eta, bad, x, y0 + 4 * k);
+    } else if (x < L.nx) {
+#pragma unroll 1
+        for (int k = 0; k < RPT; ++k)
+            if (y0 + 4 * k < L.ny)
+                iter_theta_node<T, ALPHA, false>(L, m_in, m_out, gain, bw, eta, bad, x,
+                                                 y0 + 4 * k);
+    }
+    if (bad) *diverged_at = t;
+}
+
+static inline int tiles_of(const Lattice &L) {
+    return L.tiles_x * ((L.ny + 3) / 4);
+}
+
+template <typename T, int ALPHA, int RPT>
+static void launch_iter_k(const Lattice &L, const void *m_in, void *m_out, const void *adiag,
+                          const void *bw, double eta, uint32_t *flag, uint32_t t, hipStream_t s) {
+    const int tiles = L.tiles_x * ((L.ny + 4 * RPT - 1) / (4 * RPT));
+    hipLaunchKernelGGL((k_iter_direct<T, ALPHA, RPT>), dim3(tiles), dim3(256), 0, s, L,
+                       (const T *)m_in, (T *)m_out, (const T *)adiag, (const T *)bw, (T)eta, flag,
+                       t);
+}
+
+template <typename T, int ALPHA>
+static void launch_iter_a(int rpt, const Lattice &L, const void *m_in, void *m_out,
+                          const void *adiag, const void *bw, double eta, uint32_t *flag,
+                          uint32_t t, hipStream_t s) {
+    switch (rpt) {
+        case 1: launch_iter_k<T, ALPHA, 1>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
+        case 2: launch_iter_k<T, ALPHA, 2>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
+        case 4: launch_iter_k<T, ALPHA, 4>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
+        default: launch_iter_k<T, ALPHA, 8>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
+    }
+}
+
+hipError_t launch_iter(int dtype, int rpt, const Lattice &L, const void *m_in, void *m_out,
+                       const void *adiag, const void *bw, double eta, uint32_t *flag,
+                       uint32_t t, hipStream_t s) {
+    if (dtype == 0) {
+        if (L.alpha == 1) launch_iter_a<float, 1>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
+        else launch_iter_a<float, 2>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
+    } else {
+        if (L.alpha == 1) launch_iter_a<double, 1>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
+        else launch_iter_a<double, 2>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int ALPHA, int RPT>
+static void launch_theta_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
+                           const void *bw, double eta, uint32_t *flag, uint32_t t, hipStream_t s) {
+    const int tiles = L.tiles_x * ((L.ny + 4 * RPT - 1) / (4 * RPT));
+    hipLaunchKernelGGL((k_iter_theta<T, ALPHA, RPT>), dim3(tiles), dim3(256), 0, s, L,
+                       (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta, flag,
+                       t);
+}
+
+template <typename T, int ALPHA>
+static void launch_theta_a(int rpt, const Lattice &L, const void *m_in, void *m_out,
+                           const void *gain, const void *bw, double eta, uint32_t *flag,
+                           uint32_t t, hipStream_t s) {
+    switch (rpt) {
+        case 1: launch_theta_k<T, ALPHA, 1>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
+        case 2: launch_theta_k<T, ALPHA, 2>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
+        case 4: launch_theta_k<T, ALPHA, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
+        default: launch_theta_k<T, ALPHA, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
+    }
+}
+
+hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m_in,
+                             void *m_out, const void *gain, const void *bw, double eta,
+                             uint32_t *flag, uint32_t t, hipStream_t s) {
+    if (dtype == 0) {
+        if (L.alpha == 1) launch_theta_a<float, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+        else launch_theta_a<float, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+    } else {
+        if (L.alpha == 1) launch_theta_a<double, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+        else launch_theta_a<double, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gain(int dtype, const Lattice &L, const void *m, const void *adiag, void *gain,
+                       hipStream_t s) {
+    dim3 grid(tiles_of(L)), block(256);
+    if (dtype == 0) {
+        if (L.alpha == 1)
+            hipLaunchKernelGGL((k_gain<float, 1>), grid, block, 0, s, L, (const float *)m,
+                               (const float *)adiag, (float *)gain);
+        else
+            hipLaunchKernelGGL((k_gain<float, 2>), grid, block, 0, s, L, (const float *)m,
+                               (const float *)adiag, (float *)gain);
+    } else {
+        if (L.alpha == 1)
+            hipLaunchKernelGGL((k_gain<double, 1>), grid, block, 0, s, L, (const double *)m,
+                               (const double *)adiag, (double *)gain);
+        else
+            hipLaunchKernelGGL((k_gain<double, 2>), grid, block, 0, s, L, (const double *)m,
+                               (const double *)adiag, (double *)gain);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gabp

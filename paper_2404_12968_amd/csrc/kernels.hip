@@ -1,176 +1,74 @@
-// gfx950 kernels of the lattice Gaussian belief propagation library.
+// gfx950 auxiliary kernels of the lattice Gaussian belief propagation
+// library: marginals, the FP64 residual and its deterministic reductions,
+// problem set-up, checkpoint copies and the bitwise-change test.  The
+// iteration kernels live in iter.hip.
 //
-// Message storage: two ping-pong buffers, each 2*deg planes (deg precision
-// planes, then deg information planes) of the message precision T, receiver
-// indexed: plane d at (x, y) is the message INTO (x, y) FROM (x, y) + off_d.
-// Iteration t reads buffer (t-1)&1 and writes buffer t&1 (flooding schedule:
-// every new message depends only on the previous iteration's messages).
+// Message storage is SENDER indexed: plane d at (x, y) is the message FROM
+// (x, y) TO (x, y) + off_d, so the incoming messages of a node are plane d^1
+// at its neighbours.  The C ABI's checkpoint layout is receiver-indexed;
+// k_msgs_get/k_msgs_set convert.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "internal.h"
 #include "lattice.h"
+#include "numerics.h"
+
+// Rounding is spelled out: no implicit multiply-add contraction in this file,
+// explicit fused multiply-adds where wanted.  The full iteration and the
+// information-only iteration (after the precision messages have frozen) must
+// round identically to stay bitwise equal.
+#pragma clang fp contract(off)
 
 namespace gabp {
-
-template <typename T>
-__device__ __forceinline__ T recip(T v);
-template <>
-__device__ __forceinline__ float recip<float>(float v) {
-    return __builtin_amdgcn_rcpf(v);  // 1 ulp; FP32 messages are checked at 1e-5
-}
-template <>
-__device__ __forceinline__ double recip<double>(double v) {
-    return 1.0 / v;  // correctly rounded: FP64 parity is checked at 1e-12
-}
-
-// --------------------------------------------------------------------------
-// One flooding iteration, thread per node (the reference GPU formulation).
-//
-// Node i = (x, y) with incoming messages m_{k->i} (its own slots):
-//   belief  Lam_i = A_ii + c sum_k Lam_{k->i},   th_i = b_i + c sum_k th_{k->i}
-// and for every neighbour j = i + off_d (outgoing i -> j, stored at j in the
-// opposite plane d^1):
-//   cavity  Lam_c = Lam_i - Lam_{j->i},  th_c = th_i - th_{j->i}
-//   new     Lam~ = -(Q_ij/c)^2 / Lam_c,  th~ = -(Q_ij/c) th_c / Lam_c
-//   damped  m^t = (1 - eta) m^{t-1} + eta m~
-// (Appendix "Re-weighted message updates" in information form; Section
-// "Update Damping".)  A cavity precision <= 0 or a non-finite value records t
-// in diverged_at; later launches then return at once, keeping that state.
-//
-// Every load of a node is issued before the first use so that a wave keeps
-// ~50 loads in flight.  Workgroups whose 64x4 tile and its radius-2 halo lie
-// inside the grid take the INTERIOR path with no neighbour tests; the others
-// clamp addresses, predicate stores and wrap periodic axes.
-// --------------------------------------------------------------------------
-template <typename T, int ALPHA, bool INTERIOR>
-__device__ __forceinline__ void iter_node(const Lattice &L, const T *__restrict__ m_in,
-                                          T *__restrict__ m_out, const T *__restrict__ adiag,
-                                          const T *__restrict__ bw, T eta,
-                                          uint32_t *__restrict__ diverged_at, uint32_t t,
-                                          int x, int y) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
-    const int64_t P = L.plane;
-    const int64_t i = (int64_t)y * L.pitch + x;
-    const T c = (T)L.c, inv_c = (T)L.inv_c, keep = (T)1 - eta;
-
-    int64_t j[DEG];
-    int xs[DEG], ys[DEG];
-    bool ok[DEG];
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        int xn, yn;
-        if (INTERIOR) {
-            xn = x + dir_dx(d);
-            yn = y + dir_dy(d);
-            ok[d] = true;
-        } else {
-            ok[d] = neighbour(L, x, y, d, xn, yn);
-            xn = min(max(xn, 0), L.nx - 1);
-            yn = min(max(yn, 0), L.ny - 1);
-        }
-        xs[d] = xn;
-        ys[d] = yn;
-        j[d] = (int64_t)yn * L.pitch + xn;
-    }
-    T lam[DEG], th[DEG], ol[DEG], ot[DEG];
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        lam[d] = m_in[d * P + i];
-        th[d] = m_in[(DEG + d) * P + i];
-    }
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        ol[d] = m_in[(d ^ 1) * P + j[d]];
-        ot[d] = m_in[(DEG + (d ^ 1)) * P + j[d]];
-    }
-    const T a = adiag[i];
-    const T b = bw[i];
-    T sl = 0, st = 0;
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        sl += lam[d];
-        st += th[d];
-    }
-    const T bl = a + c * sl;
-    const T bt = b + c * st;
-    // near-neighbour coefficients need l at both ends (13-point prior)
-    const T li = ALPHA == 2 ? ell<T>(L, x, y) : (T)0;
-    bool bad = false;
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        T q;
-        if (ALPHA == 1) {
-            q = -(T)L.tau * (d < 2 ? (T)L.ihx2 : (T)L.ihy2);
-        } else if (d < 4) {
-            q = -(T)L.tau * (li + ell<T>(L, xs[d], ys[d])) * (d < 2 ? (T)L.ihx2 : (T)L.ihy2);
-        } else if (d < 8) {
-            q = d < 6 ? (T)(L.tau * L.ihx2 * L.ihx2) : (T)(L.tau * L.ihy2 * L.ihy2);
-        } else {
-            q = (T)(2.0 * L.tau * L.ihx2 * L.ihy2);
-        }
-        q *= inv_c;
-        const T lc = bl - lam[d];
-        const T tc = bt - th[d];
-        const T r = recip<T>(lc);
-        const T dl = keep * ol[d] + eta * (-(q * q) * r);
-        const T dt = keep * ot[d] + eta * (-(q * tc) * r);
-        if (ok[d]) {
-            bad |= !(lc > (T)0) || !isfinite(dl) || !isfinite(dt);
-            m_out[(d ^ 1) * P + j[d]] = dl;
-            m_out[(DEG + (d ^ 1)) * P + j[d]] = dt;
-        }
-    }
-    if (bad) *diverged_at = t;
-}
-
-template <typename T, int ALPHA>
-__global__ __launch_bounds__(256) void k_iter_direct(Lattice L, const T *__restrict__ m_in,
-                                                     T *__restrict__ m_out,
-                                                     const T *__restrict__ adiag,
-                                                     const T *__restrict__ bw, T eta,
-                                                     uint32_t *__restrict__ diverged_at,
-                                                     uint32_t t) {
-    if (*diverged_at != 0u) return;
-    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
-    const int x = tx * 64 + (int)(threadIdx.x & 63u);
-    const int y = ty * 4 + (int)(threadIdx.x >> 6);
-    const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * 4 >= 2 &&
-                          ty * 4 + 6 <= L.ny;
-    if (interior) {
-        iter_node<T, ALPHA, true>(L, m_in, m_out, adiag, bw, eta, diverged_at, t, x, y);
-    } else if (x < L.nx && y < L.ny) {
-        iter_node<T, ALPHA, false>(L, m_in, m_out, adiag, bw, eta, diverged_at, t, x, y);
-    }
-}
 
 // --------------------------------------------------------------------------
 // Marginals (Compute Marginal) in FP64 from messages of precision T:
 // Lam_i = A_ii + c sum Lam_{k->i}, th_i = b_i + c sum th_{k->i}; mu = th/Lam,
 // var = 1/Lam.  Writes the pitched FP64 mean plane used by the residual and,
-// when given, contiguous mean/var arrays.
+// when given, contiguous mean/var arrays.  Once the precision messages have
+// frozen, Lam_i is a constant read from bel64 (FROZEN) and only the
+// information messages are read; bel_out records Lam_i for that phase.
 // --------------------------------------------------------------------------
-template <typename T>
+template <typename T, int ALPHA, bool FROZEN>
 __global__ __launch_bounds__(256) void k_post(Lattice L, const T *__restrict__ m,
                                               const double *__restrict__ adiag64,
                                               const double *__restrict__ b64,
+                                              const double *__restrict__ bel64,
                                               double *__restrict__ mu_plane,
                                               double *__restrict__ mean,
-                                              double *__restrict__ var) {
+                                              double *__restrict__ var,
+                                              double *__restrict__ bel_out) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
     const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
     const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
     if (x >= L.nx || y >= L.ny) return;
-    const int64_t P = L.plane;
-    const int64_t i = (int64_t)y * L.pitch + x;
-    double sl = 0.0, st = 0.0;
-    for (int d = 0; d < L.deg; ++d) {
-        sl += (double)m[d * P + i];
-        st += (double)m[(L.deg + d) * P + i];
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+    node_nbrs<DEG, false>(L, x, y, j, xs, ys, ok);
+    T lin[DEG], tin[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        if (!FROZEN) lin[d] = (m + (size_t)(d ^ 1) * L.plane)[j[d]];
+        tin[d] = (m + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
     }
-    const double bl = adiag64[i] + L.c * sl;
+    double bl;
+    if (FROZEN) {
+        bl = bel64[i];
+    } else {
+        double sl = 0.0;
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) sl += ok[d] ? (double)lin[d] : 0.0;
+        bl = adiag64[i] + L.c * sl;
+        if (bel_out) bel_out[i] = bl;
+    }
+    double st = 0.0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) st += ok[d] ? (double)tin[d] : 0.0;
     const double bt = b64[i] + L.c * st;
     const double mu = bt / bl;
     if (mu_plane) mu_plane[i] = mu;
@@ -184,30 +82,49 @@ __global__ __launch_bounds__(256) void k_post(Lattice L, const T *__restrict__ m
 // Each workgroup sums r^2 and b^2 over a fixed set of tiles in a fixed order
 // (wave64 butterfly, then LDS across the four waves): deterministic partials.
 // --------------------------------------------------------------------------
+template <int ALPHA, bool INTERIOR>
+__device__ __forceinline__ void resid_node(const Lattice &L, const double *__restrict__ mu,
+                                           const double *__restrict__ adiag64,
+                                           const double *__restrict__ b64, int x, int y,
+                                           double &rr, double &bb) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
+    double v[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) v[d] = mu[j[d]];
+    const double a = adiag64[i], m0 = mu[i], b = b64[i];
+    double s = a * m0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        const double q = q_off<double>(L, d, x, y, xs[d], ys[d]);
+        s += ok[d] ? q * v[d] : 0.0;
+    }
+    const double r = s - b;
+    rr += r * r;
+    bb += b * b;
+}
+
 template <int ALPHA>
 __global__ __launch_bounds__(256) void k_resid(Lattice L, const double *__restrict__ mu,
                                                const double *__restrict__ adiag64,
                                                const double *__restrict__ b64,
                                                double *__restrict__ partials, int ntiles) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
     __shared__ double sh[2][4];
     double rr = 0.0, bb = 0.0;
     for (int tile = (int)blockIdx.x; tile < ntiles; tile += (int)gridDim.x) {
-        const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
-        const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
-        if (x < L.nx && y < L.ny) {
-            const int64_t i = (int64_t)y * L.pitch + x;
-            double s = adiag64[i] * mu[i];
-#pragma unroll
-            for (int d = 0; d < DEG; ++d) {
-                int xn, yn;
-                if (!neighbour(L, x, y, d, xn, yn)) continue;
-                s += q_off<double>(L, d, x, y, xn, yn) * mu[(int64_t)yn * L.pitch + xn];
-            }
-            const double r = s - b64[i];
-            rr += r * r;
-            bb += b64[i] * b64[i];
-        }
+        const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+        const int x = tx * 64 + (int)(threadIdx.x & 63u);
+        const int y = ty * 4 + (int)(threadIdx.x >> 6);
+        const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * 4 >= 2 &&
+                              ty * 4 + 6 <= L.ny;
+        if (interior)
+            resid_node<ALPHA, true>(L, mu, adiag64, b64, x, y, rr, bb);
+        else if (x < L.nx && y < L.ny)
+            resid_node<ALPHA, false>(L, mu, adiag64, b64, x, y, rr, bb);
     }
     rr = wave_sum(rr);
     bb = wave_sum(bb);
@@ -327,8 +244,10 @@ __global__ __launch_bounds__(256) void k_node_init(Lattice L, double *__restrict
     if (b_w) b_w[i] = (T)b;
 }
 
-// Checkpoint copies between the pitched message planes and a dense
-// [deg][ny][nx] layout.  The set direction forces slots without a sender to 0.
+// Checkpoint copies between the sender-indexed message planes and the C ABI's
+// dense receiver-indexed [deg][ny][nx] layout: receiver slot d of (x, y) is
+// the message from s = (x, y) + off_d, i.e. sender plane d^1 at s.  Slots
+// without a sender read as 0; set ignores them.
 template <typename T>
 __global__ __launch_bounds__(256) void k_msgs_get(Lattice L, const T *__restrict__ m,
                                                   T *__restrict__ prec, T *__restrict__ info) {
@@ -336,11 +255,13 @@ __global__ __launch_bounds__(256) void k_msgs_get(Lattice L, const T *__restrict
     const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
     const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
     if (x >= L.nx || y >= L.ny) return;
-    const int64_t i = (int64_t)y * L.pitch + x;
     const int64_t n = (int64_t)L.nx * L.ny, o = (int64_t)y * L.nx + x;
     for (int d = 0; d < L.deg; ++d) {
-        if (prec) prec[d * n + o] = m[d * L.plane + i];
-        if (info) info[d * n + o] = m[(L.deg + d) * L.plane + i];
+        int xn, yn;
+        const bool ok = neighbour(L, x, y, d, xn, yn);
+        const int64_t s = (int64_t)yn * L.pitch + xn;
+        if (prec) prec[d * n + o] = ok ? m[(d ^ 1) * L.plane + s] : (T)0;
+        if (info) info[d * n + o] = ok ? m[(L.deg + (d ^ 1)) * L.plane + s] : (T)0;
     }
 }
 
@@ -352,14 +273,30 @@ __global__ __launch_bounds__(256) void k_msgs_set(Lattice L, T *__restrict__ m,
     const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
     const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
     if (x >= L.nx || y >= L.ny) return;
-    const int64_t i = (int64_t)y * L.pitch + x;
     const int64_t n = (int64_t)L.nx * L.ny, o = (int64_t)y * L.nx + x;
     for (int d = 0; d < L.deg; ++d) {
         int xn, yn;
-        const bool ok = neighbour(L, x, y, d, xn, yn);
-        if (prec) m[d * L.plane + i] = ok ? prec[d * n + o] : (T)0;
-        if (info) m[(L.deg + d) * L.plane + i] = ok ? info[d * n + o] : (T)0;
+        if (!neighbour(L, x, y, d, xn, yn)) continue;
+        const int64_t s = (int64_t)yn * L.pitch + xn;
+        if (prec) m[(d ^ 1) * L.plane + s] = prec[d * n + o];
+        if (info) m[(L.deg + (d ^ 1)) * L.plane + s] = info[d * n + o];
     }
+}
+
+// Sets *flag when any of n elements differs bitwise between a and b.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bits_differ(const T *__restrict__ a,
+                                                     const T *__restrict__ b, int64_t n,
+                                                     uint32_t *__restrict__ flag) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    bool diff = false;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) {
+        if (sizeof(T) == 4)
+            diff |= __float_as_uint((float)a[k]) != __float_as_uint((float)b[k]);
+        else
+            diff |= __double_as_longlong((double)a[k]) != __double_as_longlong((double)b[k]);
+    }
+    if (diff) *flag = 1u;
 }
 
 // --------------------------------------------------------------------------
@@ -369,37 +306,43 @@ static inline int tiles_of(const Lattice &L) {
     return L.tiles_x * ((L.ny + 3) / 4);
 }
 
-template <typename T>
-static hipError_t launch_iter_t(const Lattice &L, const void *min, void *mout, const void *adiag,
-                                const void *bw, double eta, uint32_t *flag, uint32_t t,
-                                hipStream_t s) {
-    dim3 grid(tiles_of(L)), block(256);
-    if (L.alpha == 1)
-        hipLaunchKernelGGL((k_iter_direct<T, 1>), grid, block, 0, s, L, (const T *)min, (T *)mout,
-                           (const T *)adiag, (const T *)bw, (T)eta, flag, t);
+hipError_t launch_bits_differ(int dtype, const void *a, const void *b, int64_t n,
+                              uint32_t *flag, hipStream_t s) {
+    int64_t want = (n + 255) / 256;
+    const int nb = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    if (dtype == 0)
+        hipLaunchKernelGGL((k_bits_differ<float>), dim3(nb), dim3(256), 0, s, (const float *)a,
+                           (const float *)b, n, flag);
     else
-        hipLaunchKernelGGL((k_iter_direct<T, 2>), grid, block, 0, s, L, (const T *)min,
-                           (T *)mout, (const T *)adiag, (const T *)bw, (T)eta, flag, t);
+        hipLaunchKernelGGL((k_bits_differ<double>), dim3(nb), dim3(256), 0, s, (const double *)a,
+                           (const double *)b, n, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_iter(int dtype, const Lattice &L, const void *min, void *mout,
-                       const void *adiag, const void *bw, double eta, uint32_t *flag,
-                       uint32_t t, hipStream_t s) {
-    return dtype == 0 ? launch_iter_t<float>(L, min, mout, adiag, bw, eta, flag, t, s)
-                      : launch_iter_t<double>(L, min, mout, adiag, bw, eta, flag, t, s);
+template <typename T, int ALPHA>
+static void launch_post_a(bool frozen, const Lattice &L, const void *m, const double *adiag64,
+                          const double *b64, const double *bel64, double *mu_plane,
+                          double *mean, double *var, double *bel_out, hipStream_t s) {
+    dim3 grid(tiles_of(L)), block(256);
+    if (frozen)
+        hipLaunchKernelGGL((k_post<T, ALPHA, true>), grid, block, 0, s, L, (const T *)m, adiag64,
+                           b64, bel64, mu_plane, mean, var, (double *)nullptr);
+    else
+        hipLaunchKernelGGL((k_post<T, ALPHA, false>), grid, block, 0, s, L, (const T *)m, adiag64,
+                           b64, bel64, mu_plane, mean, var, bel_out);
 }
 
 hipError_t launch_post(int dtype, const Lattice &L, const void *m, const double *adiag64,
-                       const double *b64, double *mu_plane, double *mean, double *var,
-                       hipStream_t s) {
-    dim3 grid(tiles_of(L)), block(256);
-    if (dtype == 0)
-        hipLaunchKernelGGL((k_post<float>), grid, block, 0, s, L, (const float *)m, adiag64, b64,
-                           mu_plane, mean, var);
-    else
-        hipLaunchKernelGGL((k_post<double>), grid, block, 0, s, L, (const double *)m, adiag64,
-                           b64, mu_plane, mean, var);
+                       const double *b64, const double *bel64, double *mu_plane, double *mean,
+                       double *var, double *bel_out, hipStream_t s) {
+    const bool fr = bel64 != nullptr;
+    if (dtype == 0) {
+        if (L.alpha == 1) launch_post_a<float, 1>(fr, L, m, adiag64, b64, bel64, mu_plane, mean, var, bel_out, s);
+        else launch_post_a<float, 2>(fr, L, m, adiag64, b64, bel64, mu_plane, mean, var, bel_out, s);
+    } else {
+        if (L.alpha == 1) launch_post_a<double, 1>(fr, L, m, adiag64, b64, bel64, mu_plane, mean, var, bel_out, s);
+        else launch_post_a<double, 2>(fr, L, m, adiag64, b64, bel64, mu_plane, mean, var, bel_out, s);
+    }
     return hipGetLastError();
 }
 

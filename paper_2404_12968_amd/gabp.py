@@ -65,6 +65,8 @@ _SIGS = {
     "gabp_get_messages": ([_P, _P, _P], ctypes.c_int),
     "gabp_set_messages": ([_P, _P, _P], ctypes.c_int),
     "gabp_iteration_count": ([_P, _P], ctypes.c_int),
+    "gabp_autotune": ([_P, ctypes.c_int32, ctypes.c_double, _P], ctypes.c_int),
+    "gabp_precision_frozen": ([_P, _P], ctypes.c_int),
     "gabp_num_directions": ([_P], ctypes.c_int32),
     "gabp_destroy": ([_P], None),
     "gabp_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -251,6 +253,20 @@ def gabp_iteration_count(ctx: Context) -> Tuple[int, int]:
     if st not in (GABP_OK, GABP_E_DIVERGED):
         _check(st, ctx)
     return int(it.value), int(st)
+
+
+def gabp_autotune(ctx: Context, trials: int, damping: float) -> int:
+    """Time every tile shape on `trials` real iterations each; returns the chosen one."""
+    ch = ctypes.c_int32(0)
+    _check(_lib.gabp_autotune(ctx.handle, int(trials), float(damping), ctypes.byref(ch)), ctx)
+    return int(ch.value)
+
+
+def gabp_precision_frozen(ctx: Context) -> int:
+    """Iteration at which the precision messages froze (-1 if not yet)."""
+    at = ctypes.c_int64(-1)
+    _check(_lib.gabp_precision_frozen(ctx.handle, ctypes.byref(at)), ctx)
+    return int(at.value)
 
 
 def gabp_num_directions(ctx: Context) -> int:

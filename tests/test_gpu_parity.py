@@ -342,3 +342,42 @@ def test_global8192_sampled_windows_match_oracle(G, oracle_mod):
         sd, sy, sx, e = plane_slot_map(sub, og.g)
         sel = (sy >= wy - y0) & (sy < wy - y0 + w) & (sx >= m) & (sx < m + w)
         assert rel_l2(lam_g[sd[sel], sy[sel] - (wy - y0), sx[sel] - m], og.lam[e[sel]]) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype,alpha", [("f32", 2), ("f64", 1), ("f32", 1)])
+def test_tile_shapes_are_bitwise_identical(G, dtype, alpha):
+    """The autotuner runs real iterations with every tile shape; the result
+    must equal the same number of iterations with the default shape."""
+    prob = I.small_lattice(200, 75, alpha, bc_x=I.BC_PERIODIC, kappa=0.1, frac=0.1, sigma=0.05,
+                           seed=31, dtype=dtype)
+    a = G.gabp_create_problem(prob)
+    G.gabp_iterate(a, 3, 0.5)
+    chosen = G.gabp_autotune(a, 5, 0.5)
+    assert chosen in (1, 2, 4, 8)
+    assert G.gabp_iteration_count(a) == (3 + 1 + 8 * 5, G.GABP_OK)
+    b = G.gabp_create_problem(prob)
+    G.gabp_iterate(b, 3 + 1 + 8 * 5, 0.5)
+    pa, ia = G.gabp_get_messages(a)
+    pb, ib = G.gabp_get_messages(b)
+    assert torch.equal(pa, pb) and torch.equal(ia, ib)
+
+
+@pytest.mark.parametrize("dtype,alpha,n", [("f32", 2, 600), ("f64", 1, 400), ("f32", 1, 400)])
+def test_frozen_precision_phase_is_bitwise_identical(G, dtype, alpha, n):
+    """Residual checks detect when the precision messages stop changing and
+    switch to the information-only kernel; the result must equal a run that
+    never checks (full kernel throughout), bit for bit."""
+    prob = I.small_lattice(190, 130, alpha, bc_x=I.BC_PERIODIC, kappa=0.1, tracks=5, run=4,
+                           sigma=0.05, seed=77, dtype=dtype)
+    a = G.gabp_create_problem(prob)
+    for _ in range(n // 10):
+        G.gabp_iterate(a, 10, 0.5)
+        G.gabp_residual(a)
+    frozen = G.gabp_precision_frozen(a)
+    b = G.gabp_create_problem(prob)
+    G.gabp_iterate(b, n, 0.5)
+    pa, ia = G.gabp_get_messages(a)
+    pb, ib = G.gabp_get_messages(b)
+    print("frozen at", frozen)
+    assert frozen > 0
+    assert torch.equal(pa, pb) and torch.equal(ia, ib)
