@@ -203,6 +203,72 @@ void gabp_destroy(gabp_ctx *ctx);
 
 const char *gabp_status_string(gabp_status status);
 
+/* ------------------------------------------------------------------------
+ * Batched solving of many independent lattice problems of uneven sizes in
+ * one workspace.  One iteration of the whole batch is one launch of a
+ * persistent-grid kernel over a work list of (instance, tile) items of the
+ * instances still running; instances that converge or diverge retire from
+ * the list; each instance switches to the information-only iteration when
+ * its precision messages freeze.  A chunk of check_every iterations plus the
+ * per-instance FP64 check is captured in a hipGraph and replayed while the
+ * running set is unchanged.  Every instance computes bitwise what a lone
+ * context with the same arguments computes.  The same damping applies to
+ * every instance; c and the prior are per instance.  The batch orders its
+ * work on an internal stream joined to opts->stream (NULL: the default
+ * stream) at every call, so calls are stream-ordered with the caller's work.
+ * ------------------------------------------------------------------------ */
+typedef struct gabp_batch gabp_batch;
+
+typedef struct {
+    gabp_grid grid;
+    gabp_stencil stencil;
+    gabp_obs obs;
+    gabp_noise noise;
+} gabp_instance;
+
+/* Workspace bytes for n instances (INVALID names the first bad instance). */
+gabp_status gabp_batch_workspace_size(int32_t n, const gabp_instance *inst, int32_t dtype,
+                                      size_t *bytes);
+
+/* Create a batch: validates every instance as gabp_create does, folds the
+ * observations into node terms, zeroes all messages.  opts->prior_mean must
+ * be NULL.  Synchronises. */
+gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_opts *opts,
+                              gabp_batch **out);
+
+/* n_iters iterations of every running instance (asynchronous). */
+gabp_status gabp_batch_iterate(gabp_batch *b, int32_t n_iters, double damping);
+
+/* Iterate every running instance in chunks of check_every and check each
+ * one's FP64 relative residual after every chunk; an instance retires when
+ * it reaches rel_tol (status OK), diverges (DIVERGED, same rules as
+ * gabp_solve), or the call has run max_iters iterations (NOT_CONVERGED).
+ * Per-instance results go to the caller's host arrays of n entries (each
+ * may be NULL).  Returns OK when every instance converged, else
+ * NOT_CONVERGED.  Synchronises at every check. */
+gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, double rel_tol,
+                             int32_t check_every, int64_t *iters_done, double *rel_residual,
+                             int32_t *status);
+
+/* Marginals / checkpoint copy of instance i, as gabp_posterior and
+ * gabp_get_messages (device arrays of that instance's size). */
+gabp_status gabp_batch_posterior(gabp_batch *b, int32_t i, double *mean, double *var);
+gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *info);
+
+/* Tile-shape autotuner of the batched iteration, as gabp_autotune (advances
+ * every running instance by 1 + 8 * trials iterations). */
+gabp_status gabp_batch_autotune(gabp_batch *b, int32_t trials, double damping, int32_t *chosen);
+
+/* Iterations applied to instance i, the iteration its precision messages
+ * froze at (-1 if not), and whether it is still running. */
+gabp_status gabp_batch_info(const gabp_batch *b, int32_t i, int64_t *iters, int64_t *frozen_at,
+                            int32_t *running);
+
+void gabp_batch_destroy(gabp_batch *b);
+
+/* Text of the last error of b, or of the last failed batch create (b NULL). */
+const char *gabp_batch_last_error(const gabp_batch *b);
+
 /* Text of the last error of ctx, or of the last failed create when ctx is NULL. */
 const char *gabp_last_error(const gabp_ctx *ctx);
 

@@ -13,62 +13,15 @@
 #include <string>
 
 #include "gabp.h"
+#include "host_common.h"
 #include "internal.h"
 
 using gabp::Lattice;
+using namespace gabp::host;
 
 namespace {
 
 thread_local std::string g_create_error;
-
-constexpr int kNumPartials = 2048;       // workgroups of the residual reduction
-constexpr size_t kAlign = 256;           // byte alignment of rows and planes
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-// Device workspace layout.  Every plane has the same row pitch (elements);
-// message planes are separated by `plane` elements, which adds one 256-byte
-// skew so that the 2*deg concurrent streams do not start on the same HBM
-// channel.
-struct Layout {
-    int32_t pitch = 0;
-    int64_t plane = 0;        // message-plane stride, elements
-    size_t msg[2] = {0, 0};
-    size_t gain = 0;
-    size_t adiag64 = 0, b64 = 0, mu64 = 0, bel64 = 0, adiag_w = 0, b_w = 0;
-    size_t partials = 0, red = 0, flags = 0, total = 0;
-};
-
-Layout make_layout(int64_t nx, int64_t ny, int deg, size_t esize, bool f32) {
-    Layout l;
-    const size_t row_elems = kAlign / esize;
-    l.pitch = (int32_t)round_up((size_t)nx, row_elems);
-    const size_t node_elems = (size_t)l.pitch * (size_t)ny;
-    l.plane = (int64_t)(round_up(node_elems, row_elems) + row_elems);
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = round_up(off + bytes, kAlign);
-        return o;
-    };
-    const size_t buf_bytes = (size_t)(2 * deg) * (size_t)l.plane * esize;
-    l.msg[0] = take(buf_bytes);
-    l.msg[1] = take(buf_bytes);
-    l.gain = take((size_t)deg * (size_t)l.plane * esize);
-    l.adiag64 = take(node_elems * 8);
-    l.b64 = take(node_elems * 8);
-    l.mu64 = take(node_elems * 8);
-    l.bel64 = take(node_elems * 8);
-    if (f32) {
-        l.adiag_w = take(node_elems * esize);
-        l.b_w = take(node_elems * esize);
-    }
-    l.partials = take((size_t)kNumPartials * 2 * sizeof(double));
-    l.red = take(8 * sizeof(double));
-    l.flags = take(4 * sizeof(uint32_t));
-    l.total = off;
-    return l;
-}
 
 struct HostMirror {
     double red[8];
@@ -128,52 +81,6 @@ gabp_status fail(gabp_ctx *ctx, gabp_status st, const std::string &msg) {
         if (e_ != hipSuccess)                                                             \
             return fail((ctx), GABP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
-
-gabp_status check_grid_stencil(const gabp_grid *g, const gabp_stencil *s, int32_t dtype,
-                               std::string &why) {
-    if (!g || !s) return why = "grid and stencil are required", GABP_E_INVALID;
-    if (g->nx < 1 || g->ny < 1) return why = "nx and ny must be >= 1", GABP_E_INVALID;
-    if (!(g->hx > 0) || !(g->hy > 0) || !std::isfinite(g->hx) || !std::isfinite(g->hy))
-        return why = "hx and hy must be positive and finite", GABP_E_INVALID;
-    for (int32_t bc : {g->bc_x, g->bc_y})
-        if (bc < 0 || bc > 2) return why = "unknown boundary type", GABP_E_INVALID;
-    if (s->alpha != 1 && s->alpha != 2) return why = "alpha must be 1 or 2", GABP_E_INVALID;
-    const int64_t minp = s->alpha == 1 ? 3 : 5;
-    if ((g->bc_x == GABP_BC_PERIODIC && g->nx < minp) ||
-        (g->bc_y == GABP_BC_PERIODIC && g->ny < minp))
-        return why = "a periodic axis needs >= 3 cells (alpha 1) or >= 5 (alpha 2)",
-               GABP_E_INVALID;
-    const bool dirichlet = g->bc_x == GABP_BC_DIRICHLET || g->bc_y == GABP_BC_DIRICHLET;
-    if (!std::isfinite(s->kappa) || s->kappa < 0 || (s->kappa == 0 && !dirichlet))
-        return why = "kappa must be > 0 (>= 0 with a Dirichlet axis)", GABP_E_INVALID;
-    if (!(s->tau > 0) || !std::isfinite(s->tau)) return why = "tau must be > 0", GABP_E_INVALID;
-    if (!std::isfinite(s->c) || s->c == 0) return why = "c must be finite and non-zero", GABP_E_INVALID;
-    if (dtype != GABP_F32 && dtype != GABP_F64) return why = "unknown dtype", GABP_E_INVALID;
-    const int64_t pitch = (int64_t)round_up((size_t)g->nx, 64);
-    if (g->nx > (1 << 30) || g->ny > (1 << 30) || pitch * g->ny >= ((int64_t)1 << 31) - 4096)
-        return why = "grid too large for 32-bit in-plane indices", GABP_E_INVALID;
-    return GABP_OK;
-}
-
-Lattice make_lattice(const gabp_grid *g, const gabp_stencil *s, const Layout &lay) {
-    Lattice L{};
-    L.nx = (int32_t)g->nx;
-    L.ny = (int32_t)g->ny;
-    L.pitch = lay.pitch;
-    L.bcx = g->bc_x;
-    L.bcy = g->bc_y;
-    L.alpha = s->alpha;
-    L.deg = s->alpha == 1 ? 4 : 12;
-    L.tiles_x = (int32_t)((g->nx + 63) / 64);
-    L.plane = lay.plane;
-    L.kappa2 = s->kappa * s->kappa;
-    L.tau = s->tau;
-    L.ihx2 = 1.0 / (g->hx * g->hx);
-    L.ihy2 = 1.0 / (g->hy * g->hy);
-    L.c = s->c;
-    L.inv_c = 1.0 / s->c;
-    return L;
-}
 
 gabp_status ctx_ok(gabp_ctx *ctx) {
     if (!ctx) return GABP_E_INVALID;

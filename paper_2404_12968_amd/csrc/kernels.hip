@@ -14,6 +14,7 @@
 #include "internal.h"
 #include "lattice.h"
 #include "numerics.h"
+#include "check_node.h"
 
 // Rounding is spelled out: no implicit multiply-add contraction in this file,
 // explicit fused multiply-adds where wanted.  The full iteration and the
@@ -40,41 +41,11 @@ __global__ __launch_bounds__(256) void k_post(Lattice L, const T *__restrict__ m
                                               double *__restrict__ mean,
                                               double *__restrict__ var,
                                               double *__restrict__ bel_out) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
     const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
     const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
     if (x >= L.nx || y >= L.ny) return;
-    const uint32_t i = (uint32_t)(y * L.pitch + x);
-    uint32_t j[DEG];
-    int xs[DEG], ys[DEG];
-    bool ok[DEG];
-    node_nbrs<DEG, false>(L, x, y, j, xs, ys, ok);
-    T lin[DEG], tin[DEG];
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        if (!FROZEN) lin[d] = (m + (size_t)(d ^ 1) * L.plane)[j[d]];
-        tin[d] = (m + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
-    }
-    double bl;
-    if (FROZEN) {
-        bl = bel64[i];
-    } else {
-        double sl = 0.0;
-#pragma unroll
-        for (int d = 0; d < DEG; ++d) sl += ok[d] ? (double)lin[d] : 0.0;
-        bl = adiag64[i] + L.c * sl;
-        if (bel_out) bel_out[i] = bl;
-    }
-    double st = 0.0;
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) st += ok[d] ? (double)tin[d] : 0.0;
-    const double bt = b64[i] + L.c * st;
-    const double mu = bt / bl;
-    if (mu_plane) mu_plane[i] = mu;
-    const int64_t o = (int64_t)y * L.nx + x;
-    if (mean) mean[o] = mu;
-    if (var) var[o] = 1.0 / bl;
+    post_node<T, ALPHA, FROZEN>(L, m, adiag64, b64, bel64, mu_plane, mean, var, bel_out, x, y);
 }
 
 // --------------------------------------------------------------------------
@@ -82,32 +53,6 @@ __global__ __launch_bounds__(256) void k_post(Lattice L, const T *__restrict__ m
 // Each workgroup sums r^2 and b^2 over a fixed set of tiles in a fixed order
 // (wave64 butterfly, then LDS across the four waves): deterministic partials.
 // --------------------------------------------------------------------------
-template <int ALPHA, bool INTERIOR>
-__device__ __forceinline__ void resid_node(const Lattice &L, const double *__restrict__ mu,
-                                           const double *__restrict__ adiag64,
-                                           const double *__restrict__ b64, int x, int y,
-                                           double &rr, double &bb) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
-    const uint32_t i = (uint32_t)(y * L.pitch + x);
-    uint32_t j[DEG];
-    int xs[DEG], ys[DEG];
-    bool ok[DEG];
-    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
-    double v[DEG];
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) v[d] = mu[j[d]];
-    const double a = adiag64[i], m0 = mu[i], b = b64[i];
-    double s = a * m0;
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        const double q = q_off<double>(L, d, x, y, xs[d], ys[d]);
-        s += ok[d] ? q * v[d] : 0.0;
-    }
-    const double r = s - b;
-    rr += r * r;
-    bb += b * b;
-}
-
 template <int ALPHA>
 __global__ __launch_bounds__(256) void k_resid(Lattice L, const double *__restrict__ mu,
                                                const double *__restrict__ adiag64,

@@ -51,6 +51,11 @@ class gabp_opts(ctypes.Structure):
                 ("prior_mean", ctypes.c_void_p)]
 
 
+class gabp_instance(ctypes.Structure):
+    _fields_ = [("grid", gabp_grid), ("stencil", gabp_stencil), ("obs", gabp_obs),
+                ("noise", gabp_noise)]
+
+
 # name -> (argtypes, restype), mirroring include/gabp.h
 _P = ctypes.c_void_p
 _SIGS = {
@@ -71,6 +76,17 @@ _SIGS = {
     "gabp_destroy": ([_P], None),
     "gabp_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "gabp_last_error": ([_P], ctypes.c_char_p),
+    "gabp_batch_workspace_size": ([ctypes.c_int32, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "gabp_batch_create": ([ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "gabp_batch_iterate": ([_P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+    "gabp_batch_solve": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                          _P, _P, _P], ctypes.c_int),
+    "gabp_batch_posterior": ([_P, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "gabp_batch_get_messages": ([_P, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "gabp_batch_autotune": ([_P, ctypes.c_int32, ctypes.c_double, _P], ctypes.c_int),
+    "gabp_batch_info": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "gabp_batch_destroy": ([_P], None),
+    "gabp_batch_last_error": ([_P], ctypes.c_char_p),
 }
 
 if not os.path.exists(_LIB_PATH):
@@ -277,3 +293,125 @@ def gabp_destroy(ctx: Context) -> None:
     if ctx.handle:
         _lib.gabp_destroy(ctx.handle)
         ctx.handle = None
+
+
+# --------------------------------------------------------------------------
+# batched instances
+# --------------------------------------------------------------------------
+
+class Batch:
+    """A live gabp_batch plus its torch workspace."""
+
+    def __init__(self, handle, workspace, shapes, dtype, device, stream):
+        self.handle = handle
+        self.workspace = workspace
+        self.shapes = shapes          # (nx, ny, deg) per instance
+        self.dtype = dtype
+        self.device = device
+        self.stream = stream
+
+    @property
+    def n(self) -> int:
+        return len(self.shapes)
+
+    def __del__(self):
+        try:
+            gabp_batch_destroy(self)
+        except Exception:
+            pass
+
+
+def _bcheck(st: int, b: Optional[Batch] = None):
+    if st != GABP_OK:
+        h = b.handle if b is not None else None
+        raise GabpError(st, _lib.gabp_batch_last_error(h).decode())
+
+
+def gabp_batch_create(problems, dtype: Optional[str] = None, stream=None, device=None) -> Batch:
+    """Create a batch from a list of ``inputs.Problem`` (observations are
+    staged as device tensors, kept alive until the create call returns)."""
+    device = torch.device(device or "cuda")
+    dt = DTYPES[dtype or problems[0].dtype]
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    n = len(problems)
+    arr = (gabp_instance * n)()
+    keep = []
+    shapes = []
+    for k, p in enumerate(problems):
+        cells = torch.as_tensor(np.asarray(p.cells), dtype=torch.int64).to(device).contiguous()
+        y = torch.as_tensor(np.asarray(p.y), dtype=torch.float64).to(device).contiguous()
+        var = None if p.var is None else \
+            torch.as_tensor(np.asarray(p.var), dtype=torch.float64).to(device).contiguous()
+        keep += [cells, y, var]
+        arr[k].grid = _grid(p.nx, p.ny, p.hx, p.hy, p.bc_x, p.bc_y)
+        arr[k].stencil = _stencil(p.alpha, p.kappa, p.tau, p.c)
+        arr[k].obs = gabp_obs(int(cells.numel()), cells.data_ptr() if cells.numel() else None,
+                              y.data_ptr() if y.numel() else None, 1)
+        arr[k].noise = gabp_noise(float(p.sigma), None if var is None else var.data_ptr())
+        shapes.append((p.nx, p.ny, 4 if p.alpha == 1 else 12))
+    nbytes = ctypes.c_size_t(0)
+    _bcheck(_lib.gabp_batch_workspace_size(n, arr, dt, ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+    opts = gabp_opts(dt, stream.cuda_stream, ws.data_ptr(), int(nbytes.value), None)
+    h = ctypes.c_void_p()
+    _bcheck(_lib.gabp_batch_create(n, arr, ctypes.byref(opts), ctypes.byref(h)))
+    del keep
+    return Batch(h, ws, shapes, dt, device, stream)
+
+
+def gabp_batch_iterate(b: Batch, n_iters: int, damping: float) -> None:
+    _bcheck(_lib.gabp_batch_iterate(b.handle, int(n_iters), float(damping)), b)
+
+
+def gabp_batch_solve(b: Batch, max_iters: int, damping: float, rel_tol: float,
+                     check_every: int = 10):
+    """Returns (status, iters[n], rel[n], status[n]) as numpy arrays."""
+    it = np.zeros(b.n, dtype=np.int64)
+    rel = np.zeros(b.n, dtype=np.float64)
+    sts = np.zeros(b.n, dtype=np.int32)
+    st = _lib.gabp_batch_solve(b.handle, int(max_iters), float(damping), float(rel_tol),
+                               int(check_every), it.ctypes.data_as(_P), rel.ctypes.data_as(_P),
+                               sts.ctypes.data_as(_P))
+    if st not in (GABP_OK, GABP_E_NOT_CONVERGED):
+        _bcheck(st, b)
+    return int(st), it, rel, sts
+
+
+def gabp_batch_posterior(b: Batch, i: int, want_var: bool = True):
+    nx, ny, _ = b.shapes[i]
+    mean = torch.empty((ny, nx), dtype=torch.float64, device=b.device)
+    var = torch.empty((ny, nx), dtype=torch.float64, device=b.device) if want_var else None
+    _bcheck(_lib.gabp_batch_posterior(b.handle, int(i), _ptr(mean), _ptr(var)), b)
+    return mean, var
+
+
+def gabp_batch_get_messages(b: Batch, i: int):
+    nx, ny, deg = b.shapes[i]
+    td = TORCH_DTYPES[b.dtype]
+    prec = torch.empty((deg, ny, nx), dtype=td, device=b.device)
+    info = torch.empty((deg, ny, nx), dtype=td, device=b.device)
+    _bcheck(_lib.gabp_batch_get_messages(b.handle, int(i), _ptr(prec), _ptr(info)), b)
+    return prec, info
+
+
+def gabp_batch_autotune(b: Batch, trials: int, damping: float) -> int:
+    ch = ctypes.c_int32(0)
+    _bcheck(_lib.gabp_batch_autotune(b.handle, int(trials), float(damping), ctypes.byref(ch)), b)
+    return int(ch.value)
+
+
+def gabp_batch_info(b: Batch, i: int):
+    """(iterations, frozen_at, running) of instance i."""
+    it = ctypes.c_int64(0)
+    fz = ctypes.c_int64(0)
+    run = ctypes.c_int32(0)
+    _bcheck(_lib.gabp_batch_info(b.handle, int(i), ctypes.byref(it), ctypes.byref(fz),
+                                 ctypes.byref(run)), b)
+    return int(it.value), int(fz.value), bool(run.value)
+
+
+def gabp_batch_destroy(b: Batch) -> None:
+    if b.handle:
+        _lib.gabp_batch_destroy(b.handle)
+        b.handle = None

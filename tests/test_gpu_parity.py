@@ -381,3 +381,76 @@ def test_frozen_precision_phase_is_bitwise_identical(G, dtype, alpha, n):
     print("frozen at", frozen)
     assert frozen > 0
     assert torch.equal(pa, pb) and torch.equal(ia, ib)
+
+
+# --------------------------------------------------------------------------
+# batched instances
+# --------------------------------------------------------------------------
+
+def _mixed_problems(dtype, n=9):
+    out = []
+    specs = [(70, 66, 1, I.BC_NEUMANN, I.BC_NEUMANN), (130, 40, 2, I.BC_PERIODIC, I.BC_NEUMANN),
+             (33, 90, 2, I.BC_NEUMANN, I.BC_DIRICHLET), (64, 64, 1, I.BC_PERIODIC, I.BC_PERIODIC),
+             (200, 17, 2, I.BC_NEUMANN, I.BC_NEUMANN), (5, 300, 2, I.BC_NEUMANN, I.BC_NEUMANN),
+             (97, 101, 2, I.BC_DIRICHLET, I.BC_NEUMANN), (1, 64, 1, I.BC_NEUMANN, I.BC_NEUMANN),
+             (150, 120, 2, I.BC_NEUMANN, I.BC_PERIODIC)]
+    for k, (nx, ny, a, bx, by) in enumerate(specs[:n]):
+        out.append(I.small_lattice(nx, ny, a, bc_x=bx, bc_y=by, kappa=0.1 + 0.03 * k,
+                                   frac=0.04 + 0.02 * k, sigma=0.05 + 0.01 * k, seed=500 + k,
+                                   dtype=dtype))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_iterations_bitwise_equal_single_contexts(G, dtype):
+    probs = _mixed_problems(dtype)
+    b = G.gabp_batch_create(probs)
+    G.gabp_batch_iterate(b, 37, 0.5)
+    for i, p in enumerate(probs):
+        ctx = G.gabp_create_problem(p)
+        G.gabp_iterate(ctx, 37, 0.5)
+        pa, ia = G.gabp_batch_get_messages(b, i)
+        pb, ib = G.gabp_get_messages(ctx)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib), i
+
+
+def test_batch_solve_matches_single_solves(G, oracle_mod):
+    """Per-instance convergence, retirement and freezing through the captured
+    chunk graph: iteration counts and final states equal the single-context
+    solves bit for bit; means match the direct solve; a diverging instance
+    (13-point prior with c = 1) is reported with the oracle's iteration."""
+    probs = _mixed_problems("f32", 7)
+    bad = I.small_lattice(16, 16, 2, kappa=0.05, c=1.0, frac=0.05, sigma=0.05, seed=7, dtype="f32")
+    probs.append(bad)
+    b = G.gabp_batch_create(probs)
+    st, its, rels, sts = G.gabp_batch_solve(b, 60000, 0.5, 1e-6, 10)
+    assert sts[-1] == G.GABP_E_DIVERGED
+    og = oracle_mod.OracleGaBP.from_problem(bad)
+    og.iterate(50, 0.5)
+    assert its[-1] == og.diverged_at
+    for i, p in enumerate(probs[:-1]):
+        assert sts[i] == G.GABP_OK, (i, sts[i], rels[i])
+        ctx = G.gabp_create_problem(p)
+        s1, it1, rel1 = G.gabp_solve(ctx, 60000, 0.5, 1e-6, 10)
+        assert s1 == G.GABP_OK and it1 == its[i], (i, it1, its[i])
+        assert rel1 == pytest.approx(rels[i], rel=1e-9)
+        pa, ia = G.gabp_batch_get_messages(b, i)
+        pb, ib = G.gabp_get_messages(ctx)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib), i
+        assert G.gabp_batch_info(b, i)[1] == G.gabp_precision_frozen(ctx)
+        mu, _ = G.gabp_batch_posterior(b, i, want_var=False)
+        mref, _ = G.gabp_posterior(ctx, want_var=False)
+        assert torch.equal(mu, mref)
+
+
+def test_batch_autotune_keeps_results(G):
+    probs = _mixed_problems("f32", 5)
+    a = G.gabp_batch_create(probs)
+    ch = G.gabp_batch_autotune(a, 2, 0.5)
+    assert ch in (1, 2, 4, 8)
+    b = G.gabp_batch_create(probs)
+    G.gabp_batch_iterate(b, 1 + 8 * 2, 0.5)
+    for i in range(len(probs)):
+        pa, ia = G.gabp_batch_get_messages(a, i)
+        pb, ib = G.gabp_batch_get_messages(b, i)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib)
