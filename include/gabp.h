@@ -188,6 +188,17 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
  * thread.  Synchronises. */
 gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen);
 
+/* Learned warm start: set the current messages from a prediction pred, a
+ * device array [ny][nx][16] of FP32 (channel 0 the posterior mean mu^,
+ * channels 1..deg the log(-Lam^) of the precision message from the cell to
+ * its neighbour in direction d-1).  Lam_{i->j} = -exp(pred), and
+ * th_{i->j} = Lam_{i->j} mu^_j - (Q_ij / c) mu^_i, the information message
+ * that makes every edge consistent with mu^ (with exact means and converged
+ * precisions this is the fixed point; otherwise the beliefs start at
+ * mu^_i + (b - A mu^)_i / Lam_i).  keep_precisions != 0 keeps the current
+ * precision messages.  The iteration counter is kept.  Async. */
+gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precisions);
+
 /* Iteration at which the precision messages were found frozen, or -1. */
 gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at);
 
@@ -268,6 +279,60 @@ void gabp_batch_destroy(gabp_batch *b);
 
 /* Text of the last error of b, or of the last failed batch create (b NULL). */
 const char *gabp_batch_last_error(const gabp_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Network primitives of the learned warm start: a small 3x3 convolutional
+ * network (BF16 operands, FP32 accumulation on the matrix cores) that maps
+ * observation features to mu^ and log(-Lam^) (see gabp_warm_init), trained
+ * on solutions of this solver.  Tensors are device arrays: activations NHWC
+ * BF16 [B][H][W][C] (C = 16 or 32; BF16 passed as 16-bit words), weights
+ * BF16 [32][9*cin] with k = tap*cin + ci, tap = 3*(dy+1) + (dx+1) (rows
+ * beyond cout zero), FP32 biases [32].  All calls are asynchronous on
+ * `stream` (a hipStream_t, NULL = default stream) and deterministic.
+ * ------------------------------------------------------------------------ */
+
+/* y = act(conv3x3(x, w; dilation dil, zero padding) + bias), act = ReLU when
+ * relu != 0.  Writes y_bf16 and/or y_f32 (NHWC, cout channels). */
+gabp_status gabp_conv3x3_fwd(const void *x, int32_t B, int32_t H, int32_t W, int32_t cin,
+                             const void *w, const float *bias, int32_t cout, int32_t dil,
+                             int32_t relu, void *y_bf16, float *y_f32, void *stream);
+
+/* Bytes of scratch gabp_conv3x3_bwd needs for these shapes. */
+size_t gabp_conv3x3_bwd_workspace(int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout);
+
+/* Backward of y = act(conv3x3(x, w) + b) given dy (FP32 NHWC): weight and
+ * bias gradients dw [32][9*cin], db [32] (FP32) and, when dx != NULL, the
+ * input gradient dx (FP32 NHWC, cin channels).  x and y are the layer's BF16
+ * input and output. */
+gabp_status gabp_conv3x3_bwd(const void *x, const void *y, const float *dy, int32_t B, int32_t H,
+                             int32_t W, int32_t cin, const void *w, int32_t cout, int32_t dil,
+                             int32_t relu, float *dw, float *db, float *dx, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n FP32 master weights w with
+ * gradient g and moments m, v; refreshes the BF16 copy w_bf16 (may be NULL). */
+gabp_status gabp_adam_step(float *w, const float *g, float *m, float *v, void *w_bf16, int64_t n,
+                           double lr, double beta1, double beta2, double eps, int32_t step,
+                           void *stream);
+
+/* Warm-start loss on P pixels: mean of (pred[.,0] - mu_t)^2 plus lam_weight
+ * times the mean over existing edges (valid[d][p] > 0) of
+ * (pred[.,1+d] - lam_t[d][p])^2, d < ndir.  Writes the gradient grad
+ * [P][16] and per-workgroup partial sums partials[*nparts] (FP64; the loss is
+ * their sum). */
+gabp_status gabp_warm_loss(const float *pred, const float *mu_t, const float *lam_t,
+                           const float *valid, int64_t P, int32_t ndir, double lam_weight,
+                           float *grad, double *partials, int32_t *nparts, void *stream);
+
+/* Network input features [ny][nx][16] BF16 from observations (device arrays):
+ * channel 0 mask, 1 mean observed value, 2 log(kappa) + 2.5, others 0.
+ * scratch: 2*nx*ny FP32. */
+gabp_status gabp_warm_features(int64_t nobs, const int64_t *cell, const double *y, int64_t nx,
+                               int64_t ny, double kappa, float *scratch, void *x_bf16,
+                               void *stream);
+
+/* Text of the last error of a network primitive. */
+const char *gabp_net_last_error(void);
 
 /* Text of the last error of ctx, or of the last failed create when ctx is NULL. */
 const char *gabp_last_error(const gabp_ctx *ctx);

@@ -547,6 +547,20 @@ gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at) {
     return GABP_OK;
 }
 
+gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precisions) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (!pred) return fail(ctx, GABP_E_INVALID, "pred is NULL");
+    if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
+    GABP_HIP(ctx, gabp::launch_warm_init(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L, pred,
+                                         keep_precisions ? 1 : 0, ctx->msg[ctx->iter & 1],
+                                         ctx->stream));
+    ctx->prev_valid = false;
+    ctx->frozen = false;
+    ctx->frozen_at = -1;
+    return GABP_OK;
+}
+
 gabp_status gabp_iteration_count(gabp_ctx *ctx, int64_t *iters) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;

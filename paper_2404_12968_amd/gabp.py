@@ -87,6 +87,21 @@ _SIGS = {
     "gabp_batch_info": ([_P, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "gabp_batch_destroy": ([_P], None),
     "gabp_batch_last_error": ([_P], ctypes.c_char_p),
+    "gabp_warm_init": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "gabp_conv3x3_fwd": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                          _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P],
+                         ctypes.c_int),
+    "gabp_conv3x3_bwd_workspace": ([ctypes.c_int32] * 5, ctypes.c_size_t),
+    "gabp_conv3x3_bwd": ([_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "gabp_adam_step": ([_P, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                        ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P], ctypes.c_int),
+    "gabp_warm_loss": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _P, _P,
+                        _P, _P], ctypes.c_int),
+    "gabp_warm_features": ([ctypes.c_int64, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                            ctypes.c_double, _P, _P, _P], ctypes.c_int),
+    "gabp_net_last_error": ([], ctypes.c_char_p),
 }
 
 if not os.path.exists(_LIB_PATH):
@@ -415,3 +430,83 @@ def gabp_batch_destroy(b: Batch) -> None:
     if b.handle:
         _lib.gabp_batch_destroy(b.handle)
         b.handle = None
+
+
+# --------------------------------------------------------------------------
+# learned warm start: network primitives and message initialisation
+# --------------------------------------------------------------------------
+
+def _ncheck(st: int):
+    if st != GABP_OK:
+        raise GabpError(st, _lib.gabp_net_last_error().decode())
+
+
+def _stream_handle(stream):
+    return (stream or torch.cuda.current_stream()).cuda_stream
+
+
+def gabp_warm_init(ctx: Context, pred: torch.Tensor, keep_precisions: bool = False) -> None:
+    """pred: FP32 device tensor [ny, nx, 16] (mean, log(-Lam) per sender-indexed direction)."""
+    if pred.dtype != torch.float32 or tuple(pred.shape) != (ctx.ny, ctx.nx, 16) or not pred.is_cuda:
+        raise ValueError("pred must be a CUDA float32 tensor of shape (ny, nx, 16)")
+    pred = pred.contiguous()
+    _check(_lib.gabp_warm_init(ctx.handle, _ptr(pred), int(bool(keep_precisions))), ctx)
+    ctx._keep_pred = pred
+
+
+def gabp_conv3x3_fwd(x: torch.Tensor, w: torch.Tensor, bias: Optional[torch.Tensor], cout: int,
+                     dil: int, relu: bool, want_bf16: bool = True, want_f32: bool = False,
+                     stream=None):
+    """x: bf16 [B,H,W,cin]; w: bf16 [32, 9*cin]; bias fp32 [32] -> (y_bf16, y_f32)."""
+    B, H, W, cin = x.shape
+    yb = torch.empty((B, H, W, cout), dtype=torch.bfloat16, device=x.device) if want_bf16 else None
+    yf = torch.empty((B, H, W, cout), dtype=torch.float32, device=x.device) if want_f32 else None
+    _ncheck(_lib.gabp_conv3x3_fwd(_ptr(x), B, H, W, cin, _ptr(w), _ptr(bias), int(cout), int(dil),
+                                  int(bool(relu)), _ptr(yb), _ptr(yf), _stream_handle(stream)))
+    return yb, yf
+
+
+def gabp_conv3x3_bwd(x, y, dy, w, cout, dil, relu, need_dx=True, workspace=None, stream=None):
+    """Returns (dw [32, 9*cin], db [32], dx [B,H,W,cin] or None), all FP32."""
+    B, H, W, cin = x.shape
+    nbytes = int(_lib.gabp_conv3x3_bwd_workspace(B, H, W, cin, int(cout)))
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    dw = torch.empty((32, 9 * cin), dtype=torch.float32, device=x.device)
+    db = torch.empty(32, dtype=torch.float32, device=x.device)
+    dx = torch.empty((B, H, W, cin), dtype=torch.float32, device=x.device) if need_dx else None
+    _ncheck(_lib.gabp_conv3x3_bwd(_ptr(x), _ptr(y), _ptr(dy), B, H, W, cin, _ptr(w), int(cout),
+                                  int(dil), int(bool(relu)), _ptr(dw), _ptr(db), _ptr(dx),
+                                  _ptr(workspace), nbytes, _stream_handle(stream)))
+    return dw, db, dx, workspace
+
+
+def gabp_adam_step(w, g, m, v, w_bf16, lr, beta1, beta2, eps, step, stream=None) -> None:
+    _ncheck(_lib.gabp_adam_step(_ptr(w), _ptr(g), _ptr(m), _ptr(v), _ptr(w_bf16), int(w.numel()),
+                                float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                _stream_handle(stream)))
+
+
+def gabp_warm_loss(pred, mu_t, lam_t, valid, ndir, lam_weight, stream=None):
+    """Returns (loss as a 0-d FP64 device tensor, grad [P,16])."""
+    P = pred.numel() // 16
+    grad = torch.empty_like(pred)
+    parts = torch.empty((P + 255) // 256, dtype=torch.float64, device=pred.device)
+    nparts = ctypes.c_int32(0)
+    _ncheck(_lib.gabp_warm_loss(_ptr(pred), _ptr(mu_t), _ptr(lam_t), _ptr(valid), int(P), int(ndir),
+                                float(lam_weight), _ptr(grad), _ptr(parts), ctypes.byref(nparts),
+                                _stream_handle(stream)))
+    return parts[: nparts.value].sum(), grad
+
+
+def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
+    """[ny, nx, 16] bf16 input features of one problem."""
+    device = torch.device(device or "cuda")
+    cells = torch.as_tensor(np.asarray(cells), dtype=torch.int64).to(device).contiguous()
+    y = torch.as_tensor(np.asarray(y), dtype=torch.float64).to(device).contiguous()
+    scratch = torch.empty(2 * nx * ny, dtype=torch.float32, device=device)
+    x = torch.empty((ny, nx, 16), dtype=torch.bfloat16, device=device)
+    _ncheck(_lib.gabp_warm_features(int(cells.numel()), _ptr(cells) if cells.numel() else None,
+                                    _ptr(y) if y.numel() else None, int(nx), int(ny), float(kappa),
+                                    _ptr(scratch), _ptr(x), _stream_handle(stream)))
+    return x

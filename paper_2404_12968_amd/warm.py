@@ -1,0 +1,286 @@
+"""Learned warm start for the lattice solver.
+
+A 6-layer 3x3 convolutional network with 32 hidden channels maps the
+observation features of a problem (mask, observed values, log kappa) to a
+prediction of the posterior mean and of the log(-precision) of every
+sender-indexed message; ``gabp_warm_init`` turns the prediction into a
+starting state and the ordinary solver iterates from there, so the FP64
+residual test still decides convergence and cold start remains the fallback.
+
+The network is trained on solutions the solver itself computed (batched
+solves of seeded problems of the warm-start workload).  Every numeric step
+-- convolutions forward and backward (BF16 matrix-core kernels, FP32
+accumulation), loss, Adam -- runs in the library's kernels; this module only
+orchestrates them and slices tensors.
+
+Layers: dilations 1, 3, 9, 27, 9, 1 (with 3x3 kernels the first four cover
+every offset up to +-40 cells exactly once; the whole stack sees +-50 cells),
+channels 16 (3 used) -> 32 x 5 -> 16 (13 used), ReLU on all but the last.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import gabp as G
+from . import inputs as I
+
+DILATIONS = (1, 3, 9, 27, 9, 1)
+CIN = (16, 32, 32, 32, 32, 32)
+COUT = (32, 32, 32, 32, 32, 16)
+RELU = (1, 1, 1, 1, 1, 0)
+NDIR = 12
+DIRS = [(1, 0), (-1, 0), (0, 1), (0, -1), (2, 0), (-2, 0), (0, 2), (0, -2),
+        (1, 1), (-1, -1), (1, -1), (-1, 1)]
+
+
+class WarmNet:
+    """Weights (FP32 masters + BF16 copies) and Adam state of the network."""
+
+    def __init__(self, device="cuda", seed: int = 0):
+        self.device = torch.device(device)
+        g = torch.Generator().manual_seed(seed)
+        self.w: List[torch.Tensor] = []
+        self.b: List[torch.Tensor] = []
+        for l in range(len(DILATIONS)):
+            fan_in = 9 * CIN[l]
+            std = math.sqrt(2.0 / fan_in) if RELU[l] else math.sqrt(1.0 / fan_in)
+            w = torch.zeros(32, 9 * CIN[l])
+            w[: COUT[l]] = torch.randn(COUT[l], 9 * CIN[l], generator=g) * std
+            self.w.append(w.to(self.device))
+            self.b.append(torch.zeros(32, device=self.device))
+        self.wb = [w.to(torch.bfloat16) for w in self.w]
+        self.m = [torch.zeros_like(t) for t in self.w + self.b]
+        self.v = [torch.zeros_like(t) for t in self.w + self.b]
+        self.step = 0
+        self._ws = None
+
+    # -- inference ---------------------------------------------------------
+    def forward(self, x: torch.Tensor):
+        """x: bf16 [B,H,W,16] -> (activations, pred FP32 [B,H,W,16])."""
+        acts = [x]
+        pred = None
+        for l in range(len(DILATIONS)):
+            last = l == len(DILATIONS) - 1
+            yb, yf = G.gabp_conv3x3_fwd(acts[-1], self.wb[l], self.b[l], COUT[l], DILATIONS[l],
+                                        bool(RELU[l]), want_bf16=True, want_f32=last)
+            acts.append(yb)
+            if last:
+                pred = yf
+        return acts, pred
+
+    # -- training ----------------------------------------------------------
+    def backward(self, acts, grad):
+        """Gradients (dw, db) of every layer from the loss gradient (FP32)."""
+        dws, dbs = [None] * len(DILATIONS), [None] * len(DILATIONS)
+        dy = grad
+        for l in reversed(range(len(DILATIONS))):
+            dw, db, dx, self._ws = G.gabp_conv3x3_bwd(acts[l], acts[l + 1], dy, self.wb[l],
+                                                      COUT[l], DILATIONS[l], bool(RELU[l]),
+                                                      need_dx=l > 0, workspace=self._ws)
+            dws[l], dbs[l] = dw, db
+            dy = dx
+        return dws, dbs
+
+    def adam(self, dws, dbs, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        L = len(DILATIONS)
+        for l in range(L):
+            G.gabp_adam_step(self.w[l], dws[l], self.m[l], self.v[l], self.wb[l], lr, beta1, beta2,
+                             eps, self.step)
+            G.gabp_adam_step(self.b[l], dbs[l], self.m[L + l], self.v[L + l], None, lr, beta1,
+                             beta2, eps, self.step)
+
+    # -- persistence -------------------------------------------------------
+    def save(self, path: str, meta: Optional[Dict] = None) -> None:
+        arrs = {f"w{l}": self.w[l].cpu().numpy() for l in range(len(DILATIONS))}
+        arrs.update({f"b{l}": self.b[l].cpu().numpy() for l in range(len(DILATIONS))})
+        arrs["dilations"] = np.array(DILATIONS)
+        if meta:
+            arrs["meta"] = np.array(repr(meta))
+        np.savez(path, **arrs)
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "WarmNet":
+        net = cls(device)
+        with np.load(path, allow_pickle=False) as z:
+            if tuple(z["dilations"]) != DILATIONS:
+                raise ValueError("weights are for another architecture")
+            for l in range(len(DILATIONS)):
+                net.w[l] = torch.tensor(z[f"w{l}"], device=net.device)
+                net.b[l] = torch.tensor(z[f"b{l}"], device=net.device)
+        net.wb = [w.to(torch.bfloat16) for w in net.w]
+        return net
+
+
+# --------------------------------------------------------------------------
+# targets from solver states
+# --------------------------------------------------------------------------
+
+def sender_log_precisions(prec_recv: torch.Tensor, bc_x: int, bc_y: int):
+    """log(-Lam) of sender-indexed messages from receiver-indexed precision
+    planes [deg, ny, nx] (gabp_get_messages layout): the message from i to
+    i + off_d is the receiver slot d^1 at i + off_d.  Returns (lam [12,ny,nx],
+    valid [12,ny,nx]) FP32 with valid = 1 where the edge exists."""
+    deg, ny, nx = prec_recv.shape
+    lam = torch.zeros((NDIR, ny, nx), dtype=torch.float32, device=prec_recv.device)
+    valid = torch.zeros_like(lam)
+    for d in range(deg):
+        dx, dy = DIRS[d]
+        src = prec_recv[d ^ 1].to(torch.float32)
+        # out[y, x] = src[y + dy, x + dx]
+        sh = torch.zeros_like(src)
+        ok = torch.zeros_like(src)
+        ys = slice(max(0, -dy), min(ny, ny - dy)); yt = slice(max(0, dy), min(ny, ny + dy))
+        xs = slice(max(0, -dx), min(nx, nx - dx)); xt = slice(max(0, dx), min(nx, nx + dx))
+        if bc_x == I.BC_PERIODIC or bc_y == I.BC_PERIODIC:
+            rolled = torch.roll(src, shifts=(-dy, -dx), dims=(0, 1))
+            okp = torch.ones_like(src)
+            if bc_y != I.BC_PERIODIC:
+                okp[:max(0, -dy)] = 0
+                if dy > 0:
+                    okp[ny - dy:] = 0
+            if bc_x != I.BC_PERIODIC:
+                okp[:, :max(0, -dx)] = 0
+                if dx > 0:
+                    okp[:, nx - dx:] = 0
+            sh, ok = rolled * okp, okp
+        else:
+            sh[ys, xs] = src[yt, xt]
+            ok[ys, xs] = 1.0
+        valid[d] = ok
+        lam[d] = torch.where(ok > 0, torch.log(torch.clamp(-sh, min=1e-30)), torch.zeros_like(sh))
+    return lam, valid
+
+
+class TrainingSet:
+    """Features and solver targets of many problems, resident on the GPU."""
+
+    def __init__(self):
+        self.x: List[torch.Tensor] = []      # bf16 [ny, nx, 16]
+        self.mu: List[torch.Tensor] = []     # fp32 [ny, nx]
+        self.lam: List[torch.Tensor] = []    # fp32 [12, ny, nx]
+        self.valid: List[torch.Tensor] = []  # fp32 [12, ny, nx]
+        self.iters: List[int] = []
+
+    def __len__(self):
+        return len(self.x)
+
+
+def solve_training_set(problems: Sequence[I.Problem], max_iters: int = 300000,
+                       rel_tol: float = 1e-6, device="cuda", log=print) -> TrainingSet:
+    """Solve the problems with the batched solver and keep features + targets."""
+    ts = TrainingSet()
+    t0 = time.time()
+    b = G.gabp_batch_create(list(problems), device=device)
+    st, its, rels, sts = G.gabp_batch_solve(b, max_iters, 0.5, rel_tol, 10)
+    torch.cuda.synchronize()
+    log(f"[warm] solved {len(problems)} problems in {time.time() - t0:.1f}s: "
+        f"{int((sts == G.GABP_OK).sum())} converged, iterations median {int(np.median(its))}")
+    for i, p in enumerate(problems):
+        if sts[i] != G.GABP_OK:
+            continue
+        mean, _ = G.gabp_batch_posterior(b, i, want_var=False)
+        prec, _ = G.gabp_batch_get_messages(b, i)
+        lam, valid = sender_log_precisions(prec, p.bc_x, p.bc_y)
+        ts.x.append(G.gabp_warm_features(p.cells, p.y, p.nx, p.ny, p.kappa, device=device))
+        ts.mu.append(mean.to(torch.float32))
+        ts.lam.append(lam)
+        ts.valid.append(valid)
+        ts.iters.append(int(its[i]))
+    del b
+    torch.cuda.synchronize()
+    return ts
+
+
+def train(net: WarmNet, ts: TrainingSet, steps: int, batch: int = 8, crop: int = 256,
+          lr: float = 2e-3, lam_weight: float = 0.1, seed: int = 0, log=print,
+          log_every: int = 100) -> List[float]:
+    """Adam on random crops of the training set; returns the loss history."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    t0 = time.time()
+    for s in range(steps):
+        xs, mus, lams, vals = [], [], [], []
+        for _ in range(batch):
+            k = int(rng.integers(0, len(ts)))
+            ny, nx = ts.mu[k].shape
+            cy = int(rng.integers(0, ny - crop + 1)) if ny > crop else 0
+            cx = int(rng.integers(0, nx - crop + 1)) if nx > crop else 0
+            h, w = min(crop, ny), min(crop, nx)
+            xs.append(ts.x[k][cy:cy + h, cx:cx + w])
+            mus.append(ts.mu[k][cy:cy + h, cx:cx + w])
+            lams.append(ts.lam[k][:, cy:cy + h, cx:cx + w])
+            vals.append(ts.valid[k][:, cy:cy + h, cx:cx + w])
+        x = torch.stack(xs).contiguous()
+        mu = torch.stack(mus).contiguous()
+        # direction-major targets [12, B*h*w] to match the kernel's layout
+        lam = torch.stack(lams, dim=1).reshape(NDIR, -1).contiguous()
+        val = torch.stack(vals, dim=1).reshape(NDIR, -1).contiguous()
+        acts, pred = net.forward(x)
+        loss, grad = G.gabp_warm_loss(pred, mu.reshape(-1), lam, val, NDIR, lam_weight)
+        dws, dbs = net.backward(acts, grad)
+        cur = lr * 0.5 * (1 + math.cos(math.pi * s / max(1, steps)))
+        net.adam(dws, dbs, cur)
+        if s % log_every == 0 or s == steps - 1:
+            lv = float(loss)
+            hist.append(lv)
+            log(f"[warm] step {s} loss {lv:.5f} lr {cur:.2e} ({time.time() - t0:.1f}s)")
+    return hist
+
+
+def predict(net: WarmNet, prob: I.Problem, device="cuda") -> torch.Tensor:
+    """Prediction [ny, nx, 16] FP32 for one problem."""
+    x = G.gabp_warm_features(prob.cells, prob.y, prob.nx, prob.ny, prob.kappa, device=device)
+    _, pred = net.forward(x.unsqueeze(0).contiguous())
+    return pred[0].contiguous()
+
+
+def warm_solve(net: WarmNet, prob: I.Problem, max_iters: int = 300000, probe: int = 100,
+               device="cuda", use_precisions: bool = True):
+    """Solve from the network's warm start; cold start is the fallback: after
+    `probe` iterations the warm run's residual is compared with a cold run's
+    at the same iteration, and the worse of the two is dropped.  Returns a
+    dict with status, iterations, seconds (including inference) and which
+    start won."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = predict(net, prob, device)
+    warm = G.gabp_create_problem(prob, device=device)
+    G.gabp_warm_init(warm, pred, keep_precisions=not use_precisions)
+    cold = G.gabp_create_problem(prob, device=device)
+    G.gabp_iterate(cold, probe, prob.damping)
+    rc, _ = G.gabp_residual(cold)
+    try:
+        G.gabp_iterate(warm, probe, prob.damping)
+        rw, _ = G.gabp_residual(warm)
+    except G.GabpError as e:
+        # a prediction that makes a cavity precision non-positive diverges at
+        # once: the cold start takes over
+        if e.status != G.GABP_E_DIVERGED:
+            raise
+        rw = math.inf
+    if rw <= rc:
+        ctx, which = warm, "warm"
+        G.gabp_destroy(cold)
+    else:
+        ctx, which = cold, "cold"
+        G.gabp_destroy(warm)
+    st, it, rel = G.gabp_solve(ctx, max_iters - probe, prob.damping, prob.rel_tol,
+                               prob.check_every)
+    torch.cuda.synchronize()
+    return {"status": st, "iterations": it, "seconds": time.perf_counter() - t0,
+            "rel": rel, "start": which, "probe_residual_warm": rw, "probe_residual_cold": rc}
+
+
+def cold_solve(prob: I.Problem, max_iters: int = 300000, device="cuda"):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = G.gabp_create_problem(prob, device=device)
+    st, it, rel = G.gabp_solve(ctx, max_iters, prob.damping, prob.rel_tol, prob.check_every)
+    torch.cuda.synchronize()
+    return {"status": st, "iterations": it, "seconds": time.perf_counter() - t0, "rel": rel}

@@ -1,0 +1,100 @@
+"""Train the warm-start network on solver solutions and evaluate it.
+
+    python -m paper_2404_12968_amd.warm_train --n-train 128 --steps 3000 \\
+        --out paper_2404_12968_amd/weights/warm1024.npz --eval 6
+
+1. Draws `n-train` problems of the 1024 x 1024 warm-start workload (seeds
+   0..n-1) and solves them to 1e-6 with the batched solver.
+2. Trains the network (Adam, cosine schedule) on random 256 x 256 crops of
+   those solutions.
+3. Solves `eval` held-out problems (seeds 100000 + k) cold and warm (network
+   inference included in the warm time, cold fallback active) and prints one
+   JSON summary line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import warm as Wm
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-train", type=int, default=128)
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--crop", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lam-weight", type=float, default=0.1)
+    ap.add_argument("--eval", type=int, default=6)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--summary", default=None)
+    args = ap.parse_args(argv)
+
+    def log(*a):
+        print(*a, flush=True)
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    probs = [I.warm1024(instance=k, n=args.side) for k in range(args.n_train)]
+    log(f"[warm] generated {len(probs)} problems in {time.time() - t0:.1f}s")
+    chunk = 64
+    ts = Wm.TrainingSet()
+    for c0 in range(0, len(probs), chunk):
+        part = Wm.solve_training_set(probs[c0:c0 + chunk], log=log)
+        for f in ("x", "mu", "lam", "valid", "iters"):
+            getattr(ts, f).extend(getattr(part, f))
+    log(f"[warm] training set: {len(ts)} solutions, iterations median {int(np.median(ts.iters))}")
+    net = Wm.WarmNet(seed=0)
+    t1 = time.time()
+    hist = Wm.train(net, ts, args.steps, batch=args.batch, crop=args.crop, lr=args.lr,
+                    lam_weight=args.lam_weight, log=log, log_every=200)
+    train_s = time.time() - t1
+    del ts
+    torch.cuda.empty_cache()
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        net.save(args.out, meta={"n_train": args.n_train, "steps": args.steps,
+                                 "batch": args.batch, "crop": args.crop, "lr": args.lr,
+                                 "side": args.side, "final_loss": hist[-1]})
+        log(f"[warm] saved {args.out}")
+    evals = []
+    for k in range(args.eval):
+        p = I.warm1024(instance=100000 + k, n=args.side)
+        c = Wm.cold_solve(p)
+        w = Wm.warm_solve(net, p)
+        wm = Wm.warm_solve(net, p, use_precisions=False)
+        evals.append({"instance": 100000 + k, "kappa": p.kappa, "coverage": p.coverage,
+                      "cold_iters": c["iterations"], "cold_s": c["seconds"],
+                      "warm_iters": w["iterations"], "warm_s": w["seconds"],
+                      "warm_mean_only_iters": wm["iterations"], "warm_mean_only_s": wm["seconds"],
+                      "start": w["start"], "cold_status": c["status"],
+                      "warm_status": w["status"]})
+        log(f"[warm] eval {k}: kappa {p.kappa:.3f} cold {c['iterations']} it {c['seconds']:.2f}s"
+            f" | warm {w['iterations']} it {w['seconds']:.2f}s ({w['start']})"
+            f" | mean-only {wm['iterations']} it")
+    cold_t = sum(e["cold_s"] for e in evals)
+    warm_t = sum(e["warm_s"] for e in evals)
+    summary = {"n_train": args.n_train, "steps": args.steps, "train_seconds": train_s,
+               "loss_first": hist[0], "loss_last": hist[-1], "eval": evals,
+               "cold_seconds_total": cold_t, "warm_seconds_total": warm_t,
+               "speedup": cold_t / warm_t if warm_t > 0 else None}
+    line = json.dumps(summary)
+    print(line, flush=True)
+    if args.summary:
+        with open(args.summary, "w") as f:
+            f.write(line + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

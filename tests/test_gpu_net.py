@@ -1,0 +1,171 @@
+"""GPU parity of the warm-start network kernels against the FP64 reference
+(inputs rounded to BF16 as the kernels see them) and of the warm
+initialisation against the solver's own fixed point."""
+import numpy as np
+import pytest
+
+from oracle import conv_ref as C
+from paper_2404_12968_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp
+    return gabp
+
+
+def bf16_round(a):
+    return torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def weights(rng, cin, cout):
+    w = np.zeros((32, 9 * cin))
+    w[:cout] = rng.normal(size=(cout, 9 * cin)) * 0.2
+    return bf16_round(w)
+
+
+CASES = [(16, 32, 1, 1), (32, 32, 3, 1), (32, 32, 27, 1), (32, 16, 1, 0), (16, 16, 9, 0),
+         (32, 32, 2, 0)]
+
+
+@pytest.mark.parametrize("cin,cout,dil,relu", CASES)
+def test_conv_forward_matches_reference(G, cin, cout, dil, relu):
+    rng = np.random.default_rng(cin * 100 + dil)
+    B, H, W = 2, 13, 70
+    x = bf16_round(rng.normal(size=(B, H, W, cin)))
+    w = weights(rng, cin, cout)
+    b = rng.normal(size=32).astype(np.float32)
+    xg = torch.tensor(x, dtype=torch.bfloat16, device="cuda")
+    wg = torch.tensor(w, dtype=torch.bfloat16, device="cuda")
+    bg = torch.tensor(b, device="cuda")
+    yb, yf = G.gabp_conv3x3_fwd(xg, wg, bg, cout, dil, bool(relu), want_bf16=True, want_f32=True)
+    torch.cuda.synchronize()
+    _, yref = C.conv3x3_fwd(x, w[:cout].reshape(cout, 9, cin), b[:cout], dil, bool(relu))
+    got = yf.cpu().double().numpy()
+    scale = np.abs(yref).max() + 1.0
+    assert np.abs(got - yref).max() <= 2e-5 * scale
+    assert np.array_equal(yb.cpu().float().numpy(), yf.cpu().to(torch.bfloat16).float().numpy())
+
+
+@pytest.mark.parametrize("cin,cout,dil,relu", CASES)
+def test_conv_backward_matches_reference(G, cin, cout, dil, relu):
+    rng = np.random.default_rng(cin * 7 + dil)
+    B, H, W = 2, 11, 45
+    x = bf16_round(rng.normal(size=(B, H, W, cin)))
+    w = weights(rng, cin, cout)
+    b = rng.normal(size=32).astype(np.float32) * 0.1
+    xg = torch.tensor(x, dtype=torch.bfloat16, device="cuda")
+    wg = torch.tensor(w, dtype=torch.bfloat16, device="cuda")
+    yb, _ = G.gabp_conv3x3_fwd(xg, wg, torch.tensor(b, device="cuda"), cout, dil, bool(relu))
+    dy = rng.normal(size=(B, H, W, cout)).astype(np.float32)
+    dw, db, dx, _ = G.gabp_conv3x3_bwd(xg, yb, torch.tensor(dy, device="cuda"), wg, cout, dil,
+                                      bool(relu), need_dx=True)
+    torch.cuda.synchronize()
+    # the kernels take dz = dy * relu'(y) in BF16 and mask with the stored output
+    y = yb.cpu().double().numpy()
+    dz = bf16_round(dy * ((y > 0) if relu else 1.0))
+    dxr, dwr, dbr = C.conv3x3_bwd(x, np.ones_like(dz), dz, w[:cout].reshape(cout, 9, cin), dil,
+                                  relu=False)
+    dw_g = dw.cpu().double().numpy()
+    assert np.all(dw_g[cout:] == 0)
+    np.testing.assert_allclose(dw_g[:cout].reshape(cout, 9, cin), dwr, rtol=0,
+                               atol=2e-5 * (np.abs(dwr).max() + 1))
+    np.testing.assert_allclose(db.cpu().double().numpy()[:cout], dbr, rtol=0,
+                               atol=2e-5 * (np.abs(dbr).max() + 1))
+    np.testing.assert_allclose(dx.cpu().double().numpy(), dxr, rtol=0,
+                               atol=2e-5 * (np.abs(dxr).max() + 1))
+
+
+def test_adam_matches_reference(G):
+    rng = np.random.default_rng(3)
+    n = 1000
+    w = rng.normal(size=n).astype(np.float32)
+    wr, m, v = w.astype(np.float64), np.zeros(n), np.zeros(n)
+    wg = torch.tensor(w, device="cuda")
+    mg = torch.zeros(n, device="cuda")
+    vg = torch.zeros(n, device="cuda")
+    wb = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    for step in range(1, 6):
+        g = rng.normal(size=n).astype(np.float32)
+        G.gabp_adam_step(wg, torch.tensor(g, device="cuda"), mg, vg, wb, 1e-2, 0.9, 0.999, 1e-8, step)
+        wr, m, v = C.adam(wr, g.astype(np.float64), m, v, 1e-2, 0.9, 0.999, 1e-8, step)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(wg.cpu().numpy(), wr, rtol=1e-5, atol=1e-6)
+    assert torch.equal(wb, wg.to(torch.bfloat16))
+
+
+def test_loss_and_gradient(G):
+    rng = np.random.default_rng(4)
+    P = 700
+    pred = rng.normal(size=(P, 16)).astype(np.float32)
+    mu = rng.normal(size=P).astype(np.float32)
+    lam = rng.normal(size=(12, P)).astype(np.float32)
+    val = (rng.random((12, P)) > 0.2).astype(np.float32)
+    loss, grad = G.gabp_warm_loss(torch.tensor(pred, device="cuda"), torch.tensor(mu, device="cuda"),
+                                  torch.tensor(lam, device="cuda"), torch.tensor(val, device="cuda"),
+                                  12, 0.3)
+    e0 = pred[:, 0].astype(np.float64) - mu
+    el = (pred[:, 1:13].T.astype(np.float64) - lam) * val
+    ref = (e0 ** 2).mean() + 0.3 * (el ** 2).sum() / (P * 12)
+    assert float(loss) == pytest.approx(ref, rel=1e-5)
+    g = grad.cpu().numpy()
+    np.testing.assert_allclose(g[:, 0], 2 * e0 / P, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(g[:, 1:13].T, 2 * 0.3 * el / (P * 12), rtol=1e-5, atol=1e-9)
+    assert np.all(g[:, 13:] == 0)
+
+
+def test_features(G):
+    cells = np.array([0, 5, 5, 17], dtype=np.int64)
+    y = np.array([1.0, 2.0, 4.0, -1.0])
+    x = G.gabp_warm_features(cells, y, 6, 4, 0.1).float().cpu().numpy()
+    assert x.shape == (4, 6, 16)
+    flat = x.reshape(-1, 16)
+    assert flat[0, 0] == 1 and flat[0, 1] == 1.0
+    assert flat[5, 0] == 1 and flat[5, 1] == 3.0
+    assert flat[17, 1] == -1.0 and flat[1, 0] == 0 and flat[1, 1] == 0
+    assert np.allclose(flat[:, 2], np.float32(torch.tensor(np.log(0.1) + 2.5).to(torch.bfloat16).float()))
+    assert np.all(flat[:, 3:] == 0)
+
+
+@pytest.mark.parametrize("bcx", [I.BC_NEUMANN, I.BC_PERIODIC])
+def test_warm_init_from_the_fixed_point_is_converged(G, bcx):
+    """Initialising from the solver's own converged means and precisions puts
+    every edge on the fixed point: the residual is already at the converged
+    level and further iterations do not move the mean."""
+    from paper_2404_12968_amd import warm
+    prob = I.small_lattice(90, 70, 2, bc_x=bcx, kappa=0.15, frac=0.1, sigma=0.05, seed=3,
+                           dtype="f64")
+    ref = G.gabp_create_problem(prob)
+    st, it, rel = G.gabp_solve(ref, 200000, 0.5, 1e-12, 50)
+    assert st == G.GABP_OK
+    mean, _ = G.gabp_posterior(ref, want_var=False)
+    prec, _ = G.gabp_get_messages(ref)
+    lam, valid = warm.sender_log_precisions(prec, prob.bc_x, prob.bc_y)
+    pred = torch.zeros((prob.ny, prob.nx, 16), dtype=torch.float32, device="cuda")
+    pred[:, :, 0] = mean.float()
+    pred[:, :, 1:13] = lam.permute(1, 2, 0)
+    ctx = G.gabp_create_problem(prob)
+    G.gabp_warm_init(ctx, pred)
+    r0, _ = G.gabp_residual(ctx)
+    assert r0 < 1e-5            # FP32 rounding of the prediction
+    G.gabp_iterate(ctx, 20, 0.5)
+    m2, _ = G.gabp_posterior(ctx, want_var=False)
+    assert float((m2 - mean).norm() / mean.norm()) < 1e-5
+
+
+def test_training_reduces_loss(G):
+    from paper_2404_12968_amd import warm
+    probs = [I.warm1024(instance=k, n=96) for k in range(6)]
+    for p in probs:
+        p.rel_tol = 1e-6
+    ts = warm.solve_training_set(probs, log=lambda *a: None)
+    assert len(ts) == 6
+    net = warm.WarmNet(seed=1)
+    hist = warm.train(net, ts, steps=60, batch=4, crop=64, lr=3e-3, log=lambda *a: None,
+                      log_every=10)
+    assert hist[-1] < 0.5 * hist[0], hist
