@@ -52,14 +52,15 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(phase):
-    """HBM bytes per launch of the timed kernel from the committed PMC summary,
-    if it was taken on the current kernel source (else None)."""
+def measured_traffic(phase, rpt):
+    """HBM bytes per launch of the timed kernel (its tile shape) from the
+    committed PMC summary, if that was taken on the current kernel source."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     text = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
-    t = re.search(PHASE_KERNEL[phase] + r"_traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    key = f"{PHASE_KERNEL[phase]}_rpt{rpt}_traffic_bytes_per_launch"
+    t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_source_digest():
         return None
     return float(t.group(1))
@@ -174,10 +175,15 @@ def main(argv=None):
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
     ap.add_argument("--warm-instances", type=int, default=3)
+    ap.add_argument("--print-digest", action="store_true",
+                    help="print the iteration kernels' source digest and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of known size (PMC byte calibration) and exit")
     args = ap.parse_args(argv)
 
+    if args.print_digest:
+        print(kernel_source_digest())
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the lattice would shard into row strips with a halo exchange; not built).",
@@ -277,7 +283,7 @@ def main(argv=None):
     total_iters = args.steps * ITERS_PER_STEP
     value = E * total_iters / wall
     achieved = alg_bytes / (iter_ms * 1e-3) / 1e9
-    traffic = measured_traffic(phase)
+    traffic = measured_traffic(phase, rpt)
     kname = "k_iter_theta" if phase == "theta" else "k_iter_direct"
 
     out = {
