@@ -99,6 +99,7 @@ def cpu_baseline(prob, seconds=10.0):
 def bench_warm(I, n):
     """Time to 1e-6 on held-out 1024^2 warm-start problems, cold vs the trained
     network's warm start (inference and the fallback probe included)."""
+    from paper_2404_12968_amd import multigrid as MG
     from paper_2404_12968_amd import warm as Wm
     path = os.path.join(ROOT, "paper_2404_12968_amd", "weights", "warm1024.npz")
     net = Wm.WarmNet.load(path)
@@ -110,12 +111,29 @@ def bench_warm(I, n):
         rows.append({"instance": 300000 + k, "kappa": round(p.kappa, 4),
                      "cold_iters": c["iterations"], "cold_s": c["seconds"],
                      "warm_iters": w["iterations"], "warm_s": w["seconds"], "start": w["start"]})
+    for r in rows:
+        m = MG.multigrid_solve(I.warm1024(instance=r["instance"]))
+        r["multigrid_iters"], r["multigrid_s"] = m["iterations"], m["seconds"]
     cs = sum(r["cold_s"] for r in rows)
     ws = sum(r["warm_s"] for r in rows)
+    ms = sum(r["multigrid_s"] for r in rows)
     return {"workload": "warm1024: 1024x1024, alpha=2, kappa ~ U[0.02,0.3], 16 tracks (~6%), "
                         "sigma 0.05, FP32 to 1e-6; held-out seeds",
             "cold_seconds": cs, "warm_seconds": ws, "speedup": cs / ws if ws > 0 else None,
+            "multigrid_seconds": ms, "multigrid_speedup": cs / ms if ms > 0 else None,
             "instances": rows}
+
+
+def bench_multigrid(G, prob):
+    """Time to the problem's tolerance by coarse-to-fine multigrid (all levels
+    and transfers included)."""
+    from paper_2404_12968_amd import multigrid as MG
+    r = MG.multigrid_solve(prob)
+    return {"tol": prob.rel_tol, "status": G.gabp_status_string(r["status"]),
+            "seconds": r["seconds"], "fine_iterations": r["iterations"],
+            "rel_residual": r["rel"],
+            "levels": [{"nx": lv["nx"], "ny": lv["ny"], "iterations": lv["iterations"],
+                        "observations": lv["observations"]} for lv in r["levels"]]}
 
 
 def bench_batch(G, I, torch, dev, args):
@@ -175,6 +193,8 @@ def main(argv=None):
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
     ap.add_argument("--warm-instances", type=int, default=3)
+    ap.add_argument("--no-multigrid", action="store_true",
+                    help="skip the multigrid time-to-tolerance leg")
     ap.add_argument("--print-digest", action="store_true",
                     help="print the iteration kernels' source digest and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -320,13 +340,17 @@ def main(argv=None):
         ctx2 = G.gabp_create_problem(prob, device=dev)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        st, it, r = G.gabp_solve(ctx2, args.solve_max_iters, prob.damping, prob.rel_tol,
-                                 prob.check_every)
+        st, it, r = G.gabp_solve(ctx2, args.solve_max_iters, prob.damping, prob.rel_tol, -10)
         torch.cuda.synchronize()
         out["time_to_tol"] = {"tol": prob.rel_tol, "status": G.gabp_status_string(st),
                               "iterations": it, "seconds": time.perf_counter() - t1,
                               "rel_residual": r, "start": "cold"}
         del ctx2
+    if not args.no_multigrid:
+        out["multigrid"] = bench_multigrid(G, prob)
+        if "time_to_tol" in out:
+            out["multigrid"]["speedup_vs_cold"] = (out["time_to_tol"]["seconds"] /
+                                                   out["multigrid"]["seconds"])
     if not args.no_warm:
         out["warm_start"] = bench_warm(I, args.warm_instances)
     if not args.no_cpu_baseline:

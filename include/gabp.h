@@ -137,13 +137,17 @@ gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil,
  * synchronising call reports GABP_E_DIVERGED. */
 gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping);
 
-/* Iterate in chunks of check_every iterations until the FP64 relative
- * residual ||A mu - b||_2 / ||b||_2 of the posterior mean is <= rel_tol
- * (returns OK), max_iters total iterations were run (NOT_CONVERGED), or the
- * run diverged (DIVERGED: invalid cavity precision, non-finite values, or a
- * residual more than 1e3 times the first check's).  iters_done and
- * rel_residual (either may be NULL) receive the iteration count and the last
- * residual.  Synchronises the stream at every check. */
+/* Iterate in chunks until the FP64 relative residual ||A mu - b||_2 / ||b||_2
+ * of the posterior mean is <= rel_tol (returns OK), max_iters iterations
+ * were run by this call (NOT_CONVERGED), or the run diverged (DIVERGED:
+ * invalid cavity precision, non-finite values, or a residual more than 1e3
+ * times the first check's).  check_every > 0 checks every check_every
+ * iterations; check_every < 0 checks adaptively: every |check_every|
+ * iterations until the precision messages froze, then after half the
+ * iterations the observed geometric rate predicts to rel_tol (at least
+ * |check_every|, at most 2000).  iters_done (total iterations of the
+ * context) and rel_residual (last residual) may be NULL.  Synchronises the
+ * stream at every check. */
 gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double rel_tol,
                        int32_t check_every, int64_t *iters_done, double *rel_residual);
 
@@ -198,6 +202,17 @@ gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t
  * mu^_i + (b - A mu^)_i / Lam_i).  keep_precisions != 0 keeps the current
  * precision messages.  The iteration counter is kept.  Async. */
 gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precisions);
+
+/* Multigrid transfer (Alg. 2, Upscale Messages, read as initialising the
+ * finer grid's marginals to the coarser grid's): writes into channel 0 of a
+ * prediction pred [nyf][nxf][16] (FP32, other channels 0) the bilinear
+ * interpolation of a coarse mean coarse [nyc][nxc] (FP64) whose node (i, j)
+ * sits on fine node (2i, 2j); nxc = ceil(nxf/2), nyc = ceil(nyf/2); periodic
+ * axes wrap (and need even fine sizes).  Feed pred to gabp_warm_init with
+ * keep_precisions = 1.  Device arrays; async on `stream`; errors via
+ * gabp_last_error(NULL). */
+gabp_status gabp_upsample_mean(const double *coarse, int64_t nxc, int64_t nyc, int32_t bc_x,
+                               int32_t bc_y, float *pred, int64_t nxf, int64_t nyf, void *stream);
 
 /* Iteration at which the precision messages were found frozen, or -1. */
 gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at);

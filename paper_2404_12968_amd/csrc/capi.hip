@@ -398,13 +398,20 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
                        int32_t check_every, int64_t *iters_done, double *rel_residual) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;
-    if (max_iters < 0 || check_every < 1 || !(rel_tol >= 0))
-        return fail(ctx, GABP_E_INVALID, "need max_iters >= 0, check_every >= 1, rel_tol >= 0");
-    double rel = INFINITY, first = -1.0;
-    int64_t run = 0;
+    if (max_iters < 0 || check_every == 0 || !(rel_tol >= 0))
+        return fail(ctx, GABP_E_INVALID, "need max_iters >= 0, check_every != 0, rel_tol >= 0");
+    // check_every > 0: fixed interval.  check_every < 0: adaptive, at least
+    // |check_every| iterations apart; fixed until the precision messages
+    // froze, then half the iterations the observed geometric rate predicts
+    // to rel_tol, at most kMaxInterval.
+    constexpr int64_t kMaxInterval = 2000;
+    const bool adaptive = check_every < 0;
+    const int64_t kmin = adaptive ? -(int64_t)check_every : (int64_t)check_every;
+    double rel = INFINITY, first = -1.0, prev_rel = -1.0;
+    int64_t run = 0, prev_t = 0, next = kmin;
     st = GABP_E_NOT_CONVERGED;
     while (run < max_iters) {
-        const int32_t k = (int32_t)std::min<int64_t>(check_every, max_iters - run);
+        const int32_t k = (int32_t)std::min<int64_t>(next, max_iters - run);
         gabp_status s1 = gabp_iterate(ctx, k, damping);
         if (s1 != GABP_OK) {
             st = s1;
@@ -426,6 +433,14 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
             st = GABP_OK;
             break;
         }
+        next = kmin;
+        if (adaptive && ctx->frozen && prev_rel > 0 && rel < prev_rel && rel > 0) {
+            const double rate = std::log(rel / prev_rel) / (double)(ctx->iter - prev_t);
+            const double need = std::log(rel_tol / rel) / rate;   // iterations to rel_tol
+            next = std::max<int64_t>(kmin, std::min<int64_t>(kMaxInterval, (int64_t)(0.5 * need)));
+        }
+        prev_rel = rel;
+        prev_t = ctx->iter;
     }
     if (st == GABP_E_NOT_CONVERGED) {
         if (max_iters == 0) {
@@ -544,6 +559,21 @@ gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t
 gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at) {
     if (!ctx || !at) return GABP_E_INVALID;
     *at = ctx->frozen ? ctx->frozen_at : -1;
+    return GABP_OK;
+}
+
+gabp_status gabp_upsample_mean(const double *coarse, int64_t nxc, int64_t nyc, int32_t bc_x,
+                               int32_t bc_y, float *pred, int64_t nxf, int64_t nyf, void *stream) {
+    if (!coarse || !pred || nxc < 1 || nyc < 1 || nxf < 1 || nyf < 1 ||
+        (nxf + 1) / 2 != nxc || (nyf + 1) / 2 != nyc)
+        return fail(nullptr, GABP_E_INVALID,
+                    "upsample_mean: need nxc = ceil(nxf / 2) and nyc = ceil(nyf / 2)");
+    if ((bc_x == GABP_BC_PERIODIC && nxf != 2 * nxc) || (bc_y == GABP_BC_PERIODIC && nyf != 2 * nyc))
+        return fail(nullptr, GABP_E_INVALID, "upsample_mean: periodic axes need even fine sizes");
+    hipError_t e = gabp::launch_upsample_mean(coarse, (int)nxc, (int)nyc, bc_x == GABP_BC_PERIODIC,
+                                              bc_y == GABP_BC_PERIODIC, pred, (int)nxf, (int)nyf,
+                                              (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, GABP_E_DEVICE, hipGetErrorString(e));
     return GABP_OK;
 }
 

@@ -244,6 +244,30 @@ __global__ __launch_bounds__(256) void k_bits_differ(const T *__restrict__ a,
     if (diff) *flag = 1u;
 }
 
+// Multigrid transfer: coarse node (i, j) sits on fine node (2i, 2j); every
+// fine node takes the bilinear interpolation of the coarse mean (wrapping on
+// periodic axes, clamped at the end of others) into channel 0 of a
+// prediction [nyf][nxf][16] (other channels zero).
+__global__ __launch_bounds__(256) void k_upsample_mean(const double *__restrict__ coarse,
+                                                       int nxc, int nyc, int perx, int pery,
+                                                       float *__restrict__ pred, int nxf,
+                                                       int nyf) {
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long)nxf * nyf) return;
+    const int x = (int)(p % nxf), y = (int)(p / nxf);
+    const int i0 = x >> 1, j0 = y >> 1;
+    int i1 = i0 + (x & 1), j1 = j0 + (y & 1);
+    if (i1 >= nxc) i1 = perx ? i1 - nxc : nxc - 1;
+    if (j1 >= nyc) j1 = pery ? j1 - nyc : nyc - 1;
+    const int ia = min(i0, nxc - 1), ja = min(j0, nyc - 1);
+    const double v = 0.25 * (coarse[(long)ja * nxc + ia] + coarse[(long)ja * nxc + i1] +
+                             coarse[(long)j1 * nxc + ia] + coarse[(long)j1 * nxc + i1]);
+    float *o = pred + p * 16;
+    o[0] = (float)v;
+#pragma unroll
+    for (int k = 1; k < 16; ++k) o[k] = 0.0f;
+}
+
 // --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
@@ -334,6 +358,14 @@ hipError_t launch_setup(int dtype, const Lattice &L, int64_t nobs, const int64_t
     else
         hipLaunchKernelGGL((k_node_init<double>), grid, block, 0, s, L, adiag64, b64, prior_mean,
                            (double *)nullptr, (double *)nullptr, err_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_upsample_mean(const double *coarse, int nxc, int nyc, int perx, int pery,
+                                float *pred, int nxf, int nyf, hipStream_t s) {
+    const long n = (long)nxf * nyf;
+    hipLaunchKernelGGL(k_upsample_mean, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, coarse,
+                       nxc, nyc, perx, pery, pred, nxf, nyf);
     return hipGetLastError();
 }
 

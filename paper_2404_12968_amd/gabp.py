@@ -88,6 +88,8 @@ _SIGS = {
     "gabp_batch_destroy": ([_P], None),
     "gabp_batch_last_error": ([_P], ctypes.c_char_p),
     "gabp_warm_init": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "gabp_upsample_mean": ([_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                            _P, ctypes.c_int64, ctypes.c_int64, _P], ctypes.c_int),
     "gabp_conv3x3_fwd": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                           _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P],
                          ctypes.c_int),
@@ -510,3 +512,15 @@ def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
                                     _ptr(y) if y.numel() else None, int(nx), int(ny), float(kappa),
                                     _ptr(scratch), _ptr(x), _stream_handle(stream)))
     return x
+
+
+def gabp_upsample_mean(coarse: torch.Tensor, bc_x: int, bc_y: int, nxf: int, nyf: int,
+                       stream=None) -> torch.Tensor:
+    """Prediction [nyf, nxf, 16] FP32 whose channel 0 is the bilinear
+    upsampling of the coarse FP64 mean [nyc, nxc]."""
+    coarse = coarse.to(torch.float64).contiguous()
+    nyc, nxc = coarse.shape
+    pred = torch.empty((nyf, nxf, 16), dtype=torch.float32, device=coarse.device)
+    _check(_lib.gabp_upsample_mean(_ptr(coarse), int(nxc), int(nyc), int(bc_x), int(bc_y),
+                                   _ptr(pred), int(nxf), int(nyf), _stream_handle(stream)))
+    return pred

@@ -1,0 +1,134 @@
+"""Multigrid levels (CPU) and the multigrid transfer and solve (GPU)."""
+import numpy as np
+import pytest
+
+from paper_2404_12968_amd import inputs as I
+from paper_2404_12968_amd import multigrid as MG
+
+
+def test_level_problem_keeps_coinciding_observations_and_scales_the_prior():
+    p = I.small_lattice(40, 24, 2, bc_x=I.BC_PERIODIC, frac=0.3, seed=3, tau=1.5, hx=1.0, hy=1.0)
+    q = MG.level_problem(p, 2)
+    assert (q.nx, q.ny) == (10, 6) and q.hx == 4.0 and q.hy == 4.0 and q.tau == 1.5 * 16
+    cx, cy = p.cells % p.nx, p.cells // p.nx
+    sel = (cx % 4 == 0) & (cy % 4 == 0)
+    assert q.cells.size == sel.sum()
+    np.testing.assert_array_equal(q.y, p.y[sel])
+    np.testing.assert_array_equal(q.cells % q.nx, cx[sel] // 4)
+    np.testing.assert_array_equal(q.cells // q.nx, cy[sel] // 4)
+    assert MG.level_problem(p, 0) is p
+    with pytest.raises(ValueError):
+        MG.level_problem(I.small_lattice(42, 24, 2, bc_x=I.BC_PERIODIC, seed=1), 2)
+
+
+@pytest.mark.parametrize("alpha", [1, 2])
+def test_coarse_level_discretises_the_same_field_energy(alpha, oracle_mod):
+    """A smooth field has (to O(h^2)) the same prior energy f^T Q f on every
+    level: the sum over nodes approximates the integral divided by the cell
+    area, which the 4^l scaling of tau restores.  Leaving tau or h unscaled
+    misses by a factor of four or by tens of percent."""
+    nx, ny = 256, 128
+    p = I.small_lattice(nx, ny, alpha, bc_x=I.BC_PERIODIC, bc_y=I.BC_PERIODIC, kappa=0.3,
+                        tau=1.7, seed=1)
+
+    def f(X, Y):
+        return np.cos(2 * np.pi * X / nx + 0.3) * np.cos(2 * np.pi * Y / ny) + \
+            0.5 * np.sin(4 * np.pi * X / nx)
+
+    def energy(q):
+        Q = oracle_mod.precision(q.nx, q.ny, alpha, q.kappa, q.tau, q.hx, q.hy, q.bc_x, q.bc_y)
+        step = p.nx // q.nx
+        X, Y = np.meshgrid(np.arange(q.nx) * step, np.arange(q.ny) * step)
+        v = f(X, Y).ravel()
+        return v @ (Q @ v)
+
+    fine = energy(p)
+    for lev in (1, 2):
+        assert abs(energy(MG.level_problem(p, lev)) / fine - 1.0) < 1e-3
+
+
+def test_max_levels():
+    p = I.small_lattice(256, 128, 2, seed=0)
+    assert MG.max_levels(p, coarsest=32) == 3     # 128 -> 64 -> 32
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nxf,nyf,bcx,bcy", [(9, 6, I.BC_NEUMANN, I.BC_NEUMANN),
+                                             (8, 7, I.BC_PERIODIC, I.BC_NEUMANN),
+                                             (10, 8, I.BC_PERIODIC, I.BC_PERIODIC)])
+def test_upsample_matches_bilinear(nxf, nyf, bcx, bcy):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp as G
+    nxc, nyc = (nxf + 1) // 2, (nyf + 1) // 2
+    c = np.random.default_rng(0).normal(size=(nyc, nxc))
+    got = G.gabp_upsample_mean(torch.tensor(c, device="cuda"), bcx, bcy, nxf, nyf).cpu().numpy()
+    ref = np.zeros((nyf, nxf))
+    for y in range(nyf):
+        for x in range(nxf):
+            i0, j0 = x // 2, y // 2
+            i1, j1 = i0 + x % 2, j0 + y % 2
+            i1 = i1 % nxc if bcx == I.BC_PERIODIC else min(i1, nxc - 1)
+            j1 = j1 % nyc if bcy == I.BC_PERIODIC else min(j1, nyc - 1)
+            ref[y, x] = 0.25 * (c[j0, i0] + c[j0, i1] + c[j1, i0] + c[j1, i1])
+    np.testing.assert_allclose(got[:, :, 0], ref.astype(np.float32), rtol=1e-6, atol=1e-7)
+    assert np.all(got[:, :, 1:] == 0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bcx", [I.BC_NEUMANN, I.BC_PERIODIC])
+def test_multigrid_reaches_the_direct_solve(bcx, oracle_mod):
+    """Three levels to 1e-10 on a 128 x 96 lattice (prior range about nine
+    cells, so the cold solve needs tens of thousands of iterations): the result
+    is the direct solve's mean, and the warm-started fine level needs fewer
+    iterations than a cold solve of the same problem."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp as G
+    p = I.small_lattice(128, 96, 2, bc_x=bcx, kappa=0.3, tracks=4, run=3, sigma=0.05, seed=11,
+                        dtype="f64")
+    p.rel_tol = 1e-10
+    res = MG.multigrid_solve(p, 3, coarse_tol=1e-4, max_iters=100000, keep_context=True)
+    assert res["status"] == G.GABP_OK, res["levels"]
+    assert [lv["level"] for lv in res["levels"]] == [2, 1, 0]
+    # The residual on the oracle's own system meets the tolerance, and the
+    # error obeys |x - x*| / |x*| <= cond(A) |b - A x| / |b| (cond is about 5e4).
+    import scipy.sparse.linalg as sla
+    A, b = oracle_mod.posterior_system(p)
+    exact = oracle_mod.direct_solve(A, b)
+    mu = G.gabp_posterior(res["ctx"], want_var=False)[0].cpu().numpy().ravel()
+    rel = np.linalg.norm(b - A @ mu) / np.linalg.norm(b)
+    assert rel <= 1.01e-10
+    lmax = sla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = sla.eigsh(A, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+    err = np.linalg.norm(mu - exact) / np.linalg.norm(exact)
+    assert err <= (lmax / lmin) * rel
+    G.gabp_destroy(res["ctx"])
+    cold = G.gabp_create_problem(p)
+    st, cold_iters, _ = G.gabp_solve(cold, 100000, p.damping, p.rel_tol, -10)
+    G.gabp_destroy(cold)
+    assert st == G.GABP_OK
+    assert res["iterations"] < cold_iters
+
+
+@pytest.mark.gpu
+def test_multigrid_paper_early_stop_rule():
+    """Coarse levels stopped by the message-change rule of Appendix A (mean
+    |m^t - m^(t-1)| below 1e-3 of the level's first change); the fine level
+    still reaches its residual tolerance."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp as G
+    p = I.small_lattice(128, 96, 2, kappa=0.3, tracks=4, run=3, sigma=0.05, seed=12,
+                        dtype="f32")
+    p.rel_tol = 1e-6
+    res = MG.multigrid_solve(p, 3, coarse_stop="message_change", max_iters=100000)
+    assert res["status"] == G.GABP_OK, res["levels"]
+    for lv in res["levels"][:-1]:
+        assert lv["status"] == G.GABP_OK and lv["rel"] < 1e-3
+    assert res["levels"][-1]["rel"] <= 1e-6
+    with pytest.raises(ValueError):
+        MG.multigrid_solve(p, 2, coarse_stop="bogus")
