@@ -214,6 +214,24 @@ gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precis
 gabp_status gabp_upsample_mean(const double *coarse, int64_t nxc, int64_t nyc, int32_t bc_x,
                                int32_t bc_y, float *pred, int64_t nxf, int64_t nyf, void *stream);
 
+/* Multigrid transfer of the precision messages (Alg. 2, Upscale Messages:
+ * the finer grid's edge values start from the coarser grid's).  For every
+ * node (x, y) of a fine grid nxf x nyf with ceil(nxf/2) x ceil(nyf/2) = the
+ * coarse context's grid, writes channels 1..deg of pred [nyf][nxf][16]
+ * (FP32, device) with log(scale * -Lam) of the coarse context's current
+ * precision message from node (x/2, y/2) in the same direction (the opposite
+ * direction where the coarse node has none in that direction; -inf, a zero
+ * message, where it has neither).  Channel 0 and the channels past deg are
+ * not written: fill channel 0 with gabp_upsample_mean first, then pass pred
+ * to the fine context's gabp_warm_init with keep_precisions = 0.  The paper
+ * gives no rescaling between levels; halving h with tau scaled by 4 scales
+ * the prior's off-diagonal entries by 4^(1-alpha), so scale = 4^(alpha-1)
+ * brings the coarse messages to the fine scale.  Async on the coarse
+ * context's stream; INVALID on a size mismatch, a NULL pred or a scale that
+ * is not finite and positive. */
+gabp_status gabp_upscale_precisions(gabp_ctx *coarse, float *pred, int64_t nxf, int64_t nyf,
+                                    double scale);
+
 /* Iteration at which the precision messages were found frozen, or -1. */
 gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at);
 

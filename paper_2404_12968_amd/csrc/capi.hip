@@ -577,6 +577,23 @@ gabp_status gabp_upsample_mean(const double *coarse, int64_t nxc, int64_t nyc, i
     return GABP_OK;
 }
 
+gabp_status gabp_upscale_precisions(gabp_ctx *coarse, float *pred, int64_t nxf, int64_t nyf,
+                                    double scale) {
+    gabp_status st = ctx_ok(coarse);
+    if (st != GABP_OK) return st;
+    if (!pred) return fail(coarse, GABP_E_INVALID, "pred is NULL");
+    if (nxf < 1 || nyf < 1 || (nxf + 1) / 2 != coarse->L.nx || (nyf + 1) / 2 != coarse->L.ny)
+        return fail(coarse, GABP_E_INVALID,
+                    "upscale_precisions: need ceil(nxf / 2) = nx and ceil(nyf / 2) = ny of the "
+                    "coarse context");
+    if (!(scale > 0.0) || !std::isfinite(scale))
+        return fail(coarse, GABP_E_INVALID, "upscale_precisions: scale must be finite and > 0");
+    GABP_HIP(coarse, gabp::launch_upscale_prec(coarse->dtype == GABP_F32 ? 0 : 1, coarse->L,
+                                               cur_msgs(coarse), (float)scale, pred, (int)nxf,
+                                               (int)nyf, coarse->stream));
+    return GABP_OK;
+}
+
 gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precisions) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;

@@ -40,6 +40,8 @@ hipError_t launch_setup(int dtype, const Lattice &L, int64_t nobs, const int64_t
                         double *b64, const double *prior_mean, void *adiag_w, void *b_w,
                         uint32_t *err_flag, hipStream_t s);
 // Multigrid: bilinear upsampling of a coarse mean into a prediction.
+hipError_t launch_upscale_prec(int dtype, const Lattice &Lc, const void *m, float scale,
+                               float *pred, int nxf, int nyf, hipStream_t s);
 hipError_t launch_upsample_mean(const double *coarse, int nxc, int nyc, int perx, int pery,
                                 float *pred, int nxf, int nyf, hipStream_t s);
 // Message initialisation from a network prediction (net.hip).

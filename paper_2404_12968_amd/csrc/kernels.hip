@@ -268,6 +268,38 @@ __global__ __launch_bounds__(256) void k_upsample_mean(const double *__restrict_
     for (int k = 1; k < 16; ++k) o[k] = 0.0f;
 }
 
+// Multigrid transfer of the precision messages: fine node (x, y) is covered
+// by coarse node (x/2, y/2) (clamped at the end of an axis); channel 1 + d of
+// the prediction gets log(scale * -Lam) of the coarse sender-indexed precision
+// message in direction d, or in the opposite direction where the coarse node
+// has no neighbour in direction d, or -inf (a zero message) where it has
+// neither.  Channel 0 and channels past the stencil are left untouched.
+template <typename T, int ALPHA>
+__global__ __launch_bounds__(256) void k_upscale_prec(Lattice Lc, const T *__restrict__ m,
+                                                      float scale, float *__restrict__ pred,
+                                                      int nxf, int nyf) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long)nxf * nyf) return;
+    const int x = (int)(p % nxf), y = (int)(p / nxf);
+    const int xc = min(x >> 1, Lc.nx - 1), yc = min(y >> 1, Lc.ny - 1);
+    const size_t ic = (size_t)yc * Lc.pitch + xc;
+    float *o = pred + p * 16 + 1;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        int xn, yn;
+        int src = -1;
+        if (neighbour(Lc, xc, yc, d, xn, yn)) src = d;
+        else if (neighbour(Lc, xc, yc, d ^ 1, xn, yn)) src = d ^ 1;
+        float v = -INFINITY;
+        if (src >= 0) {
+            const float lam = -(float)(m + (size_t)src * Lc.plane)[ic];
+            if (lam > 0.0f) v = logf(scale * lam);
+        }
+        o[d] = v;
+    }
+}
+
 // --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
@@ -366,6 +398,24 @@ hipError_t launch_upsample_mean(const double *coarse, int nxc, int nyc, int perx
     const long n = (long)nxf * nyf;
     hipLaunchKernelGGL(k_upsample_mean, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, coarse,
                        nxc, nyc, perx, pery, pred, nxf, nyf);
+    return hipGetLastError();
+}
+
+hipError_t launch_upscale_prec(int dtype, const Lattice &Lc, const void *m, float scale,
+                               float *pred, int nxf, int nyf, hipStream_t s) {
+    const long n = (long)nxf * nyf;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (dtype == 0) {
+        if (Lc.alpha == 1)
+            hipLaunchKernelGGL((k_upscale_prec<float, 1>), grid, block, 0, s, Lc, (const float *)m, scale, pred, nxf, nyf);
+        else
+            hipLaunchKernelGGL((k_upscale_prec<float, 2>), grid, block, 0, s, Lc, (const float *)m, scale, pred, nxf, nyf);
+    } else {
+        if (Lc.alpha == 1)
+            hipLaunchKernelGGL((k_upscale_prec<double, 1>), grid, block, 0, s, Lc, (const double *)m, scale, pred, nxf, nyf);
+        else
+            hipLaunchKernelGGL((k_upscale_prec<double, 2>), grid, block, 0, s, Lc, (const double *)m, scale, pred, nxf, nyf);
+    }
     return hipGetLastError();
 }
 

@@ -88,6 +88,8 @@ _SIGS = {
     "gabp_batch_destroy": ([_P], None),
     "gabp_batch_last_error": ([_P], ctypes.c_char_p),
     "gabp_warm_init": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
+                                ctypes.c_int),
     "gabp_upsample_mean": ([_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                             _P, ctypes.c_int64, ctypes.c_int64, _P], ctypes.c_int),
     "gabp_conv3x3_fwd": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
@@ -512,6 +514,17 @@ def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
                                     _ptr(y) if y.numel() else None, int(nx), int(ny), float(kappa),
                                     _ptr(scratch), _ptr(x), _stream_handle(stream)))
     return x
+
+
+def gabp_upscale_precisions(coarse_ctx: Context, pred: torch.Tensor, scale: float) -> None:
+    """Write channels 1..deg of a fine prediction [nyf, nxf, 16] (FP32) from
+    the coarse context's precision messages, multiplied by `scale`."""
+    if pred.dtype != torch.float32 or pred.dim() != 3 or pred.shape[2] != 16 or \
+            not pred.is_contiguous():
+        raise ValueError("pred must be a contiguous float32 [nyf, nxf, 16] tensor")
+    nyf, nxf, _ = pred.shape
+    _check(_lib.gabp_upscale_precisions(coarse_ctx.handle, _ptr(pred), int(nxf), int(nyf),
+                                        float(scale)), coarse_ctx)
 
 
 def gabp_upsample_mean(coarse: torch.Tensor, bc_x: int, bc_y: int, nxf: int, nyf: int,

@@ -9,9 +9,12 @@ iterated until its FP64 relative residual reaches a tolerance; the next finer
 level starts from the coarse posterior mean, upsampled bilinearly
 (`gabp_upsample_mean`) and installed with `gabp_warm_init` -- the paper's
 "Upscale Messages", read as initialising the finer grid's marginals to the
-coarser grid's, which it states the message copy is equivalent to.  The
-precision messages start cold on every level (they converge in tens of
-iterations).  A coarse level stops either at an FP64 relative residual
+coarser grid's, which it states the message copy is equivalent to.  With
+`transfer="messages"` (the default) the precision messages are carried over
+too, from the covering coarse node in the same direction, scaled by
+4^(alpha-1) (`gabp_upscale_precisions`: the prior's off-diagonal entries
+shrink by that factor per level); with `transfer="mean"` they start cold on
+every level.  A coarse level stops either at an FP64 relative residual
 (`coarse_stop="residual"`) or by the paper's early-stop rule of Appendix A
 (`"message_change"`: mean |m^t - m^(t-1)| below `coarse_tol` times the
 level's mean |m^2 - m^1|; the paper takes 1e-3).  The last level is solved to
@@ -61,35 +64,42 @@ def max_levels(prob: I.Problem, coarsest: int = 32) -> int:
         L += 1
 
 
-def _iters(ctx) -> int:
-    return G.gabp_iteration_count(ctx)[0]
-
-
 def _until_messages_settle(ctx, damping: float, tau: float, max_iters: int, every: int):
     """Early stop of Appendix A: iterate until the mean absolute message
     change falls below tau times that of the level's first two iterations."""
     ratio = float("inf")
-    while _iters(ctx) < max_iters:
-        G.gabp_iterate(ctx, min(every, max_iters - _iters(ctx)), damping)
-        if _iters(ctx) >= 3:
+    it, st = G.gabp_iteration_count(ctx)
+    while it < max_iters:
+        G.gabp_iterate(ctx, min(every, max_iters - it), damping)
+        it, st = G.gabp_iteration_count(ctx)
+        if st == G.GABP_E_DIVERGED:
+            return st, it, ratio
+        if it >= 3:
             ratio = G.gabp_message_change(ctx)
             if ratio < tau:
-                return G.GABP_OK, _iters(ctx), ratio
-    return G.GABP_E_NOT_CONVERGED, _iters(ctx), ratio
+                return G.GABP_OK, it, ratio
+    return G.GABP_E_NOT_CONVERGED, it, ratio
 
 
 def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
                     coarse_tol: Optional[float] = None, max_iters: int = 300000,
                     check_every: int = -10, device="cuda", keep_context: bool = False,
-                    coarse_stop: str = "residual"):
+                    coarse_stop: str = "residual", final_stop: str = "residual",
+                    final_tol: Optional[float] = None, transfer: str = "messages"):
     """Solve coarse-to-fine.  `levels` defaults to halving down to a 32-node
     short side (the paper's base grid); `coarse_tol` defaults to the problem's
-    own residual tolerance (1e-3 for the message-change rule).  Returns a dict
+    own residual tolerance (1e-3 for the message-change rule).  The target
+    level stops at the problem's residual tolerance, or with
+    `final_stop="message_change"` by the early-stop rule at `final_tol`
+    (default 1e-3), the paper's own setting.  Returns a dict
     with the final status, the iterations per level (coarsest first), the
     fine-level iterations, the total seconds, and (keep_context) the fine
     context."""
-    if coarse_stop not in ("residual", "message_change"):
-        raise ValueError("coarse_stop is 'residual' or 'message_change'")
+    if coarse_stop not in ("residual", "message_change") or \
+            final_stop not in ("residual", "message_change"):
+        raise ValueError("coarse_stop and final_stop are 'residual' or 'message_change'")
+    if transfer not in ("messages", "mean"):
+        raise ValueError("transfer is 'messages' or 'mean'")
     if levels is None:
         levels = max_levels(prob, coarsest=32)
     if coarse_tol is None:
@@ -105,9 +115,15 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
         p = level_problem(prob, lev)
         ctx = G.gabp_create_problem(p, device=device)
         if pred is not None:
-            G.gabp_warm_init(ctx, pred, keep_precisions=True)
-        if lev == 0:
-            st, it, rel = G.gabp_solve(ctx, max_iters, p.damping, prob.rel_tol, check_every)
+            G.gabp_warm_init(ctx, pred, keep_precisions=(transfer == "mean"))
+        if lev == 0 and final_stop == "message_change":
+            st, it, rel = _until_messages_settle(ctx, p.damping,
+                                                 1e-3 if final_tol is None else final_tol,
+                                                 max_iters, abs(check_every))
+        elif lev == 0:
+            st, it, rel = G.gabp_solve(ctx, max_iters, p.damping,
+                                       prob.rel_tol if final_tol is None else final_tol,
+                                       check_every)
         elif coarse_stop == "residual":
             st, it, rel = G.gabp_solve(ctx, max_iters, p.damping, max(coarse_tol, prob.rel_tol),
                                        check_every)
@@ -122,6 +138,8 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
             mean, _ = G.gabp_posterior(ctx, want_var=False)
             fine = level_problem(prob, lev - 1)
             pred = G.gabp_upsample_mean(mean, p.bc_x, p.bc_y, fine.nx, fine.ny)
+            if transfer == "messages":
+                G.gabp_upscale_precisions(ctx, pred, 4.0 ** (prob.alpha - 1))
             G.gabp_destroy(ctx)
     torch.cuda.synchronize()
     out = {"status": st, "levels": per_level, "iterations": per_level[-1]["iterations"],

@@ -77,8 +77,60 @@ def test_upsample_matches_bilinear(nxf, nyf, bcx, bcy):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("bcx", [I.BC_NEUMANN, I.BC_PERIODIC])
-def test_multigrid_reaches_the_direct_solve(bcx, oracle_mod):
+@pytest.mark.parametrize("alpha,bcx,nxf,nyf", [(2, I.BC_NEUMANN, 23, 18), (2, I.BC_PERIODIC, 24, 17),
+                                               (1, I.BC_DIRICHLET, 21, 20)])
+def test_upscale_precisions_copies_the_covering_coarse_message(alpha, bcx, nxf, nyf):
+    """Channel 1 + d of the fine prediction is log(scale * -Lam) of the coarse
+    node (x/2, y/2)'s outgoing precision message in direction d (the opposite
+    direction at a coarse boundary), read here through the receiver-indexed
+    checkpoint layout."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp as G
+    from conftest import DIRS
+    nxc, nyc = (nxf + 1) // 2, (nyf + 1) // 2
+    p = I.small_lattice(nxc, nyc, alpha, bc_x=bcx, frac=0.2, seed=5, dtype="f32")
+    ctx = G.gabp_create_problem(p)
+    G.gabp_iterate(ctx, 25, 0.5)
+    prec = G.gabp_get_messages(ctx)[0].cpu().numpy()          # [d][y][x] into (x, y)
+    pred = torch.full((nyf, nxf, 16), 7.0, dtype=torch.float32, device="cuda")
+    G.gabp_upscale_precisions(ctx, pred, 4.0)
+    got = pred.cpu().numpy()
+    G.gabp_destroy(ctx)
+    px = bcx == I.BC_PERIODIC
+
+    def inside(x, y):
+        if px:
+            x %= nxc
+        elif not 0 <= x < nxc:
+            return None
+        return (x, y) if 0 <= y < nyc else None
+
+    deg = 4 if alpha == 1 else 12
+    for y in range(nyf):
+        for x in range(nxf):
+            xc, yc = min(x // 2, nxc - 1), min(y // 2, nyc - 1)
+            for d in range(deg):
+                dx, dy = DIRS[d]
+                fwd, back = inside(xc + dx, yc + dy), inside(xc - dx, yc - dy)
+                if fwd is not None:       # message (xc,yc) -> fwd sits in plane d^1 at fwd
+                    lam = -prec[d ^ 1, fwd[1], fwd[0]]
+                elif back is not None:    # message (xc,yc) -> back sits in plane d at back
+                    lam = -prec[d, back[1], back[0]]
+                else:
+                    lam = 0.0
+                want = np.log(np.float32(4.0) * np.float32(lam)) if lam > 0 else -np.inf
+                assert np.isclose(got[y, x, 1 + d], want, rtol=1e-6, atol=1e-6), (x, y, d)
+            assert np.all(got[y, x, 1 + deg:] == 7.0) and got[y, x, 0] == 7.0
+    with pytest.raises(G.GabpError):
+        G.gabp_upscale_precisions(G.gabp_create_problem(p), pred[:, :-3].contiguous(), 4.0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bcx,transfer", [(I.BC_NEUMANN, "messages"), (I.BC_PERIODIC, "messages"),
+                                          (I.BC_NEUMANN, "mean")])
+def test_multigrid_reaches_the_direct_solve(bcx, transfer, oracle_mod):
     """Three levels to 1e-10 on a 128 x 96 lattice (prior range about nine
     cells, so the cold solve needs tens of thousands of iterations): the result
     is the direct solve's mean, and the warm-started fine level needs fewer
@@ -90,7 +142,8 @@ def test_multigrid_reaches_the_direct_solve(bcx, oracle_mod):
     p = I.small_lattice(128, 96, 2, bc_x=bcx, kappa=0.3, tracks=4, run=3, sigma=0.05, seed=11,
                         dtype="f64")
     p.rel_tol = 1e-10
-    res = MG.multigrid_solve(p, 3, coarse_tol=1e-4, max_iters=100000, keep_context=True)
+    res = MG.multigrid_solve(p, 3, coarse_tol=1e-4, max_iters=100000, keep_context=True,
+                             transfer=transfer)
     assert res["status"] == G.GABP_OK, res["levels"]
     assert [lv["level"] for lv in res["levels"]] == [2, 1, 0]
     # The residual on the oracle's own system meets the tolerance, and the
