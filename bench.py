@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "edge-message updates/s + HBM GB/s; time to 1e-6 rel. residual, warm vs cold"
 ITERS_PER_STEP = 10
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_iter_global8192_traffic.md")
-PHASE_KERNEL = {"full": "k_iter_direct", "theta": "k_iter_theta"}
+PHASE_KERNEL = {"full": "k_iter_direct", "theta": "k_iter_theta", "theta2": "k_iter_theta2"}
 
 
 def edge_count(nx, ny, alpha, bcx, bcy):
@@ -59,7 +59,8 @@ def measured_traffic(phase, rpt):
         return None
     text = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
-    key = f"{PHASE_KERNEL[phase]}_rpt{rpt}_traffic_bytes_per_launch"
+    shape = f"pair{rpt}" if phase == "theta2" else f"rpt{rpt}"
+    key = f"{PHASE_KERNEL[phase]}_{shape}_traffic_bytes_per_launch"
     t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_source_digest():
         return None
@@ -361,18 +362,60 @@ def main(argv=None):
         step()
     frozen_at = G.gabp_precision_frozen(ctx)
     phase = "theta" if frozen_at >= 0 else "full"
-    alg_bytes = alg_theta if phase == "theta" else alg_full
     rpt = G.gabp_autotune(ctx, 3, prob.damping) if phase == "theta" else rpt_full
+    pair = G.gabp_get_tile(ctx)[1] if phase == "theta" else 0
+
+    def event_ms(fn, reps):
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b_ in ev:
+            a.record(stream)
+            fn()
+            b_.record(stream)
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b_) for a, b_ in ev) / reps
+
+    if phase == "theta":
+        # single-iteration information kernel, then the two-iteration kernel:
+        # a call of 2m+1 iterations is m pair launches and one single launch
+        G.gabp_set_tile(ctx, rpt, 0)
+        ms1 = event_ms(lambda: G.gabp_iterate(ctx, ITERS_PER_STEP, prob.damping), 3) / ITERS_PER_STEP
+        kernels["theta"] = {"iter_ms": ms1, "algorithmic_bytes": alg_theta,
+                            "gbps": alg_theta / (ms1 * 1e-3) / 1e9, "rows_per_thread": rpt}
+        for p2 in ((4, 8, 16) if prob.dtype == "f32" else (4,)):
+            G.gabp_set_tile(ctx, rpt, p2)
+            m = 10
+            ms_call = event_ms(lambda: G.gabp_iterate(ctx, 2 * m + 1, prob.damping), 3)
+            ms2 = (ms_call - ms1) / m
+            kernels[f"theta_pair{p2}"] = {
+                "launch_ms": ms2, "iters_per_launch": 2,
+                "algorithmic_bytes": 2 * alg_theta,
+                "gbps": 2 * alg_theta / (ms2 * 1e-3) / 1e9, "pair_rows": p2}
+        G.gabp_set_tile(ctx, rpt, pair)
     for _ in range(args.warmup):
         step()
     wall, iter_ms, rel = timed(args.steps)
-    kernels[phase] = {"iter_ms": iter_ms, "algorithmic_bytes": alg_bytes,
-                      "gbps": alg_bytes / (iter_ms * 1e-3) / 1e9, "rows_per_thread": rpt}
+    if phase == "full":
+        kernels["full_timed"] = {"iter_ms": iter_ms}
     total_iters = args.steps * ITERS_PER_STEP
     value = E * total_iters / wall
-    achieved = alg_bytes / (iter_ms * 1e-3) / 1e9
-    traffic = measured_traffic(phase, rpt)
-    kname = "k_iter_theta" if phase == "theta" else "k_iter_direct"
+    if phase == "theta" and pair > 0:
+        kname = "k_iter_theta2"
+        launch_ms = kernels[f"theta_pair{pair}"]["launch_ms"]
+        alg_launch = 2 * alg_theta
+        traffic = measured_traffic("theta2", pair)
+    elif phase == "theta":
+        kname = "k_iter_theta"
+        launch_ms = kernels["theta"]["iter_ms"]
+        alg_launch = alg_theta
+        traffic = measured_traffic("theta", rpt)
+    else:
+        kname = "k_iter_direct"
+        launch_ms = kernels["full"]["iter_ms"]
+        alg_launch = alg_full
+        traffic = measured_traffic("full", rpt)
+    achieved = alg_launch / (launch_ms * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -397,11 +440,12 @@ def main(argv=None):
         "iter_ms": iter_ms,
         "rel_residual_after": rel,
         "timed_phase": {"kernel": kname, "precision_frozen_at_iteration": frozen_at,
+                        "rows_per_thread": rpt, "pair_rows": pair,
                         "iterations_before_timing": G.gabp_iteration_count(ctx)[0] - total_iters},
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "launch_ms": launch_ms, "algorithmic_bytes_per_launch": alg_launch,
                      "traffic": traffic},
     }
     if args.solve:

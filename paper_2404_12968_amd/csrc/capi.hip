@@ -56,6 +56,8 @@ struct gabp_ctx {
                                    // [2] precision messages changed in the last iteration
     HostMirror *host = nullptr;    // pinned
     int rpt = 4;                   // rows per thread of the iteration kernel's tile
+    int pair = 0;                  // tile height of the two-iteration kernel, 0 = unused
+    int cur = 0;                   // buffer holding the current messages m^iter
     int64_t iter = 0;
     bool diverged = false;
     bool prev_valid = false;       // the other buffer holds m^{iter-1}
@@ -110,11 +112,16 @@ gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
     return GABP_OK;
 }
 
-const void *cur_msgs(const gabp_ctx *ctx) { return ctx->msg[ctx->iter & 1]; }
+const void *cur_msgs(const gabp_ctx *ctx) { return ctx->msg[ctx->cur]; }
 
-// Autotuner results, process-wide, keyed by (alpha, dtype, size class).
+// Autotuner results (rows per thread, pair tile height), process-wide,
+// keyed by (alpha, dtype, size class).
 std::mutex g_tune_mu;
-std::map<long long, int> g_tune;
+std::map<long long, std::pair<int, int>> g_tune;
+
+bool pair_ok(int dtype, int pair) {
+    return pair == 0 || pair == 4 || ((pair == 8 || pair == 16) && dtype == GABP_F32);
+}
 
 long long tune_key(const gabp_ctx *ctx) {
     const long long n = (long long)ctx->L.nx * ctx->L.ny;
@@ -313,7 +320,12 @@ gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil, cons
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(tune_key(ctx));
-        if (it != g_tune.end()) ctx->rpt = it->second;
+        if (it != g_tune.end()) {
+            ctx->rpt = it->second.first;
+            ctx->pair = it->second.second;
+        } else {
+            ctx->pair = dtype == GABP_F32 ? 8 : 4;
+        }
     }
     *out = ctx;
     return GABP_OK;
@@ -338,17 +350,33 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
     if (ctx->iter + n_iters >= (int64_t)UINT32_MAX)
         return fail(ctx, GABP_E_INVALID, "iteration counter overflow");
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
-    for (int32_t k = 0; k < n_iters; ++k) {
+    int32_t k = 0;
+    while (k < n_iters) {
+        const void *src = ctx->msg[ctx->cur];
+        void *dst = ctx->msg[ctx->cur ^ 1];
+        if (ctx->frozen && ctx->pair > 0 && ctx->iter >= 2 && n_iters - k >= 3) {
+            // two iterations per launch; the last one or two iterations of a
+            // call run singly so that the buffers end on m^{t-1} and m^t
+            GABP_HIP(ctx, gabp::launch_iter_theta2(dt, ctx->pair, ctx->L, src, dst, ctx->gain,
+                                                   ctx->b_w, damping, ctx->flags,
+                                                   (uint32_t)ctx->iter, ctx->stream));
+            ctx->iter += 2;
+            k += 2;
+            ctx->cur ^= 1;
+            continue;
+        }
         const int64_t t = ctx->iter + 1;
         if (ctx->frozen)
-            GABP_HIP(ctx, gabp::launch_iter_theta(dt, ctx->rpt, ctx->L, ctx->msg[(t - 1) & 1],
-                                                  ctx->msg[t & 1], ctx->gain, ctx->b_w, damping,
-                                                  ctx->flags, (uint32_t)t, ctx->stream));
+            GABP_HIP(ctx, gabp::launch_iter_theta(dt, ctx->rpt, ctx->L, src, dst, ctx->gain,
+                                                  ctx->b_w, damping, ctx->flags, (uint32_t)t,
+                                                  ctx->stream));
         else
-            GABP_HIP(ctx, gabp::launch_iter(dt, ctx->rpt, ctx->L, ctx->msg[(t - 1) & 1],
-                                            ctx->msg[t & 1], ctx->adiag_w, ctx->b_w, damping,
-                                            ctx->flags, (uint32_t)t, ctx->stream));
+            GABP_HIP(ctx, gabp::launch_iter(dt, ctx->rpt, ctx->L, src, dst, ctx->adiag_w,
+                                            ctx->b_w, damping, ctx->flags, (uint32_t)t,
+                                            ctx->stream));
         ctx->iter = t;
+        ctx->cur ^= 1;
+        ++k;
         if (t == 2) {
             const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
             GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[0], ctx->msg[1], n, ctx->partials,
@@ -369,8 +397,8 @@ gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_resid
     const bool probe = !ctx->frozen && ctx->prev_valid && ctx->iter >= 2;
     if (probe) {
         GABP_HIP(ctx, hipMemsetAsync(ctx->flags + 2, 0, sizeof(uint32_t), ctx->stream));
-        GABP_HIP(ctx, gabp::launch_bits_differ(dt, ctx->msg[ctx->iter & 1],
-                                               ctx->msg[(ctx->iter - 1) & 1],
+        GABP_HIP(ctx, gabp::launch_bits_differ(dt, ctx->msg[ctx->cur],
+                                               ctx->msg[ctx->cur ^ 1],
                                                (int64_t)ctx->L.deg * ctx->L.plane, ctx->flags + 2,
                                                ctx->stream));
     }
@@ -474,7 +502,7 @@ gabp_status gabp_message_change(gabp_ctx *ctx, double *ratio) {
         return fail(ctx, GABP_E_INVALID, "needs two consecutive iterations past t = 2");
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
     const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
-    GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[ctx->iter & 1], ctx->msg[(ctx->iter - 1) & 1],
+    GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[ctx->cur], ctx->msg[ctx->cur ^ 1],
                                           n, ctx->partials, kNumPartials, ctx->red + 2, ctx->stream));
     st = sync_flags(ctx, true);
     if (st != GABP_OK) return st;
@@ -496,7 +524,7 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
     if (st != GABP_OK) return st;
     if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
     GABP_HIP(ctx, gabp::launch_msgs_set(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L,
-                                        ctx->msg[ctx->iter & 1], prec, info, ctx->stream));
+                                        ctx->msg[ctx->cur], prec, info, ctx->stream));
     ctx->prev_valid = false;
     ctx->frozen = false;
     ctx->frozen_at = -1;
@@ -513,47 +541,89 @@ gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t
         (void)hipEventDestroy(ev[0]);
         return fail(ctx, GABP_E_DEVICE, "hipEventCreate failed");
     }
-    float best_ms = INFINITY;
-    int best = ctx->rpt;
-    const int saved = ctx->rpt;
-    // one untimed iteration first, then two timed passes over the shapes;
-    // the best time of a shape over both passes counts
-    st = gabp_iterate(ctx, 1, damping);
-    if (st != GABP_OK) {
+    const int saved_rpt = ctx->rpt, saved_pair = ctx->pair;
+    auto finish = [&](gabp_status s1) {
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);
-        return st;
-    }
-    for (int pass = 0; pass < 2; ++pass)
-    for (int rpt : gabp::kRptChoices) {
+        return s1;
+    };
+    // time `trials` iterations with one tile configuration
+    auto timed = [&](int rpt, int pair, float &ms) {
         ctx->rpt = rpt;
+        ctx->pair = pair;
         gabp_status s1 = GABP_OK;
         if (hipEventRecord(ev[0], ctx->stream) != hipSuccess) s1 = GABP_E_DEVICE;
         if (s1 == GABP_OK) s1 = gabp_iterate(ctx, trials, damping);
         if (s1 == GABP_OK && hipEventRecord(ev[1], ctx->stream) != hipSuccess) s1 = GABP_E_DEVICE;
         if (s1 == GABP_OK && hipEventSynchronize(ev[1]) != hipSuccess) s1 = GABP_E_DEVICE;
-        float ms = 0.f;
-        if (s1 == GABP_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) s1 = GABP_E_DEVICE;
+        ms = 0.f;
+        if (s1 == GABP_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+            s1 = GABP_E_DEVICE;
         if (s1 != GABP_OK) {
-            ctx->rpt = saved;
-            (void)hipEventDestroy(ev[0]);
-            (void)hipEventDestroy(ev[1]);
-            return s1 == GABP_E_DEVICE ? fail(ctx, s1, "autotune timing failed") : s1;
+            ctx->rpt = saved_rpt;
+            ctx->pair = saved_pair;
+            if (s1 == GABP_E_DEVICE) fail(ctx, s1, "autotune timing failed");
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = rpt;
+        return s1;
+    };
+    // one untimed iteration first, then two timed passes over the shapes;
+    // the best time of a shape over both passes counts
+    st = gabp_iterate(ctx, 1, damping);
+    if (st != GABP_OK) return finish(st);
+    float best_ms = INFINITY;
+    int best_rpt = ctx->rpt, best_pair = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int rpt : gabp::kRptChoices) {
+            float ms;
+            if ((st = timed(rpt, 0, ms)) != GABP_OK) return finish(st);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_rpt = rpt;
+            }
         }
+    if (ctx->frozen) {
+        // the two-iteration kernel against the best single-iteration shape
+        for (int pass = 0; pass < 2; ++pass)
+            for (int pair : gabp::kPairChoicesF32) {
+                if (!pair_ok(ctx->dtype, pair)) continue;
+                float ms;
+                if ((st = timed(best_rpt, pair, ms)) != GABP_OK) return finish(st);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_pair = pair;
+                }
+            }
+    } else {
+        best_pair = saved_pair;
     }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    ctx->rpt = best;
+    ctx->rpt = best_rpt;
+    ctx->pair = best_pair;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
-        g_tune[tune_key(ctx)] = best;
+        g_tune[tune_key(ctx)] = {best_rpt, best_pair};
     }
-    if (chosen) *chosen = best;
-    return sync_flags(ctx, false);
+    if (chosen) *chosen = best_rpt;
+    return finish(sync_flags(ctx, false));
+}
+
+gabp_status gabp_set_tile(gabp_ctx *ctx, int32_t rows_per_thread, int32_t pair_rows) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    bool rpt_ok = false;
+    for (int r : gabp::kRptChoices) rpt_ok |= r == rows_per_thread;
+    if (!rpt_ok) return fail(ctx, GABP_E_INVALID, "rows_per_thread must be 1, 2, 4 or 8");
+    if (!pair_ok(ctx->dtype, pair_rows))
+        return fail(ctx, GABP_E_INVALID, "pair_rows must be 0, 4 or (FP32 only) 8 or 16");
+    ctx->rpt = rows_per_thread;
+    ctx->pair = pair_rows;
+    return GABP_OK;
+}
+
+gabp_status gabp_get_tile(const gabp_ctx *ctx, int32_t *rows_per_thread, int32_t *pair_rows) {
+    if (!ctx) return GABP_E_INVALID;
+    if (rows_per_thread) *rows_per_thread = ctx->rpt;
+    if (pair_rows) *pair_rows = ctx->pair;
+    return GABP_OK;
 }
 
 gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at) {
@@ -600,7 +670,7 @@ gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precis
     if (!pred) return fail(ctx, GABP_E_INVALID, "pred is NULL");
     if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
     GABP_HIP(ctx, gabp::launch_warm_init(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L, pred,
-                                         keep_precisions ? 1 : 0, ctx->msg[ctx->iter & 1],
+                                         keep_precisions ? 1 : 0, ctx->msg[ctx->cur],
                                          ctx->stream));
     ctx->prev_valid = false;
     ctx->frozen = false;

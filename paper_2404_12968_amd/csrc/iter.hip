@@ -131,6 +131,156 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
     if (bad) *diverged_at = t;
 }
 
+// --------------------------------------------------------------------------
+// Two information-only iterations per pass (temporal blocking).  A
+// workgroup owns a 64 x TH tile.  Step 1 computes iteration t+1 for the tile
+// and a halo of R = stencil radius nodes around it (inputs from HBM/L2, the
+// halo's reads overlapping the neighbouring tiles'), keeping the results in
+// LDS (tile nodes also in registers with their gains).  Step 2 computes
+// iteration t+2 for the tile from LDS and writes it out.  HBM then sees one
+// read of the inputs and one write of the outputs per two iterations.  Every
+// node goes through theta_update, so the result is bitwise what two
+// single-iteration launches give.  Local position (lx, ly) in
+// [0, 64 + 2R) x [0, TH + 2R) is global (x0 - R + lx, y0 - R + ly), wrapped
+// on periodic axes; positions outside a non-periodic axis are skipped and
+// never read (their edges do not exist).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void record_divergence(uint32_t *p, uint32_t v) {
+    uint32_t old = atomicCAS(p, 0u, v);
+    while (old != 0u && old > v) {   // keep the earliest iteration
+        const uint32_t prev = atomicCAS(p, old, v);
+        if (prev == old) break;
+        old = prev;
+    }
+}
+
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <typename T, int ALPHA, int TH>
+__global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
+                                                     T *__restrict__ m_out,
+                                                     const T *__restrict__ gain,
+                                                     const T *__restrict__ bw, T eta,
+                                                     uint32_t *__restrict__ diverged_at,
+                                                     uint32_t t) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    constexpr int R = ALPHA == 1 ? 1 : 2;
+    constexpr int RPT = TH / 4;
+    constexpr int LW = 64 + 2 * R, LH = TH + 2 * R;
+    constexpr int NBAND = 2 * R * LW;             // R rows above and below, full width
+    constexpr int NHALO = NBAND + 2 * R * TH;     // plus R columns left and right
+    __shared__ T s1[DEG][LH][LW];
+    if (*diverged_at != 0u) return;               // uniform across the workgroup
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int x0 = (tile % L.tiles_x) * 64, y0 = (tile / L.tiles_x) * TH;
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    const bool px = L.bcx == BC_PERIODIC, py = L.bcy == BC_PERIODIC;
+    const bool interior = x0 >= 2 * R && x0 + 64 + 2 * R <= L.nx && y0 >= 2 * R &&
+                          y0 + TH + 2 * R <= L.ny;
+    const T c = (T)L.c, keep = (T)1 - eta;
+    bool bad1 = false, bad2 = false;
+    T th1[RPT][DEG], gk[RPT][DEG], bk[RPT];
+
+    // step 1: tile positions (one column per lane, rows w, w+4, ...)
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ly = R + w + 4 * k, lx = R + lane;
+        int gx = x0 + lane, gy = y0 + w + 4 * k;
+        T tin[DEG], ot[DEG];
+        bool ok[DEG];
+        bool here = true;
+        if (interior) {
+            theta_gather<T, ALPHA, true>(L, m_in, gain, bw, gx, gy, tin, ot, gk[k], bk[k], ok);
+        } else {
+            if (gx >= L.nx) { if (px) gx = wrap_coord(gx, L.nx); else here = false; }
+            if (gy >= L.ny) { if (py) gy = wrap_coord(gy, L.ny); else here = false; }
+            if (here)
+                theta_gather<T, ALPHA, false>(L, m_in, gain, bw, gx, gy, tin, ot, gk[k], bk[k],
+                                              ok);
+        }
+        if (here) {
+            theta_update<T, DEG>(tin, ot, gk[k], bk[k], c, eta, keep, th1[k]);
+#pragma unroll
+            for (int d = 0; d < DEG; ++d) {
+                s1[d][ly][lx] = th1[k][d];
+                if (ok[d]) bad1 |= !isfinite(th1[k][d]);
+            }
+        }
+    }
+    // step 1: halo positions
+#pragma unroll 1
+    for (int h = (int)threadIdx.x; h < NHALO; h += 256) {
+        int lx, ly;
+        if (h < NBAND) {
+            const int r = h / LW;
+            lx = h % LW;
+            ly = r < R ? r : TH + r;
+        } else {
+            const int s = h - NBAND, col = s % (2 * R);
+            ly = R + s / (2 * R);
+            lx = col < R ? col : 64 + col;
+        }
+        int gx = x0 - R + lx, gy = y0 - R + ly;
+        // only the messages this halo node sends into the tile are used
+        bool need[DEG];
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) {
+            const int tx_ = lx + dir_dx(d) - R, ty_ = ly + dir_dy(d) - R;
+            need[d] = tx_ >= 0 && tx_ < 64 && ty_ >= 0 && ty_ < TH;
+        }
+        T tin[DEG], ot[DEG], g[DEG], out[DEG], b;
+        bool ok[DEG];
+        bool here = true;
+        if (interior) {
+            theta_gather_some<T, ALPHA, true>(L, m_in, gain, bw, gx, gy, need, tin, ot, g, b, ok);
+        } else {
+            if (gx < 0 || gx >= L.nx) { if (px) gx = wrap_coord(gx, L.nx); else here = false; }
+            if (gy < 0 || gy >= L.ny) { if (py) gy = wrap_coord(gy, L.ny); else here = false; }
+            if (here)
+                theta_gather_some<T, ALPHA, false>(L, m_in, gain, bw, gx, gy, need, tin, ot, g, b,
+                                                   ok);
+        }
+        if (here) {
+            theta_update<T, DEG>(tin, ot, g, b, c, eta, keep, out);
+#pragma unroll
+            for (int d = 0; d < DEG; ++d) {
+                if (!need[d]) continue;
+                s1[d][ly][lx] = out[d];
+                if (ok[d]) bad1 |= !isfinite(out[d]);
+            }
+        }
+    }
+    __syncthreads();
+    // step 2: the tile's own nodes, from LDS
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int x = x0 + lane, y = y0 + w + 4 * k;
+        if (x >= L.nx || y >= L.ny) continue;
+        const int ly = R + w + 4 * k, lx = R + lane;
+        T tin[DEG], out[DEG];
+        bool ok[DEG];
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) {
+            int xn, yn;
+            ok[d] = interior || neighbour(L, x, y, d, xn, yn);
+            tin[d] = ok[d] ? s1[d ^ 1][ly + dir_dy(d)][lx + dir_dx(d)] : (T)0;
+        }
+        theta_update<T, DEG>(tin, th1[k], gk[k], bk[k], c, eta, keep, out);
+        const uint32_t i = (uint32_t)(y * L.pitch + x);
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) {
+            if (ok[d]) {
+                bad2 |= !isfinite(out[d]);
+                (m_out + (size_t)(DEG + d) * L.plane)[i] = out[d];
+            }
+        }
+    }
+    if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
+}
+
 static inline int tiles_of(const Lattice &L) {
     return L.tiles_x * ((L.ny + 3) / 4);
 }
@@ -199,6 +349,36 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
     } else {
         if (L.alpha == 1) launch_theta_a<double, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
         else launch_theta_a<double, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int ALPHA, int TH>
+static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
+                            const void *bw, double eta, uint32_t *flag, uint32_t t,
+                            hipStream_t s) {
+    const int tiles = L.tiles_x * ((L.ny + TH - 1) / TH);
+    hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH>), dim3(tiles), dim3(256), 0, s, L,
+                       (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta, flag,
+                       t);
+}
+
+hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
+                              const void *gain, const void *bw, double eta, uint32_t *flag,
+                              uint32_t t, hipStream_t s) {
+    if (dtype == 0) {
+        if (L.alpha == 1) {
+            if (th == 16) launch_theta2_k<float, 1, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            else if (th == 8) launch_theta2_k<float, 1, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            else launch_theta2_k<float, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+        } else {
+            if (th == 16) launch_theta2_k<float, 2, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            else if (th == 8) launch_theta2_k<float, 2, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            else launch_theta2_k<float, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+        }
+    } else {
+        if (L.alpha == 1) launch_theta2_k<double, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+        else launch_theta2_k<double, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
     }
     return hipGetLastError();
 }

@@ -88,6 +88,86 @@ __device__ __forceinline__ void iter_node(const Lattice &L, const T *__restrict_
     }
 }
 
+// --------------------------------------------------------------------------
+// Information-only update (precision messages frozen, gains g stored).  For
+// node i with incoming information messages tin[d] (from i + off_d, zero
+// where that neighbour does not exist), its previous outgoing messages ot[d],
+// the gains g[d] of its outgoing edges and its data term b:
+//   th_i = b + c sum_d tin[d],   out[d] = (1 - eta) ot[d] + eta g[d] (th_i - tin[d]).
+// Every information-only kernel goes through this function so that all of
+// them, and the full iteration, round identically.
+// --------------------------------------------------------------------------
+template <typename T, int DEG>
+__device__ __forceinline__ void theta_update(const T *tin, const T *ot, const T *g, T b, T c,
+                                             T eta, T keep, T *out) {
+    T st = 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) st += tin[d];
+    const T bt = fmadd(c, st, b);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        const T tc = bt - tin[d];
+        out[d] = fmadd(eta, g[d] * tc, keep * ot[d]);
+    }
+}
+
+// Loads of one node for theta_update (all issued before the first use).
+template <typename T, int ALPHA, bool INTERIOR>
+__device__ __forceinline__ void theta_gather(const Lattice &L, const T *__restrict__ m_in,
+                                             const T *__restrict__ gain,
+                                             const T *__restrict__ bw, int x, int y, T *tin,
+                                             T *ot, T *g, T &b, bool *ok) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) tin[d] = (m_in + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        ot[d] = (m_in + (size_t)(DEG + d) * L.plane)[i];
+        g[d] = (gain + (size_t)d * L.plane)[i];
+    }
+    b = bw[i];
+    if (!INTERIOR) {
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) tin[d] = ok[d] ? tin[d] : (T)0;
+    }
+}
+
+// As theta_gather, but the previous outgoing message and the gain are loaded
+// only for the directions in need[] (zero elsewhere: those outputs are
+// computed but must not be used).
+template <typename T, int ALPHA, bool INTERIOR>
+__device__ __forceinline__ void theta_gather_some(const Lattice &L, const T *__restrict__ m_in,
+                                                  const T *__restrict__ gain,
+                                                  const T *__restrict__ bw, int x, int y,
+                                                  const bool *need, T *tin, T *ot, T *g, T &b,
+                                                  bool *ok) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) tin[d] = (m_in + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        ot[d] = (T)0;
+        g[d] = (T)0;
+        if (need[d]) {
+            ot[d] = (m_in + (size_t)(DEG + d) * L.plane)[i];
+            g[d] = (gain + (size_t)d * L.plane)[i];
+        }
+    }
+    b = bw[i];
+    if (!INTERIOR) {
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) tin[d] = ok[d] ? tin[d] : (T)0;
+    }
+}
+
 template <typename T, int ALPHA, bool INTERIOR>
 __device__ __forceinline__ void iter_theta_node(const Lattice &L, const T *__restrict__ m_in,
                                                 T *__restrict__ m_out,
@@ -96,35 +176,15 @@ __device__ __forceinline__ void iter_theta_node(const Lattice &L, const T *__res
                                                 int x, int y) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
     const uint32_t i = (uint32_t)(y * L.pitch + x);
-    const T c = (T)L.c, keep = (T)1 - eta;
-    uint32_t j[DEG];
-    int xs[DEG], ys[DEG];
+    T tin[DEG], ot[DEG], g[DEG], out[DEG], b;
     bool ok[DEG];
-    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
-    T tin[DEG], ot[DEG], g[DEG];
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) tin[d] = (m_in + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
+    theta_gather<T, ALPHA, INTERIOR>(L, m_in, gain, bw, x, y, tin, ot, g, b, ok);
+    theta_update<T, DEG>(tin, ot, g, b, (T)L.c, eta, (T)1 - eta, out);
 #pragma unroll
     for (int d = 0; d < DEG; ++d) {
-        ot[d] = (m_in + (size_t)(DEG + d) * L.plane)[i];
-        g[d] = (gain + (size_t)d * L.plane)[i];
-    }
-    const T b = bw[i];
-    if (!INTERIOR) {
-#pragma unroll
-        for (int d = 0; d < DEG; ++d) tin[d] = ok[d] ? tin[d] : (T)0;
-    }
-    T st = 0;
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) st += tin[d];
-    const T bt = fmadd(c, st, b);
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        const T tc = bt - tin[d];
-        const T dt = fmadd(eta, g[d] * tc, keep * ot[d]);
         if (ok[d]) {
-            bad |= !isfinite(dt);
-            (m_out + (size_t)(DEG + d) * L.plane)[i] = dt;
+            bad |= !isfinite(out[d]);
+            (m_out + (size_t)(DEG + d) * L.plane)[i] = out[d];
         }
     }
 }

@@ -88,6 +88,8 @@ _SIGS = {
     "gabp_batch_destroy": ([_P], None),
     "gabp_batch_last_error": ([_P], ctypes.c_char_p),
     "gabp_warm_init": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "gabp_get_tile": ([_P, _P, _P], ctypes.c_int),
     "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
                                 ctypes.c_int),
     "gabp_upsample_mean": ([_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -514,6 +516,19 @@ def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
                                     _ptr(y) if y.numel() else None, int(nx), int(ny), float(kappa),
                                     _ptr(scratch), _ptr(x), _stream_handle(stream)))
     return x
+
+
+def gabp_set_tile(ctx: Context, rows_per_thread: int, pair_rows: int) -> None:
+    """Tile configuration of the iteration kernels (results never depend on it)."""
+    _check(_lib.gabp_set_tile(ctx.handle, int(rows_per_thread), int(pair_rows)), ctx)
+
+
+def gabp_get_tile(ctx: Context) -> Tuple[int, int]:
+    """(rows_per_thread, pair_rows) of a context."""
+    r = ctypes.c_int32(0)
+    p = ctypes.c_int32(0)
+    _check(_lib.gabp_get_tile(ctx.handle, ctypes.byref(r), ctypes.byref(p)), ctx)
+    return int(r.value), int(p.value)
 
 
 def gabp_upscale_precisions(coarse_ctx: Context, pred: torch.Tensor, scale: float) -> None:

@@ -383,6 +383,78 @@ def test_frozen_precision_phase_is_bitwise_identical(G, dtype, alpha, n):
     assert torch.equal(pa, pb) and torch.equal(ia, ib)
 
 
+def _freeze(G, ctx):
+    while G.gabp_precision_frozen(ctx) < 0:
+        G.gabp_iterate(ctx, 10, 0.5)
+        G.gabp_residual(ctx)
+        assert G.gabp_iteration_count(ctx)[0] < 5000
+    return G.gabp_precision_frozen(ctx)
+
+
+@pytest.mark.parametrize("dtype,alpha,pair,nx,ny,bcx,bcy", [
+    ("f32", 2, 8, 130, 23, I.BC_NEUMANN, I.BC_NEUMANN),
+    ("f32", 2, 4, 70, 37, I.BC_PERIODIC, I.BC_NEUMANN),
+    ("f32", 2, 8, 67, 40, I.BC_DIRICHLET, I.BC_PERIODIC),
+    ("f32", 2, 16, 200, 17, I.BC_PERIODIC, I.BC_PERIODIC),
+    ("f32", 2, 16, 150, 70, I.BC_NEUMANN, I.BC_DIRICHLET),
+    ("f32", 2, 4, 5, 70, I.BC_NEUMANN, I.BC_PERIODIC),
+    ("f32", 1, 8, 129, 45, I.BC_PERIODIC, I.BC_DIRICHLET),
+    ("f32", 1, 16, 100, 50, I.BC_NEUMANN, I.BC_PERIODIC),
+    ("f64", 2, 4, 140, 30, I.BC_PERIODIC, I.BC_NEUMANN),
+    ("f64", 1, 4, 190, 130, I.BC_PERIODIC, I.BC_NEUMANN),
+])
+def test_two_iteration_kernel_is_bitwise_identical(G, dtype, alpha, pair, nx, ny, bcx, bcy):
+    """Once the precision messages froze, two information-only iterations per
+    launch (LDS halo, ragged and wrapped tiles) give bit for bit the messages,
+    means and message-change statistic of one iteration per launch."""
+    if (dtype, alpha) == ("f64", 1):
+        # FP64 precision messages of the 5-point prior freeze bitwise only on
+        # some problems; this is the frozen-phase test's, which does
+        prob = I.small_lattice(nx, ny, alpha, bc_x=bcx, bc_y=bcy, kappa=0.1, tracks=5, run=4,
+                               sigma=0.05, seed=77, dtype=dtype)
+    else:
+        prob = I.small_lattice(nx, ny, alpha, bc_x=bcx, bc_y=bcy, kappa=0.12, frac=0.08,
+                               sigma=0.05, seed=nx + ny, dtype=dtype)
+    a = G.gabp_create_problem(prob)
+    b = G.gabp_create_problem(prob)
+    G.gabp_set_tile(a, 4, pair)
+    G.gabp_set_tile(b, 4, 0)
+    assert G.gabp_get_tile(a) == (4, pair)
+    fa, fb = _freeze(G, a), _freeze(G, b)
+    assert fa == fb > 0
+    for n in (41, 3, 2, 1, 16):
+        G.gabp_iterate(a, n, 0.5)
+        G.gabp_iterate(b, n, 0.5)
+        pa, ia = G.gabp_get_messages(a)
+        pb, ib = G.gabp_get_messages(b)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib), n
+        assert G.gabp_message_change(a) == G.gabp_message_change(b)
+    ma, _ = G.gabp_posterior(a, want_var=False)
+    mb, _ = G.gabp_posterior(b, want_var=False)
+    assert torch.equal(ma, mb)
+    assert G.gabp_iteration_count(a) == G.gabp_iteration_count(b)
+
+
+def test_autotune_after_freezing_times_the_two_iteration_kernel(G):
+    prob = I.small_lattice(150, 60, 2, kappa=0.12, frac=0.08, sigma=0.05, seed=3, dtype="f32")
+    a = G.gabp_create_problem(prob)
+    _freeze(G, a)
+    t0 = G.gabp_iteration_count(a)[0]
+    G.gabp_autotune(a, 5, 0.5)
+    assert G.gabp_iteration_count(a)[0] == t0 + 1 + 8 * 5 + 6 * 5
+    rpt, pair = G.gabp_get_tile(a)
+    assert rpt in (1, 2, 4, 8) and pair in (0, 4, 8, 16)
+    b = G.gabp_create_problem(prob)
+    G.gabp_set_tile(b, 4, 0)
+    _freeze(G, b)
+    G.gabp_iterate(b, 1 + 8 * 5 + 6 * 5, 0.5)
+    assert torch.equal(G.gabp_get_messages(a)[1], G.gabp_get_messages(b)[1])
+    with pytest.raises(G.GabpError):
+        G.gabp_set_tile(a, 3, 0)
+    with pytest.raises(G.GabpError):
+        G.gabp_set_tile(G.gabp_create_problem(I.small_lattice(20, 20, 2, dtype="f64")), 4, 8)
+
+
 # --------------------------------------------------------------------------
 # batched instances
 # --------------------------------------------------------------------------
