@@ -134,16 +134,19 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
 // --------------------------------------------------------------------------
 // Two information-only iterations per pass (temporal blocking).  A
 // workgroup owns a 64 x TH tile.  Step 1 computes iteration t+1 for the tile
-// and a halo of R = stencil radius nodes around it (inputs from HBM/L2, the
-// halo's reads overlapping the neighbouring tiles'), keeping the results in
-// LDS (tile nodes also in registers with their gains).  Step 2 computes
-// iteration t+2 for the tile from LDS and writes it out.  HBM then sees one
-// read of the inputs and one write of the outputs per two iterations.  Every
-// node goes through theta_update, so the result is bitwise what two
-// single-iteration launches give.  Local position (lx, ly) in
-// [0, 64 + 2R) x [0, TH + 2R) is global (x0 - R + lx, y0 - R + ly), wrapped
-// on periodic axes; positions outside a non-periodic axis are skipped and
-// never read (their edges do not exist).
+// and for a halo of R = stencil radius nodes around it (inputs from HBM/L2;
+// a halo node only computes the messages it sends into the tile), and leaves
+// in LDS, for every tile node and direction d, its incoming message from
+// the node at + off_d (receiver-indexed, 64 x TH x deg values; the tile
+// nodes' own new messages stay in registers with their gains).  Step 2
+// computes iteration t+2 for the tile from LDS and writes it out.  HBM then
+// sees one read of the inputs and one write of the outputs per two
+// iterations.  Every node goes through theta_update, so the result is bitwise
+// what two single-iteration launches give.  Local position (lx, ly) in
+// [-R, 64 + R) x [-R, TH + R) is global (x0 + lx, y0 + ly), wrapped on
+// periodic axes; positions outside a non-periodic axis are skipped (their
+// edges do not exist), and tile positions past the end of a periodic axis
+// repeat wrapped nodes without being written back.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void record_divergence(uint32_t *p, uint32_t v) {
     uint32_t old = atomicCAS(p, 0u, v);
@@ -159,8 +162,8 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-template <typename T, int ALPHA, int TH>
-__global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
+template <typename T, int ALPHA, int TH, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
                                                      T *__restrict__ m_out,
                                                      const T *__restrict__ gain,
                                                      const T *__restrict__ bw, T eta,
@@ -168,11 +171,13 @@ __global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restr
                                                      uint32_t t) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
     constexpr int R = ALPHA == 1 ? 1 : 2;
-    constexpr int RPT = TH / 4;
-    constexpr int LW = 64 + 2 * R, LH = TH + 2 * R;
+    constexpr int NT = 64 * WAVES;
+    constexpr int RPT = TH / WAVES;
+    static_assert(TH % WAVES == 0, "tile rows must be a multiple of the wave count");
+    constexpr int LW = 64 + 2 * R;
     constexpr int NBAND = 2 * R * LW;             // R rows above and below, full width
     constexpr int NHALO = NBAND + 2 * R * TH;     // plus R columns left and right
-    __shared__ T s1[DEG][LH][LW];
+    __shared__ T sin_[DEG][TH][64];               // incoming messages at t+1, receiver-indexed
     if (*diverged_at != 0u) return;               // uniform across the workgroup
     const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int x0 = (tile % L.tiles_x) * 64, y0 = (tile / L.tiles_x) * TH;
@@ -184,11 +189,17 @@ __global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restr
     bool bad1 = false, bad2 = false;
     T th1[RPT][DEG], gk[RPT][DEG], bk[RPT];
 
-    // step 1: tile positions (one column per lane, rows w, w+4, ...)
+    // store message (lx, ly) -> (lx, ly) + off_e if its receiver is in the tile
+    auto deliver = [&](int lx, int ly, int e, T v) {
+        const int rx = lx + dir_dx(e), ry = ly + dir_dy(e);
+        if (rx >= 0 && rx < 64 && ry >= 0 && ry < TH) sin_[e ^ 1][ry][rx] = v;
+    };
+
+    // step 1: tile positions (one column per lane, rows w, w + WAVES, ...)
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int ly = R + w + 4 * k, lx = R + lane;
-        int gx = x0 + lane, gy = y0 + w + 4 * k;
+        const int ly = w + WAVES * k;
+        int gx = x0 + lane, gy = y0 + ly;
         T tin[DEG], ot[DEG];
         bool ok[DEG];
         bool here = true;
@@ -205,31 +216,31 @@ __global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restr
             theta_update<T, DEG>(tin, ot, gk[k], bk[k], c, eta, keep, th1[k]);
 #pragma unroll
             for (int d = 0; d < DEG; ++d) {
-                s1[d][ly][lx] = th1[k][d];
+                deliver(lane, ly, d, th1[k][d]);
                 if (ok[d]) bad1 |= !isfinite(th1[k][d]);
             }
         }
     }
     // step 1: halo positions
 #pragma unroll 1
-    for (int h = (int)threadIdx.x; h < NHALO; h += 256) {
+    for (int h = (int)threadIdx.x; h < NHALO; h += NT) {
         int lx, ly;
         if (h < NBAND) {
             const int r = h / LW;
-            lx = h % LW;
-            ly = r < R ? r : TH + r;
+            lx = h % LW - R;
+            ly = r < R ? r - R : TH + r - R;
         } else {
             const int s = h - NBAND, col = s % (2 * R);
-            ly = R + s / (2 * R);
-            lx = col < R ? col : 64 + col;
+            ly = s / (2 * R);
+            lx = col < R ? col - R : 64 + col - R;
         }
-        int gx = x0 - R + lx, gy = y0 - R + ly;
+        int gx = x0 + lx, gy = y0 + ly;
         // only the messages this halo node sends into the tile are used
         bool need[DEG];
 #pragma unroll
         for (int d = 0; d < DEG; ++d) {
-            const int tx_ = lx + dir_dx(d) - R, ty_ = ly + dir_dy(d) - R;
-            need[d] = tx_ >= 0 && tx_ < 64 && ty_ >= 0 && ty_ < TH;
+            const int rx = lx + dir_dx(d), ry = ly + dir_dy(d);
+            need[d] = rx >= 0 && rx < 64 && ry >= 0 && ry < TH;
         }
         T tin[DEG], ot[DEG], g[DEG], out[DEG], b;
         bool ok[DEG];
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restr
 #pragma unroll
             for (int d = 0; d < DEG; ++d) {
                 if (!need[d]) continue;
-                s1[d][ly][lx] = out[d];
+                sin_[d ^ 1][ly + dir_dy(d)][lx + dir_dx(d)] = out[d];
                 if (ok[d]) bad1 |= !isfinite(out[d]);
             }
         }
@@ -257,19 +268,19 @@ __global__ __launch_bounds__(256) void k_iter_theta2(Lattice L, const T *__restr
     // step 2: the tile's own nodes, from LDS
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int x = x0 + lane, y = y0 + w + 4 * k;
+        const int ly = w + WAVES * k;
+        const int x = x0 + lane, y = y0 + ly;
         if (x >= L.nx || y >= L.ny) continue;
-        const int ly = R + w + 4 * k, lx = R + lane;
+        const uint32_t i = (uint32_t)(y * L.pitch + x);
         T tin[DEG], out[DEG];
         bool ok[DEG];
 #pragma unroll
         for (int d = 0; d < DEG; ++d) {
             int xn, yn;
             ok[d] = interior || neighbour(L, x, y, d, xn, yn);
-            tin[d] = ok[d] ? s1[d ^ 1][ly + dir_dy(d)][lx + dir_dx(d)] : (T)0;
+            tin[d] = ok[d] ? sin_[d][ly][lane] : (T)0;
         }
         theta_update<T, DEG>(tin, th1[k], gk[k], bk[k], c, eta, keep, out);
-        const uint32_t i = (uint32_t)(y * L.pitch + x);
 #pragma unroll
         for (int d = 0; d < DEG; ++d) {
             if (ok[d]) {
@@ -353,14 +364,16 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
     return hipGetLastError();
 }
 
+// tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8
 template <typename T, int ALPHA, int TH>
 static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
                             const void *bw, double eta, uint32_t *flag, uint32_t t,
                             hipStream_t s) {
+    constexpr int WAVES = TH == 4 ? 4 : 8;
     const int tiles = L.tiles_x * ((L.ny + TH - 1) / TH);
-    hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH>), dim3(tiles), dim3(256), 0, s, L,
-                       (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta, flag,
-                       t);
+    hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(tiles), dim3(64 * WAVES), 0, s,
+                       L, (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
+                       flag, t);
 }
 
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
