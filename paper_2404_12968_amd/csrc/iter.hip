@@ -157,6 +157,8 @@ __device__ __forceinline__ void record_divergence(uint32_t *p, uint32_t v) {
     }
 }
 
+constexpr int kStrip = 8;   // tile columns per strip of the two-iteration kernel's order
+
 __device__ __forceinline__ int wrap_coord(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -179,8 +181,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
     constexpr int NHALO = NBAND + 2 * R * TH;     // plus R columns left and right
     __shared__ T sin_[DEG][TH][64];               // incoming messages at t+1, receiver-indexed
     if (*diverged_at != 0u) return;               // uniform across the workgroup
-    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int x0 = (tile % L.tiles_x) * 64, y0 = (tile / L.tiles_x) * TH;
+    // Tiles in strip-major order: strips of kStrip tile columns, each walked
+    // row by row, and each XCD a contiguous range of that order.  Tiles above
+    // and below then run close together on one XCD and share their halo rows
+    // in its L2.
+    int tx, ty;
+    {
+        const int t_ = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+        const int rows = (L.ny + TH - 1) / TH;
+        const int strip = t_ / (kStrip * rows), r = t_ - strip * kStrip * rows;
+        const int width = min(kStrip, L.tiles_x - strip * kStrip);
+        ty = r / width;
+        tx = strip * kStrip + r % width;
+    }
+    const int x0 = tx * 64, y0 = ty * TH;
     const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
     const bool px = L.bcx == BC_PERIODIC, py = L.bcy == BC_PERIODIC;
     const bool interior = x0 >= 2 * R && x0 + 64 + 2 * R <= L.nx && y0 >= 2 * R &&
