@@ -7,6 +7,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -58,6 +59,16 @@ struct gabp_ctx {
     int rpt = 4;                   // rows per thread of the iteration kernel's tile
     int pair = 0;                  // tile height of the two-iteration kernel, 0 = unused
     int cur = 0;                   // buffer holding the current messages m^iter
+    // launches since the last flag read-back, one record per gabp_iterate
+    // call: it started at iteration `start` with buffer `buf`, ran `pairs`
+    // two-iteration launches, then `singles` one-iteration launches (each
+    // launch writes the other buffer).  A divergence found at the next
+    // read-back selects the buffer its launch wrote.
+    struct LaunchRun {
+        int64_t start;
+        int buf, pairs, singles;
+    };
+    std::vector<LaunchRun> runs;
     int64_t iter = 0;
     bool diverged = false;
     bool prev_valid = false;       // the other buffer holds m^{iter-1}
@@ -104,7 +115,18 @@ gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
     if (t != 0u && !ctx->diverged) {
         ctx->diverged = true;
         ctx->iter = (int64_t)t;
+        // later launches returned without writing: the messages of the
+        // diverged iteration are in the buffer its own launch wrote
+        for (const auto &r : ctx->runs) {
+            const int64_t rel = (int64_t)t - r.start;
+            if (rel < 1 || rel > 2 * (int64_t)r.pairs + r.singles) continue;
+            const int64_t k = rel <= 2 * (int64_t)r.pairs ? (rel + 1) / 2
+                                                          : r.pairs + (rel - 2 * (int64_t)r.pairs);
+            ctx->cur = r.buf ^ (int)(k & 1);
+            break;
+        }
     }
+    ctx->runs.clear();
     if (ctx->diverged)
         return fail(ctx, GABP_E_DIVERGED,
                     fmt("diverged at iteration %.0f (non-positive cavity precision or non-finite message)",
@@ -350,6 +372,7 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
     if (ctx->iter + n_iters >= (int64_t)UINT32_MAX)
         return fail(ctx, GABP_E_INVALID, "iteration counter overflow");
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
+    ctx->runs.push_back({ctx->iter, ctx->cur, 0, 0});
     int32_t k = 0;
     while (k < n_iters) {
         const void *src = ctx->msg[ctx->cur];
@@ -363,6 +386,7 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
             ctx->iter += 2;
             k += 2;
             ctx->cur ^= 1;
+            ++ctx->runs.back().pairs;
             continue;
         }
         const int64_t t = ctx->iter + 1;
@@ -376,6 +400,7 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
                                             ctx->stream));
         ctx->iter = t;
         ctx->cur ^= 1;
+        ++ctx->runs.back().singles;
         ++k;
         if (t == 2) {
             const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
