@@ -161,6 +161,21 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
  * gains (bitwise the same results, 12 instead of 16 bytes per FP32 edge). */
 gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_residual);
 
+/* The paper's stopping rule (Alg. 2, Iterate MP Until Convergence, with the
+ * Early Stop of Appendix A): iterate until mean|m^t - m^{t-1}| <
+ * tau * mean|m^2 - m^1| (both components of every directed message, m^1 and
+ * m^2 the context's first two iterations; the paper takes tau = 1e-3), with
+ * at most max_iters iterations in this call (the paper's T; NOT_CONVERGED
+ * when reached, which the paper treats as a normal end), or until the run
+ * diverges (DIVERGED).  check_every > 0: the statistic every check_every
+ * iterations; < 0: adaptively, every |check_every| iterations until the
+ * precision messages froze (with a residual check, which detects the
+ * freeze), then after half the iterations the ratio's observed geometric
+ * decay predicts to tau (at least |check_every|, at most 2000).  iters_done
+ * and ratio (the last statistic) may be NULL.  Synchronises at every check. */
+gabp_status gabp_solve_early_stop(gabp_ctx *ctx, int64_t max_iters, double damping, double tau,
+                                  int32_t check_every, int64_t *iters_done, double *ratio);
+
 /* Marginals of the current messages (Compute Marginal): belief precision
  * Lam_i = A_ii + c sum Lam_{k->i}, information th_i = b_i + c sum th_{k->i}
  * accumulated in FP64; mean[i] = th_i / Lam_i, var[i] = 1 / Lam_i.  mean and

@@ -509,6 +509,66 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
     return st;
 }
 
+gabp_status gabp_solve_early_stop(gabp_ctx *ctx, int64_t max_iters, double damping, double tau,
+                                  int32_t check_every, int64_t *iters_done, double *ratio_out) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (max_iters < 0 || check_every == 0 || !(tau >= 0))
+        return fail(ctx, GABP_E_INVALID, "need max_iters >= 0, check_every != 0, tau >= 0");
+    // same check schedule as gabp_solve, on the message-change ratio
+    constexpr int64_t kMaxInterval = 2000;
+    const bool adaptive = check_every < 0;
+    const int64_t kmin = adaptive ? -(int64_t)check_every : (int64_t)check_every;
+    double ratio = INFINITY, prev = -1.0;
+    int64_t run = 0, prev_t = 0;
+    int64_t next = std::max<int64_t>(kmin, ctx->iter < 3 ? 3 - ctx->iter : 0);
+    st = GABP_E_NOT_CONVERGED;
+    while (run < max_iters) {
+        const int32_t k = (int32_t)std::min<int64_t>(next, max_iters - run);
+        gabp_status s1 = gabp_iterate(ctx, k, damping);
+        if (s1 != GABP_OK) {
+            st = s1;
+            break;
+        }
+        run += k;
+        if (ctx->iter < 3) {
+            next = 3 - ctx->iter;
+            continue;
+        }
+        s1 = gabp_message_change(ctx, &ratio);
+        if (s1 != GABP_OK) {
+            st = s1;
+            break;
+        }
+        if (ratio < tau) {
+            st = GABP_OK;
+            break;
+        }
+        next = kmin;
+        if (adaptive && ctx->frozen && prev > 0 && ratio < prev && ratio > 0 && tau > 0) {
+            const double rate = std::log(ratio / prev) / (double)(ctx->iter - prev_t);
+            const double need = std::log(tau / ratio) / rate;
+            next = std::max<int64_t>(kmin, std::min<int64_t>(kMaxInterval, (int64_t)(0.5 * need)));
+        }
+        if (!ctx->frozen && adaptive) {
+            // a residual check is what detects frozen precision messages
+            double rel;
+            s1 = gabp_residual(ctx, &rel, nullptr);
+            if (s1 != GABP_OK) {
+                st = s1;
+                break;
+            }
+        }
+        prev = ratio;
+        prev_t = ctx->iter;
+    }
+    if (st == GABP_E_NOT_CONVERGED)
+        fail(ctx, st, fmt("message change ratio %g after %.0f iterations", ratio, (double)ctx->iter));
+    if (iters_done) *iters_done = ctx->iter;
+    if (ratio_out) *ratio_out = ratio;
+    return st;
+}
+
 gabp_status gabp_posterior(gabp_ctx *ctx, double *mean, double *var) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;

@@ -88,6 +88,8 @@ _SIGS = {
     "gabp_batch_destroy": ([_P], None),
     "gabp_batch_last_error": ([_P], ctypes.c_char_p),
     "gabp_warm_init": ([_P, _P, ctypes.c_int32], ctypes.c_int),
+    "gabp_solve_early_stop": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int32, _P, _P], ctypes.c_int),
     "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "gabp_get_tile": ([_P, _P, _P], ctypes.c_int),
     "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
@@ -237,6 +239,19 @@ def gabp_solve(ctx: Context, max_iters: int, damping: float, rel_tol: float,
     if st not in (GABP_OK, GABP_E_DIVERGED, GABP_E_NOT_CONVERGED):
         _check(st, ctx)
     return int(st), int(it.value), float(rel.value)
+
+
+def gabp_solve_early_stop(ctx: Context, max_iters: int, damping: float, tau: float = 1e-3,
+                          check_every: int = -10) -> Tuple[int, int, float]:
+    """The paper's early-stop rule; returns (status, total iterations, last
+    message-change ratio)."""
+    it = ctypes.c_int64(0)
+    r = ctypes.c_double(0.0)
+    st = _lib.gabp_solve_early_stop(ctx.handle, int(max_iters), float(damping), float(tau),
+                                    int(check_every), ctypes.byref(it), ctypes.byref(r))
+    if st not in (GABP_OK, GABP_E_DIVERGED, GABP_E_NOT_CONVERGED):
+        _check(st, ctx)
+    return int(st), int(it.value), float(r.value)
 
 
 def gabp_residual(ctx: Context) -> Tuple[float, float]:

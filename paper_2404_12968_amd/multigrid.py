@@ -64,23 +64,6 @@ def max_levels(prob: I.Problem, coarsest: int = 32) -> int:
         L += 1
 
 
-def _until_messages_settle(ctx, damping: float, tau: float, max_iters: int, every: int):
-    """Early stop of Appendix A: iterate until the mean absolute message
-    change falls below tau times that of the level's first two iterations."""
-    ratio = float("inf")
-    it, st = G.gabp_iteration_count(ctx)
-    while it < max_iters:
-        G.gabp_iterate(ctx, min(every, max_iters - it), damping)
-        it, st = G.gabp_iteration_count(ctx)
-        if st == G.GABP_E_DIVERGED:
-            return st, it, ratio
-        if it >= 3:
-            ratio = G.gabp_message_change(ctx)
-            if ratio < tau:
-                return G.GABP_OK, it, ratio
-    return G.GABP_E_NOT_CONVERGED, it, ratio
-
-
 def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
                     coarse_tol: Optional[float] = None, max_iters: int = 300000,
                     check_every: int = -10, device="cuda", keep_context: bool = False,
@@ -117,9 +100,9 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
         if pred is not None:
             G.gabp_warm_init(ctx, pred, keep_precisions=(transfer == "mean"))
         if lev == 0 and final_stop == "message_change":
-            st, it, rel = _until_messages_settle(ctx, p.damping,
-                                                 1e-3 if final_tol is None else final_tol,
-                                                 max_iters, abs(check_every))
+            st, it, rel = G.gabp_solve_early_stop(ctx, max_iters, p.damping,
+                                                  1e-3 if final_tol is None else final_tol,
+                                                  check_every)
         elif lev == 0:
             st, it, rel = G.gabp_solve(ctx, max_iters, p.damping,
                                        prob.rel_tol if final_tol is None else final_tol,
@@ -128,8 +111,8 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
             st, it, rel = G.gabp_solve(ctx, max_iters, p.damping, max(coarse_tol, prob.rel_tol),
                                        check_every)
         else:
-            st, it, rel = _until_messages_settle(ctx, p.damping, coarse_tol, max_iters,
-                                                 abs(check_every))
+            st, it, rel = G.gabp_solve_early_stop(ctx, max_iters, p.damping, coarse_tol,
+                                                  check_every)
         per_level.append({"level": lev, "nx": p.nx, "ny": p.ny, "iterations": it,
                           "status": st, "rel": rel, "observations": int(p.cells.size)})
         if st == G.GABP_E_DIVERGED:

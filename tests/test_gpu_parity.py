@@ -246,6 +246,41 @@ def test_message_change_statistic_matches_oracle(G, oracle_mod):
     assert r == pytest.approx(num / ref, rel=1e-10)
 
 
+def test_early_stop_rule_stops_where_the_oracle_does(G, oracle_mod):
+    """The paper's early stop (mean |m^t - m^(t-1)| < tau mean |m^2 - m^1|),
+    checked every iteration, ends at the first iteration where the oracle's
+    statistic falls below tau; checked adaptively, it ends later but with
+    the oracle's statistic at that iteration below tau."""
+    prob = I.small_lattice(40, 30, 2, kappa=0.2, c=10.0, frac=0.1, sigma=0.05, seed=12, dtype="f64")
+    tau = 1e-3
+    og = oracle_mod.OracleGaBP.from_problem(prob)
+    og.iterate(1, 0.5)
+    m1 = (og.lam.copy(), og.th.copy())
+    og.iterate(1, 0.5)
+    ref = og.abs_change(og.lam, og.th, *m1)
+    ratios = {}
+    t = 2
+    while t < 3000:
+        prev = (og.lam.copy(), og.th.copy())
+        og.iterate(1, 0.5)
+        t += 1
+        ratios[t] = og.abs_change(og.lam, og.th, *prev) / ref
+        if ratios[t] < tau:
+            break
+    t_stop = t
+    assert ratios[t_stop] < tau and 50 < t_stop < 3000
+    ctx = G.gabp_create_problem(prob)
+    st, it, r = G.gabp_solve_early_stop(ctx, 5000, 0.5, tau, 1)
+    assert st == G.GABP_OK and it == t_stop
+    assert r == pytest.approx(ratios[t_stop], rel=1e-9)
+    ctx2 = G.gabp_create_problem(prob)
+    st, it2, r2 = G.gabp_solve_early_stop(ctx2, 5000, 0.5, tau, -5)
+    assert st == G.GABP_OK and it2 >= t_stop and r2 < tau
+    ctx3 = G.gabp_create_problem(prob)
+    st, it3, _ = G.gabp_solve_early_stop(ctx3, 40, 0.5, tau, 1)
+    assert st == G.GABP_E_NOT_CONVERGED and it3 == 40
+
+
 def test_no_observations_gives_zero_mean(G):
     prob = I.Problem("empty", 40, 30, I.BC_NEUMANN, I.BC_NEUMANN, 2, 0.2, 1.0, 10.0, 0.1,
                      np.zeros(0, np.int64), np.zeros(0), dtype="f64")
