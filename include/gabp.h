@@ -319,6 +319,10 @@ gabp_status gabp_batch_iterate(gabp_batch *b, int32_t n_iters, double damping);
  * one's FP64 relative residual after every chunk; an instance retires when
  * it reaches rel_tol (status OK), diverges (DIVERGED, same rules as
  * gabp_solve), or the call has run max_iters iterations (NOT_CONVERGED).
+ * check_every < 0 sizes chunks adaptively: |check_every| until every running
+ * instance's precision messages froze, then the largest |check_every| * 2^j
+ * (at most 1280) not above half the iterations the slowest running
+ * instance's observed residual decay predicts to rel_tol.
  * Per-instance results go to the caller's host arrays of n entries (each
  * may be NULL).  Returns OK when every instance converged, else
  * NOT_CONVERGED.  Synchronises at every check. */

@@ -31,6 +31,7 @@
 #include "host_common.h"
 #include "internal.h"
 #include "iter_node.h"
+#include "pair_tile.h"
 #include "lattice.h"
 #include "numerics.h"
 
@@ -75,8 +76,8 @@ __global__ __launch_bounds__(256) void k_batch_iter(const BatchInst *__restrict_
     const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
     const int w1 = min(total, ((int)blockIdx.x + 1) * per);
     for (int w = (int)blockIdx.x * per; w < w1; ++w) {
-        const int a = find_item(prefix, nact, w);
-        const int I = act[a];
+        const int a = __builtin_amdgcn_readfirstlane(find_item(prefix, nact, w));
+        const int I = __builtin_amdgcn_readfirstlane(act[a]);
         if (diverged_at[I] != 0u) continue;
         const BatchInst &B = inst[I];
         const Lattice L = B.L;
@@ -116,6 +117,41 @@ __global__ __launch_bounds__(256) void k_batch_iter(const BatchInst *__restrict_
         }
         if (bad) diverged_at[I] = t;
     }
+}
+
+// Two information-only iterations of every frozen running instance with the
+// prior order ALPHA: one workgroup per work item, item w (XCD-remapped so
+// that each XCD takes a contiguous range) maps to instance act[a] and 64 x TH
+// tile w - prefix[a].  Launches come in couples: the first (second == 0)
+// reads the buffer of the state it starts from, iteration t, and writes the
+// other one; the second reads that one and writes back, so after a couple
+// each instance is in the buffer its iteration number selects, as after
+// single iterations.
+template <typename T, int ALPHA, int TH, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_batch_pair(const BatchInst *__restrict__ inst,
+                                                           const int *__restrict__ act,
+                                                           const int *__restrict__ prefix,
+                                                           int nact,
+                                                           const uint32_t *__restrict__ t_dev,
+                                                           int t_off, int second, T eta,
+                                                           uint32_t *__restrict__ diverged_at) {
+    __shared__ T lds[(ALPHA == 1 ? 4 : 12) * TH * 64];
+    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int a = __builtin_amdgcn_readfirstlane(find_item(prefix, nact, w));
+    const int I = __builtin_amdgcn_readfirstlane(act[a]);
+    if (diverged_at[I] != 0u) return;   // waves that return leave the tile's barrier
+    const uint32_t t = *t_dev + (uint32_t)t_off;   // iteration the launch starts from
+    const BatchInst &B = inst[I];
+    const Lattice L = B.L;
+    const int tile = w - prefix[a];
+    const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+    const uint32_t own = t & 1u;
+    const T *m_in = (const T *)B.msg[second ? own ^ 1u : own];
+    T *m_out = (T *)B.msg[second ? own : own ^ 1u];
+    bool bad1 = false, bad2 = false;
+    pair_tile<T, ALPHA, TH, WAVES>(L, m_in, m_out, (const T *)B.gain, (const T *)B.b_w, eta, tx,
+                                   ty, lds, bad1, bad2);
+    if (bad1 || bad2) record_divergence(&diverged_at[I], bad1 ? t + 1u : t + 2u);
 }
 
 // Marginals of every running instance (64 x 4 tiles), writing each
@@ -248,6 +284,7 @@ struct InstHost {
     Layout lay;
     size_t base = 0;            // byte offset of the instance's region
     int tiles_iter = 0;         // work items of the iteration kernel
+    int tiles_pair = 0;         // work items of the two-iteration kernel
     int tiles_check = 0;        // work items of the check kernels (64 x 4)
     bool running = true;
     bool frozen = false;
@@ -256,6 +293,8 @@ struct InstHost {
     int64_t iters = 0;          // iterations applied to this instance
     double rel = INFINITY;
     double first_rel = -1.0;
+    double prev_rel = -1.0;     // residual and iteration count at the check before
+    int64_t prev_iters = 0;
     bool prev_valid = false;
 };
 
@@ -279,6 +318,9 @@ struct gabp_batch {
     BatchInst *d_inst = nullptr;
     int *d_act = nullptr, *d_wprefix = nullptr, *d_pprefix = nullptr;
     int *d_frozen = nullptr, *d_probe = nullptr;
+    int *d_actu = nullptr, *d_wprefu = nullptr;   // running, precision not frozen (1 iteration)
+    int *d_actf[2] = {nullptr, nullptr}, *d_wpreff[2] = {nullptr, nullptr};
+                                                  // running, frozen, by prior order (2 per launch)
     uint32_t *d_div = nullptr, *d_bits = nullptr, *d_t = nullptr, *d_err = nullptr;
     double *d_partials = nullptr, *d_out = nullptr;
     size_t partial_cap = 0;     // work items of the check kernels
@@ -287,9 +329,11 @@ struct gabp_batch {
     uint32_t *p_div = nullptr, *p_bits = nullptr, *p_t = nullptr;
     int *p_lists = nullptr;     // staging for act / prefixes / frozen / probe
     int rpt = 4;
+    int pair = 0;               // tile height of the two-iteration kernel, 0 = unused
     int64_t t = 0;              // iterations applied to the running set
     // current work lists
     int nact = 0, wtotal = 0, ptotal = 0;
+    int nu = 0, wtotu = 0, nf[2] = {0, 0}, wtotf[2] = {0, 0};
     bool lists_dirty = true;
     // captured chunk
     hipGraph_t graph = nullptr;
@@ -336,6 +380,14 @@ int tiles_iter_of(const Lattice &L, int rpt) {
     return L.tiles_x * ((L.ny + 4 * rpt - 1) / (4 * rpt));
 }
 
+int tiles_pair_of(const Lattice &L, int th) {
+    return L.tiles_x * ((L.ny + th - 1) / th);
+}
+
+// lists staging / device layout: act[n] wprefix[n+1] pprefix[n+1] frozen[n]
+// probe[n] actu[n] wprefu[n+1], then actf[n] wpreff[n+1] for alpha = 1 and 2
+constexpr int lists_ints(int n) { return 11 * n + 5; }
+
 void drop_graph(gabp_batch *b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -348,7 +400,13 @@ void drop_graph(gabp_batch *b) {
 gabp_status upload_lists(gabp_batch *b) {
     const int n = b->n;
     int *act = b->p_lists, *wp = act + n, *pp = wp + n + 1, *fz = pp + n + 1, *pr = fz + n;
-    int na = 0, w = 0, p = 0;
+    int *actu = pr + n, *wpu = actu + n;
+    int *actf[2], *wpf[2];
+    actf[0] = wpu + n + 1;
+    wpf[0] = actf[0] + n;
+    actf[1] = wpf[0] + n + 1;
+    wpf[1] = actf[1] + n;
+    int na = 0, w = 0, p = 0, nu = 0, wu = 0, nf[2] = {0, 0}, wf[2] = {0, 0};
     for (int i = 0; i < n; ++i) {
         InstHost &H = b->h[i];
         fz[i] = H.frozen ? 1 : 0;
@@ -361,14 +419,36 @@ gabp_status upload_lists(gabp_batch *b) {
         w += H.tiles_iter;
         p += H.tiles_check;
         ++na;
+        if (H.frozen && b->pair > 0) {
+            const int q = H.L.alpha == 1 ? 0 : 1;
+            H.tiles_pair = tiles_pair_of(H.L, b->pair);
+            actf[q][nf[q]] = i;
+            wpf[q][nf[q]] = wf[q];
+            wf[q] += H.tiles_pair;
+            ++nf[q];
+        } else {
+            actu[nu] = i;
+            wpu[nu] = wu;
+            wu += H.tiles_iter;
+            ++nu;
+        }
     }
     wp[na] = w;
     pp[na] = p;
+    wpu[nu] = wu;
+    wpf[0][nf[0]] = wf[0];
+    wpf[1][nf[1]] = wf[1];
     b->nact = na;
     b->wtotal = w;
     b->ptotal = p;
-    // d_act, d_wprefix, d_pprefix, d_frozen, d_probe are contiguous
-    BHIP(b, hipMemcpyAsync(b->d_act, b->p_lists, sizeof(int) * (size_t)(5 * n + 2),
+    b->nu = nu;
+    b->wtotu = wu;
+    for (int q = 0; q < 2; ++q) {
+        b->nf[q] = nf[q];
+        b->wtotf[q] = wf[q];
+    }
+    // all lists are contiguous from d_act on
+    BHIP(b, hipMemcpyAsync(b->d_act, b->p_lists, sizeof(int) * (size_t)lists_ints(n),
                            hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));   // staging buffer is reused
     b->lists_dirty = false;
@@ -376,25 +456,79 @@ gabp_status upload_lists(gabp_batch *b) {
     return GABP_OK;
 }
 
-gabp_status launch_iters(gabp_batch *b, int k, double eta) {
-    if (b->nact == 0) return GABP_OK;
-    const int grid = std::min(kBatchGrid, std::max(1, b->wtotal));
-    for (int s = 1; s <= k; ++s) {
+// One iteration of the instances in one work list (single-iteration kernel).
+gabp_status launch_single(gabp_batch *b, const int *act, const int *prefix, int na, int total,
+                          int s, double eta) {
+    if (na == 0) return GABP_OK;
+    const int grid = std::min(kBatchGrid, std::max(1, total));
+    if (b->dtype == GABP_F32) {
+        switch (b->rpt) {
+#define RPT_CASE(R) case R: hipLaunchKernelGGL((gabp::k_batch_iter<float, R>), dim3(grid), dim3(256), 0, b->stream, b->d_inst, act, prefix, na, total, b->d_frozen, b->d_t, s, (float)eta, b->d_div); break;
+            RPT_CASE(1) RPT_CASE(2) RPT_CASE(4) default: RPT_CASE(8)
+#undef RPT_CASE
+        }
+    } else {
+        switch (b->rpt) {
+#define RPT_CASE(R) case R: hipLaunchKernelGGL((gabp::k_batch_iter<double, R>), dim3(grid), dim3(256), 0, b->stream, b->d_inst, act, prefix, na, total, b->d_frozen, b->d_t, s, eta, b->d_div); break;
+            RPT_CASE(1) RPT_CASE(2) RPT_CASE(4) default: RPT_CASE(8)
+#undef RPT_CASE
+        }
+    }
+    BHIP(b, hipGetLastError());
+    return GABP_OK;
+}
+
+// Two iterations (starting from iteration offset s0) of the frozen lists.
+gabp_status launch_pair(gabp_batch *b, int s0, int second, double eta) {
+    for (int q = 0; q < 2; ++q) {
+        if (b->nf[q] == 0) continue;
+        const dim3 grid((unsigned)b->wtotf[q]);
+        const int *act = b->d_actf[q], *pre = b->d_wpreff[q];
         if (b->dtype == GABP_F32) {
-            switch (b->rpt) {
-#define RPT_CASE(R) case R: hipLaunchKernelGGL((gabp::k_batch_iter<float, R>), dim3(grid), dim3(256), 0, b->stream, b->d_inst, b->d_act, b->d_wprefix, b->nact, b->wtotal, b->d_frozen, b->d_t, s, (float)eta, b->d_div); break;
-                RPT_CASE(1) RPT_CASE(2) RPT_CASE(4) default: RPT_CASE(8)
-#undef RPT_CASE
-            }
+            if (q == 0)
+                hipLaunchKernelGGL((gabp::k_batch_pair<float, 1, 16, 8>), grid, dim3(512), 0,
+                                   b->stream, b->d_inst, act, pre, b->nf[q], b->d_t, s0, second,
+                                   (float)eta, b->d_div);
+            else
+                hipLaunchKernelGGL((gabp::k_batch_pair<float, 2, 16, 8>), grid, dim3(512), 0,
+                                   b->stream, b->d_inst, act, pre, b->nf[q], b->d_t, s0, second,
+                                   (float)eta, b->d_div);
         } else {
-            switch (b->rpt) {
-#define RPT_CASE(R) case R: hipLaunchKernelGGL((gabp::k_batch_iter<double, R>), dim3(grid), dim3(256), 0, b->stream, b->d_inst, b->d_act, b->d_wprefix, b->nact, b->wtotal, b->d_frozen, b->d_t, s, eta, b->d_div); break;
-                RPT_CASE(1) RPT_CASE(2) RPT_CASE(4) default: RPT_CASE(8)
-#undef RPT_CASE
-            }
+            if (q == 0)
+                hipLaunchKernelGGL((gabp::k_batch_pair<double, 1, 4, 4>), grid, dim3(256), 0,
+                                   b->stream, b->d_inst, act, pre, b->nf[q], b->d_t, s0, second,
+                                   eta, b->d_div);
+            else
+                hipLaunchKernelGGL((gabp::k_batch_pair<double, 2, 4, 4>), grid, dim3(256), 0,
+                                   b->stream, b->d_inst, act, pre, b->nf[q], b->d_t, s0, second,
+                                   eta, b->d_div);
         }
         BHIP(b, hipGetLastError());
     }
+    return GABP_OK;
+}
+
+// k iterations of the running set.  Frozen instances run couples of
+// two-iteration launches (4 iterations each) while at least 5 iterations
+// remain, the others single iterations alongside; the last 1 to 4
+// iterations run singly for everyone, so that every instance ends on its
+// two newest iterations in its two buffers.
+gabp_status launch_iters(gabp_batch *b, int k, double eta) {
+    if (b->nact == 0) return GABP_OK;
+    const int couples = (b->pair > 0 && b->nf[0] + b->nf[1] > 0 && k >= 5) ? (k - 1) / 4 : 0;
+    gabp_status st = GABP_OK;
+    int s = 1;
+    for (int c = 0; c < couples && st == GABP_OK; ++c, s += 4) {
+        st = launch_pair(b, s - 1, 0, eta);
+        for (int q = 0; q < 2 && st == GABP_OK; ++q)
+            st = launch_single(b, b->d_actu, b->d_wprefu, b->nu, b->wtotu, s + q, eta);
+        if (st == GABP_OK) st = launch_pair(b, s + 1, 1, eta);
+        for (int q = 2; q < 4 && st == GABP_OK; ++q)
+            st = launch_single(b, b->d_actu, b->d_wprefu, b->nu, b->wtotu, s + q, eta);
+    }
+    for (; s <= k && st == GABP_OK; ++s)
+        st = launch_single(b, b->d_act, b->d_wprefix, b->nact, b->wtotal, s, eta);
+    if (st != GABP_OK) return st;
     hipLaunchKernelGGL(gabp::k_batch_advance, dim3(1), dim3(64), 0, b->stream, b->d_t, k);
     BHIP(b, hipGetLastError());
     return GABP_OK;
@@ -517,7 +651,7 @@ static gabp_status batch_layout(int32_t n, const gabp_instance *inst, int32_t dt
     *tables_off = off;
     // instance table, 5 int lists, 4 uint flag arrays, partials, results
     off = round_up(off + sizeof(BatchInst) * (size_t)n, kAlign);
-    off = round_up(off + sizeof(int) * (size_t)(5 * n + 2), kAlign);
+    off = round_up(off + sizeof(int) * (size_t)lists_ints(n), kAlign);
     off = round_up(off + sizeof(uint32_t) * (size_t)(3 * n + 2), kAlign);
     off = round_up(off + sizeof(double) * 2 * pc, kAlign);
     off = round_up(off + sizeof(double) * 2 * (size_t)n, kAlign);
@@ -573,6 +707,7 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     };
     b->n = n;
     b->dtype = dtype;
+    b->pair = dtype == GABP_F32 ? 16 : 4;   // matches the k_batch_pair instances launched
     b->esize = dtype == GABP_F32 ? 4 : 8;
     b->h = hs;
     b->partial_cap = pc;
@@ -623,7 +758,13 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     b->d_pprefix = b->d_wprefix + n + 1;
     b->d_frozen = b->d_pprefix + n + 1;
     b->d_probe = b->d_frozen + n;
-    off = round_up(off + sizeof(int) * (size_t)(5 * n + 2), kAlign);
+    b->d_actu = b->d_probe + n;
+    b->d_wprefu = b->d_actu + n;
+    b->d_actf[0] = b->d_wprefu + n + 1;
+    b->d_wpreff[0] = b->d_actf[0] + n;
+    b->d_actf[1] = b->d_wpreff[0] + n + 1;
+    b->d_wpreff[1] = b->d_actf[1] + n;
+    off = round_up(off + sizeof(int) * (size_t)lists_ints(n), kAlign);
     b->d_div = (uint32_t *)(b->ws + off);
     b->d_bits = b->d_div + n;
     b->d_t = b->d_bits + n;
@@ -632,9 +773,9 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     b->d_partials = (double *)(b->ws + off);
     off = round_up(off + sizeof(double) * 2 * pc, kAlign);
     b->d_out = (double *)(b->ws + off);
-    // pinned mirror: out[2n], div[n], bits[n], t, lists[5n+2]
+    // pinned mirror: out[2n], div[n], bits[n], t, lists
     const size_t pin_bytes = sizeof(double) * 2 * (size_t)n + sizeof(uint32_t) * (2 * (size_t)n + 2) +
-                             sizeof(int) * (size_t)(5 * n + 2) + 64;
+                             sizeof(int) * (size_t)lists_ints(n) + 64;
     if (hipHostMalloc((void **)&b->p_out, pin_bytes, hipHostMallocDefault) != hipSuccess) {
         b->p_out = nullptr;
         b->err = "pinned host allocation failed";
@@ -787,9 +928,16 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
     if (!b) return GABP_E_INVALID;
     StreamJoin join(b);
     if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
-    if (max_iters < 0 || check_every < 1 || !(rel_tol >= 0) || !(damping > 0.0) ||
+    if (max_iters < 0 || check_every == 0 || !(rel_tol >= 0) || !(damping > 0.0) ||
         !(damping <= 1.0))
-        return bfail(b, GABP_E_INVALID, "need max_iters >= 0, check_every >= 1, rel_tol >= 0, damping in (0, 1]");
+        return bfail(b, GABP_E_INVALID, "need max_iters >= 0, check_every != 0, rel_tol >= 0, damping in (0, 1]");
+    // check_every < 0: adaptive chunks, as gabp_solve's, on the slowest
+    // running instance; powers of two times |check_every|, at most kMaxChunk,
+    // so that few chunk graphs are captured
+    constexpr int kMaxChunk = 1280;
+    const bool adaptive = check_every < 0;
+    const int kmin = adaptive ? -check_every : check_every;
+    int next = kmin;
     int64_t run = 0;
     while (run < max_iters) {
         if (b->lists_dirty) {
@@ -797,7 +945,7 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
             if (st != GABP_OK) return st;
         }
         if (b->nact == 0) break;
-        const int k = (int)std::min<int64_t>(check_every, max_iters - run);
+        const int k = (int)std::min<int64_t>(next, max_iters - run);
         // precision-change probes of instances not yet frozen: compare the
         // two newest buffers right after this chunk, outside the graph
         bool need_probe = false;
@@ -845,6 +993,26 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
             }
         }
         if (changed) b->lists_dirty = true;
+        next = kmin;
+        if (adaptive) {
+            double want = (double)kMaxChunk;
+            for (auto &H : b->h) {
+                if (!H.running) continue;
+                double ki = kmin;
+                if (H.frozen && H.prev_rel > 0 && H.rel < H.prev_rel && H.rel > 0 &&
+                    H.iters > H.prev_iters) {
+                    const double rate = std::log(H.rel / H.prev_rel) / (double)(H.iters - H.prev_iters);
+                    ki = 0.5 * std::log(rel_tol / H.rel) / rate;
+                }
+                want = std::min(want, ki);
+            }
+            while (next * 2 <= kMaxChunk && next * 2 <= want) next *= 2;
+        }
+        for (auto &H : b->h)
+            if (H.running) {
+                H.prev_rel = H.rel;
+                H.prev_iters = H.iters;
+            }
     }
     for (int i = 0; i < b->n; ++i) {
         const InstHost &H = b->h[i];

@@ -19,6 +19,7 @@
 #include "lattice.h"
 #include "numerics.h"
 #include "iter_node.h"
+#include "pair_tile.h"
 
 // Rounding is spelled out: no implicit multiply-add contraction in this file,
 // explicit fused multiply-adds where wanted.  The full iteration and the
@@ -131,55 +132,15 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
     if (bad) *diverged_at = t;
 }
 
-// --------------------------------------------------------------------------
-// Two information-only iterations per pass (temporal blocking).  A
-// workgroup owns a 64 x TH tile.  Step 1 computes iteration t+1 for the tile
-// and for a halo of R = stencil radius nodes around it (inputs from HBM/L2;
-// a halo node only computes the messages it sends into the tile), and leaves
-// in LDS, for every tile node and direction d, its incoming message from
-// the node at + off_d (receiver-indexed, 64 x TH x deg values; the tile
-// nodes' own new messages stay in registers with their gains).  Step 2
-// computes iteration t+2 for the tile from LDS and writes it out.  HBM then
-// sees one read of the inputs and one write of the outputs per two
-// iterations.  Every node goes through theta_update, so the result is bitwise
-// what two single-iteration launches give.  Local position (lx, ly) in
-// [-R, 64 + R) x [-R, TH + R) is global (x0 + lx, y0 + ly), wrapped on
-// periodic axes; positions outside a non-periodic axis are skipped (their
-// edges do not exist), and tile positions past the end of a periodic axis
-// repeat wrapped nodes without being written back.
-// --------------------------------------------------------------------------
-__device__ __forceinline__ void record_divergence(uint32_t *p, uint32_t v) {
-    uint32_t old = atomicCAS(p, 0u, v);
-    while (old != 0u && old > v) {   // keep the earliest iteration
-        const uint32_t prev = atomicCAS(p, old, v);
-        if (prev == old) break;
-        old = prev;
-    }
-}
-
-constexpr int kStrip = 8;   // tile columns per strip of the two-iteration kernel's order
-
-__device__ __forceinline__ int wrap_coord(int v, int n) {
-    v %= n;
-    return v < 0 ? v + n : v;
-}
-
 template <typename T, int ALPHA, int TH, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
-                                                     T *__restrict__ m_out,
-                                                     const T *__restrict__ gain,
-                                                     const T *__restrict__ bw, T eta,
-                                                     uint32_t *__restrict__ diverged_at,
-                                                     uint32_t t) {
+                                                            T *__restrict__ m_out,
+                                                            const T *__restrict__ gain,
+                                                            const T *__restrict__ bw, T eta,
+                                                            uint32_t *__restrict__ diverged_at,
+                                                            uint32_t t) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
-    constexpr int R = ALPHA == 1 ? 1 : 2;
-    constexpr int NT = 64 * WAVES;
-    constexpr int RPT = TH / WAVES;
-    static_assert(TH % WAVES == 0, "tile rows must be a multiple of the wave count");
-    constexpr int LW = 64 + 2 * R;
-    constexpr int NBAND = 2 * R * LW;             // R rows above and below, full width
-    constexpr int NHALO = NBAND + 2 * R * TH;     // plus R columns left and right
-    __shared__ T sin_[DEG][TH][64];               // incoming messages at t+1, receiver-indexed
+    __shared__ T lds[DEG * TH * 64];
     if (*diverged_at != 0u) return;               // uniform across the workgroup
     // Tiles in strip-major order: strips of kStrip tile columns, each walked
     // row by row, and each XCD a contiguous range of that order.  Tiles above
@@ -194,115 +155,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
         ty = r / width;
         tx = strip * kStrip + r % width;
     }
-    const int x0 = tx * 64, y0 = ty * TH;
-    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
-    const bool px = L.bcx == BC_PERIODIC, py = L.bcy == BC_PERIODIC;
-    const bool interior = x0 >= 2 * R && x0 + 64 + 2 * R <= L.nx && y0 >= 2 * R &&
-                          y0 + TH + 2 * R <= L.ny;
-    const T c = (T)L.c, keep = (T)1 - eta;
     bool bad1 = false, bad2 = false;
-    T th1[RPT][DEG], gk[RPT][DEG], bk[RPT];
-
-    // store message (lx, ly) -> (lx, ly) + off_e if its receiver is in the tile
-    auto deliver = [&](int lx, int ly, int e, T v) {
-        const int rx = lx + dir_dx(e), ry = ly + dir_dy(e);
-        if (rx >= 0 && rx < 64 && ry >= 0 && ry < TH) sin_[e ^ 1][ry][rx] = v;
-    };
-
-    // step 1: tile positions (one column per lane, rows w, w + WAVES, ...)
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int ly = w + WAVES * k;
-        int gx = x0 + lane, gy = y0 + ly;
-        T tin[DEG], ot[DEG];
-        bool ok[DEG];
-        bool here = true;
-        if (interior) {
-            theta_gather<T, ALPHA, true>(L, m_in, gain, bw, gx, gy, tin, ot, gk[k], bk[k], ok);
-        } else {
-            if (gx >= L.nx) { if (px) gx = wrap_coord(gx, L.nx); else here = false; }
-            if (gy >= L.ny) { if (py) gy = wrap_coord(gy, L.ny); else here = false; }
-            if (here)
-                theta_gather<T, ALPHA, false>(L, m_in, gain, bw, gx, gy, tin, ot, gk[k], bk[k],
-                                              ok);
-        }
-        if (here) {
-            theta_update<T, DEG>(tin, ot, gk[k], bk[k], c, eta, keep, th1[k]);
-#pragma unroll
-            for (int d = 0; d < DEG; ++d) {
-                deliver(lane, ly, d, th1[k][d]);
-                if (ok[d]) bad1 |= !isfinite(th1[k][d]);
-            }
-        }
-    }
-    // step 1: halo positions
-#pragma unroll 1
-    for (int h = (int)threadIdx.x; h < NHALO; h += NT) {
-        int lx, ly;
-        if (h < NBAND) {
-            const int r = h / LW;
-            lx = h % LW - R;
-            ly = r < R ? r - R : TH + r - R;
-        } else {
-            const int s = h - NBAND, col = s % (2 * R);
-            ly = s / (2 * R);
-            lx = col < R ? col - R : 64 + col - R;
-        }
-        int gx = x0 + lx, gy = y0 + ly;
-        // only the messages this halo node sends into the tile are used
-        bool need[DEG];
-#pragma unroll
-        for (int d = 0; d < DEG; ++d) {
-            const int rx = lx + dir_dx(d), ry = ly + dir_dy(d);
-            need[d] = rx >= 0 && rx < 64 && ry >= 0 && ry < TH;
-        }
-        T tin[DEG], ot[DEG], g[DEG], out[DEG], b;
-        bool ok[DEG];
-        bool here = true;
-        if (interior) {
-            theta_gather_some<T, ALPHA, true>(L, m_in, gain, bw, gx, gy, need, tin, ot, g, b, ok);
-        } else {
-            if (gx < 0 || gx >= L.nx) { if (px) gx = wrap_coord(gx, L.nx); else here = false; }
-            if (gy < 0 || gy >= L.ny) { if (py) gy = wrap_coord(gy, L.ny); else here = false; }
-            if (here)
-                theta_gather_some<T, ALPHA, false>(L, m_in, gain, bw, gx, gy, need, tin, ot, g, b,
-                                                   ok);
-        }
-        if (here) {
-            theta_update<T, DEG>(tin, ot, g, b, c, eta, keep, out);
-#pragma unroll
-            for (int d = 0; d < DEG; ++d) {
-                if (!need[d]) continue;
-                sin_[d ^ 1][ly + dir_dy(d)][lx + dir_dx(d)] = out[d];
-                if (ok[d]) bad1 |= !isfinite(out[d]);
-            }
-        }
-    }
-    __syncthreads();
-    // step 2: the tile's own nodes, from LDS
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int ly = w + WAVES * k;
-        const int x = x0 + lane, y = y0 + ly;
-        if (x >= L.nx || y >= L.ny) continue;
-        const uint32_t i = (uint32_t)(y * L.pitch + x);
-        T tin[DEG], out[DEG];
-        bool ok[DEG];
-#pragma unroll
-        for (int d = 0; d < DEG; ++d) {
-            int xn, yn;
-            ok[d] = interior || neighbour(L, x, y, d, xn, yn);
-            tin[d] = ok[d] ? sin_[d][ly][lane] : (T)0;
-        }
-        theta_update<T, DEG>(tin, th1[k], gk[k], bk[k], c, eta, keep, out);
-#pragma unroll
-        for (int d = 0; d < DEG; ++d) {
-            if (ok[d]) {
-                bad2 |= !isfinite(out[d]);
-                (m_out + (size_t)(DEG + d) * L.plane)[i] = out[d];
-            }
-        }
-    }
+    pair_tile<T, ALPHA, TH, WAVES>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 

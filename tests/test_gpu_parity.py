@@ -550,6 +550,28 @@ def test_batch_solve_matches_single_solves(G, oracle_mod):
         assert torch.equal(mu, mref)
 
 
+def test_batch_adaptive_chunks_converge_and_stay_bitwise(G):
+    """check_every < 0 grows the chunks once every running instance froze;
+    every instance still reaches the tolerance, and its messages equal a lone
+    context's after the same number of iterations, bit for bit."""
+    probs = _mixed_problems("f32", 6)
+    b = G.gabp_batch_create(probs)
+    st, its, rels, sts = G.gabp_batch_solve(b, 60000, 0.5, 1e-6, -10)
+    assert st == G.GABP_OK
+    fixed = G.gabp_batch_create(probs)
+    _, its_fixed, _, _ = G.gabp_batch_solve(fixed, 60000, 0.5, 1e-6, 10)
+    for i, p in enumerate(probs):
+        assert sts[i] == G.GABP_OK and rels[i] <= 1e-6, (i, sts[i], rels[i])
+        assert its[i] >= its_fixed[i]
+        ctx = G.gabp_create_problem(p)
+        G.gabp_iterate(ctx, its[i], 0.5)
+        pa, ia = G.gabp_batch_get_messages(b, i)
+        pb, ib = G.gabp_get_messages(ctx)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib), i
+    with pytest.raises(G.GabpError):
+        G.gabp_batch_solve(b, 10, 0.5, 1e-6, 0)
+
+
 def test_batch_autotune_keeps_results(G):
     probs = _mixed_problems("f32", 5)
     a = G.gabp_batch_create(probs)
