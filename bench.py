@@ -46,7 +46,7 @@ def edge_count(nx, ny, alpha, bcx, bcy):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("iter.hip", "iter_node.h", "numerics.h", "lattice.h"):
+    for f in ("iter.hip", "iter_node.h", "pair_tile.h", "numerics.h", "lattice.h"):
         with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -384,7 +384,7 @@ def main(argv=None):
         ms1 = event_ms(lambda: G.gabp_iterate(ctx, ITERS_PER_STEP, prob.damping), 3) / ITERS_PER_STEP
         kernels["theta"] = {"iter_ms": ms1, "algorithmic_bytes": alg_theta,
                             "gbps": alg_theta / (ms1 * 1e-3) / 1e9, "rows_per_thread": rpt}
-        for p2 in ((4, 8, 16) if prob.dtype == "f32" else (4,)):
+        for p2 in ((4, 8, 16, 32) if prob.dtype == "f32" else (4,)):
             G.gabp_set_tile(ctx, rpt, p2)
             m = 10
             ms_call = event_ms(lambda: G.gabp_iterate(ctx, 2 * m + 1, prob.damping), 3)

@@ -202,19 +202,20 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
  * twice over, time them with HIP events on the context's stream, and keep
  * the fastest for this context and for later contexts of the same prior
  * order, dtype and size class in this process.  Once the precision messages
- * have frozen, the two-iteration kernel (tile heights 4, 8 and 16 in FP32, 4
- * in FP64; see gabp_set_tile) is timed against the best of those, twice
- * over, and kept if faster.  Every shape computes bitwise-identical
+ * have frozen, the two-iteration kernel (tile heights 4, 8, 16 and 32 in
+ * FP32, 4 in FP64; see gabp_set_tile) is timed against the best of those,
+ * twice over, and kept if faster.  Every shape computes bitwise-identical
  * messages, so these are ordinary iterations: the counter advances by
- * 1 + 8 * trials, plus 6 * trials (FP32) or 2 * trials (FP64) when frozen.  *chosen (may be
+ * 1 + 8 * trials, plus 8 * trials (FP32) or 2 * trials (FP64) when frozen.  *chosen (may be
  * NULL) receives the rows per thread.  Synchronises. */
 gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen);
 
 /* Tile configuration of a context's iteration kernels, a tuning knob that
  * never changes results.  rows_per_thread (1, 2, 4 or 8): rows each thread
  * of a 64-wide, 256-thread tile walks, for the single-iteration kernels.
- * pair_rows (0, 4, or 8 and 16 for FP32 only): once the precision messages have
- * frozen, gabp_iterate runs two information-only iterations per launch on
+ * pair_rows (0, 4, or 8, 16 and 32 for FP32 only): once the precision
+ * messages have frozen, gabp_iterate runs two information-only iterations per
+ * launch on
  * 64 x pair_rows tiles (iteration t+1 of the tile and a halo of the stencil
  * radius kept in LDS, iteration t+2 written out: one HBM pass per two
  * iterations) and the last one or two iterations of each call singly;

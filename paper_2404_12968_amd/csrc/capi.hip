@@ -142,7 +142,7 @@ std::mutex g_tune_mu;
 std::map<long long, std::pair<int, int>> g_tune;
 
 bool pair_ok(int dtype, int pair) {
-    return pair == 0 || pair == 4 || ((pair == 8 || pair == 16) && dtype == GABP_F32);
+    return pair == 0 || pair == 4 || ((pair == 8 || pair == 16 || pair == 32) && dtype == GABP_F32);
 }
 
 long long tune_key(const gabp_ctx *ctx) {
@@ -698,7 +698,7 @@ gabp_status gabp_set_tile(gabp_ctx *ctx, int32_t rows_per_thread, int32_t pair_r
     for (int r : gabp::kRptChoices) rpt_ok |= r == rows_per_thread;
     if (!rpt_ok) return fail(ctx, GABP_E_INVALID, "rows_per_thread must be 1, 2, 4 or 8");
     if (!pair_ok(ctx->dtype, pair_rows))
-        return fail(ctx, GABP_E_INVALID, "pair_rows must be 0, 4 or (FP32 only) 8 or 16");
+        return fail(ctx, GABP_E_INVALID, "pair_rows must be 0, 4 or (FP32 only) 8, 16 or 32");
     ctx->rpt = rows_per_thread;
     ctx->pair = pair_rows;
     return GABP_OK;

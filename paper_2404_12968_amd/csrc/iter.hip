@@ -232,12 +232,13 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
     return hipGetLastError();
 }
 
-// tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8
+// tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8,
+// 32 rows on 16
 template <typename T, int ALPHA, int TH>
 static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
                             const void *bw, double eta, uint32_t *flag, uint32_t t,
                             hipStream_t s) {
-    constexpr int WAVES = TH == 4 ? 4 : 8;
+    constexpr int WAVES = TH == 4 ? 4 : TH == 32 ? 16 : 8;
     const int tiles = L.tiles_x * ((L.ny + TH - 1) / TH);
     hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(tiles), dim3(64 * WAVES), 0, s,
                        L, (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
@@ -249,11 +250,13 @@ hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m
                               uint32_t t, hipStream_t s) {
     if (dtype == 0) {
         if (L.alpha == 1) {
-            if (th == 16) launch_theta2_k<float, 1, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            if (th == 32) launch_theta2_k<float, 1, 32>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            else if (th == 16) launch_theta2_k<float, 1, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
             else if (th == 8) launch_theta2_k<float, 1, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s);
             else launch_theta2_k<float, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
         } else {
-            if (th == 16) launch_theta2_k<float, 2, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            if (th == 32) launch_theta2_k<float, 2, 32>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            else if (th == 16) launch_theta2_k<float, 2, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
             else if (th == 8) launch_theta2_k<float, 2, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s);
             else launch_theta2_k<float, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
         }

@@ -432,6 +432,8 @@ def _freeze(G, ctx):
     ("f32", 2, 8, 67, 40, I.BC_DIRICHLET, I.BC_PERIODIC),
     ("f32", 2, 16, 200, 17, I.BC_PERIODIC, I.BC_PERIODIC),
     ("f32", 2, 16, 150, 70, I.BC_NEUMANN, I.BC_DIRICHLET),
+    ("f32", 2, 32, 140, 75, I.BC_PERIODIC, I.BC_NEUMANN),
+    ("f32", 1, 32, 70, 40, I.BC_DIRICHLET, I.BC_PERIODIC),
     ("f32", 2, 4, 5, 70, I.BC_NEUMANN, I.BC_PERIODIC),
     ("f32", 1, 8, 129, 45, I.BC_PERIODIC, I.BC_DIRICHLET),
     ("f32", 1, 16, 100, 50, I.BC_NEUMANN, I.BC_PERIODIC),
@@ -476,13 +478,13 @@ def test_autotune_after_freezing_times_the_two_iteration_kernel(G):
     _freeze(G, a)
     t0 = G.gabp_iteration_count(a)[0]
     G.gabp_autotune(a, 5, 0.5)
-    assert G.gabp_iteration_count(a)[0] == t0 + 1 + 8 * 5 + 6 * 5
+    assert G.gabp_iteration_count(a)[0] == t0 + 1 + 8 * 5 + 8 * 5
     rpt, pair = G.gabp_get_tile(a)
-    assert rpt in (1, 2, 4, 8) and pair in (0, 4, 8, 16)
+    assert rpt in (1, 2, 4, 8) and pair in (0, 4, 8, 16, 32)
     b = G.gabp_create_problem(prob)
     G.gabp_set_tile(b, 4, 0)
     _freeze(G, b)
-    G.gabp_iterate(b, 1 + 8 * 5 + 6 * 5, 0.5)
+    G.gabp_iterate(b, 1 + 8 * 5 + 8 * 5, 0.5)
     assert torch.equal(G.gabp_get_messages(a)[1], G.gabp_get_messages(b)[1])
     with pytest.raises(G.GabpError):
         G.gabp_set_tile(a, 3, 0)
