@@ -214,14 +214,13 @@ gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t
  * never changes results.  rows_per_thread (1, 2, 4 or 8): rows each thread
  * of a 64-wide, 256-thread tile walks, for the single-iteration kernels.
  * pair_rows (0, 4, or 8, 16 and 32 for FP32 only): once the precision
- * messages have frozen, gabp_iterate runs two information-only iterations per
- * launch on
- * 64 x pair_rows tiles (iteration t+1 of the tile and a halo of the stencil
- * radius kept in LDS, iteration t+2 written out: one HBM pass per two
- * iterations) and the last one or two iterations of each call singly;
- * 0 = always one iteration per launch.  Default: rows 4, pair 8 (FP32) or 4
- * (FP64), or what the autotuner chose for this problem class.  INVALID for
- * other values. */
+ * messages have frozen, gabp_iterate runs two information-only iterations
+ * per launch on 64 x pair_rows tiles (iteration t+1 of the tile and a halo of
+ * the stencil radius kept in LDS, iteration t+2 written out: one HBM pass
+ * per two iterations) and the last one or two iterations of each call
+ * singly; 0 = always one iteration per launch.  Default: rows 4, pair 8
+ * (FP32) or 4 (FP64), or what the autotuner chose for this problem class.
+ * INVALID for other values. */
 gabp_status gabp_set_tile(gabp_ctx *ctx, int32_t rows_per_thread, int32_t pair_rows);
 gabp_status gabp_get_tile(const gabp_ctx *ctx, int32_t *rows_per_thread, int32_t *pair_rows);
 
