@@ -379,6 +379,32 @@ def test_global8192_sampled_windows_match_oracle(G, oracle_mod):
         assert rel_l2(lam_g[sd[sel], sy[sel] - (wy - y0), sx[sel] - m], og.lam[e[sel]]) <= 1e-5
 
 
+def test_global8192_two_iteration_kernel_is_bitwise_identical(G):
+    """The 8192 x 4096 workload in the configuration the benchmark times
+    (16-row two-iteration tiles once the precision messages froze): every
+    message equals the single-iteration kernel's after the same iterations."""
+    prob = I.global8192()
+    a = G.gabp_create_problem(prob)
+    b = G.gabp_create_problem(prob)
+    G.gabp_set_tile(a, 1, 16)
+    G.gabp_set_tile(b, 1, 0)
+    fa, fb = _freeze(G, a), _freeze(G, b)
+    assert fa == fb > 0
+    for n in (21, 2):
+        G.gabp_iterate(a, n, prob.damping)
+        G.gabp_iterate(b, n, prob.damping)
+    assert G.gabp_iteration_count(a) == G.gabp_iteration_count(b)
+    pa, ia = G.gabp_get_messages(a)
+    pb, ib = G.gabp_get_messages(b)
+    assert torch.equal(pa, pb)
+    del pa, pb
+    assert torch.equal(ia, ib)
+    del ia, ib
+    assert G.gabp_residual(a) == G.gabp_residual(b)
+    G.gabp_destroy(a)
+    G.gabp_destroy(b)
+
+
 @pytest.mark.parametrize("dtype,alpha", [("f32", 2), ("f64", 1), ("f32", 1)])
 def test_tile_shapes_are_bitwise_identical(G, dtype, alpha):
     """The autotuner runs real iterations with every tile shape; the result
