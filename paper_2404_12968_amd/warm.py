@@ -177,7 +177,7 @@ def solve_training_set(problems: Sequence[I.Problem], max_iters: int = 300000,
     ts = TrainingSet()
     t0 = time.time()
     b = G.gabp_batch_create(list(problems), device=device)
-    st, its, rels, sts = G.gabp_batch_solve(b, max_iters, 0.5, rel_tol, 10)
+    st, its, rels, sts = G.gabp_batch_solve(b, max_iters, 0.5, rel_tol, -10)
     torch.cuda.synchronize()
     log(f"[warm] solved {len(problems)} problems in {time.time() - t0:.1f}s: "
         f"{int((sts == G.GABP_OK).sum())} converged, iterations median {int(np.median(its))}")
