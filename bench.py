@@ -260,6 +260,8 @@ def main(argv=None):
     ap.add_argument("--warm-instances", type=int, default=3)
     ap.add_argument("--table1-truths", type=int, default=3,
                     help="ground truths per Table 1 configuration")
+    ap.add_argument("--no-table1", action="store_true",
+                    help="skip the paper's Table 1 leg (nine grid/density configurations)")
     ap.add_argument("--no-multigrid", action="store_true",
                     help="skip the multigrid time-to-tolerance leg")
     ap.add_argument("--print-digest", action="store_true",
@@ -475,6 +477,13 @@ def main(argv=None):
                                                    out["multigrid"]["seconds"])
     if not args.no_warm:
         out["warm_start"] = bench_warm(I, args.warm_instances)
+    if not args.no_table1:
+        t1 = bench_table1(G, I, torch, args)
+        out["table1"] = {"seconds": t1["value"], "paper_seconds_rtx3090": t1["value"] / t1["vs_baseline"],
+                         "config": t1["config"]["workload"], "truths_per_config": args.table1_truths,
+                         "rows": [{k: r[k] for k in ("grid", "observed", "seconds", "rmse",
+                                                      "paper_mp_seconds_rtx3090", "paper_mp_rmse",
+                                                      "paper_exact_rmse")} for r in t1["rows"]]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
