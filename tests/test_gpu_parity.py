@@ -600,6 +600,27 @@ def test_batch_adaptive_chunks_converge_and_stay_bitwise(G):
         G.gabp_batch_solve(b, 10, 0.5, 1e-6, 0)
 
 
+def test_batch256_full_size_sampled_instances_bitwise(G):
+    """The 256-instance workload in the benchmark's configuration (adaptive
+    chunks, FP32, to 1e-6): every instance converges, and sampled instances
+    (the smallest, a median one, the slowest) equal lone contexts run for the
+    same number of iterations, bit for bit."""
+    probs = I.batch256()
+    b = G.gabp_batch_create(probs)
+    st, its, rels, sts = G.gabp_batch_solve(b, 300000, 0.5, 1e-6, -10)
+    assert st == G.GABP_OK and np.all(sts == G.GABP_OK) and np.all(rels <= 1e-6)
+    sizes = np.array([p.n for p in probs])
+    picks = {int(np.argmin(sizes)), int(np.argsort(its)[len(its) // 2]), int(np.argmax(its))}
+    for i in sorted(picks):
+        ctx = G.gabp_create_problem(probs[i])
+        G.gabp_iterate(ctx, int(its[i]), 0.5)
+        pa, ia = G.gabp_batch_get_messages(b, i)
+        pb, ib = G.gabp_get_messages(ctx)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib), (i, its[i])
+        G.gabp_destroy(ctx)
+    G.gabp_batch_destroy(b)
+
+
 def test_batch_autotune_keeps_results(G):
     probs = _mixed_problems("f32", 5)
     a = G.gabp_batch_create(probs)
