@@ -252,8 +252,8 @@ def main(argv=None):
                     choices=["global8192", "tracks2048", "batch256", "table1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--solve", action="store_true",
-                    help="also time a cold solve to the workload's tolerance")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the cold solve to the workload's tolerance")
     ap.add_argument("--solve-max-iters", type=int, default=200000)
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
@@ -460,7 +460,7 @@ def main(argv=None):
                          / 1e9),
                      "traffic": traffic},
     }
-    if args.solve:
+    if not args.no_solve:
         ctx2 = G.gabp_create_problem(prob, device=dev)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
