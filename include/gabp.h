@@ -145,9 +145,12 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping);
  * iterations; check_every < 0 checks adaptively: every |check_every|
  * iterations until the precision messages froze, then after half the
  * iterations the observed geometric rate predicts to rel_tol (at least
- * |check_every|, at most 2000).  iters_done (total iterations of the
- * context) and rel_residual (last residual) may be NULL.  Synchronises the
- * stream at every check. */
+ * |check_every|, at most 2000; with graphs on, rounded down to
+ * |check_every| * 2^j).  Each chunk of iterations is recorded once as a
+ * hipGraph (per chunk length, starting buffer, phase, tile shape and
+ * damping) and replayed (see gabp_set_graph).  iters_done (total iterations
+ * of the context) and rel_residual (last residual) may be NULL.
+ * Synchronises the stream at every check. */
 gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double rel_tol,
                        int32_t check_every, int64_t *iters_done, double *rel_residual);
 
@@ -209,6 +212,16 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
  * 1 + 8 * trials, plus 8 * trials (FP32) or 2 * trials (FP64) when frozen.  *chosen (may be
  * NULL) receives the rows per thread.  Synchronises. */
 gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen);
+
+/* Chunk graphs of gabp_solve and gabp_solve_early_stop (Alg. 2, Iterate MP
+ * Until Convergence: chunks of iterations between checks): enable != 0
+ * (default) records each chunk of at least 2 iterations, once the context has
+ * run 2 iterations, as a hipGraph on an internal stream and replays it on the
+ * context's stream (iteration numbers come from a device counter the graph
+ * advances); 0 launches every kernel directly and drops recorded graphs.
+ * Results are bitwise identical either way.  gabp_iterate always launches
+ * directly. */
+gabp_status gabp_set_graph(gabp_ctx *ctx, int32_t enable);
 
 /* Tile configuration of a context's iteration kernels, a tuning knob that
  * never changes results.  rows_per_thread (1, 2, 4 or 8): rows each thread

@@ -69,6 +69,20 @@ struct gabp_ctx {
         int buf, pairs, singles;
     };
     std::vector<LaunchRun> runs;
+    // captured chunks: iterations are numbered from the device counter
+    // flags[3] (host copy tbase); graphs are recorded on a side stream and
+    // replayed on the context's stream
+    uint32_t tbase = 0;
+    bool graphs = true;
+    hipStream_t side = nullptr;
+    struct Chunk {
+        int32_t k;
+        int cur, frozen, rpt, pair;
+        double eta;
+        hipGraphExec_t exec;
+        int pairs, singles;
+    };
+    std::vector<Chunk> chunks;
     int64_t iter = 0;
     bool diverged = false;
     bool prev_valid = false;       // the other buffer holds m^{iter-1}
@@ -135,6 +149,11 @@ gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
 }
 
 const void *cur_msgs(const gabp_ctx *ctx) { return ctx->msg[ctx->cur]; }
+
+void drop_chunks(gabp_ctx *ctx) {
+    for (auto &c : ctx->chunks) (void)hipGraphExecDestroy(c.exec);
+    ctx->chunks.clear();
+}
 
 // Autotuner results (rows per thread, pair tile height), process-wide,
 // keyed by (alpha, dtype, size class).
@@ -357,59 +376,159 @@ void gabp_destroy(gabp_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    drop_chunks(ctx);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->host) (void)hipHostFree(ctx->host);
     delete ctx;
 }
 
-gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
-    gabp_status st = ctx_ok(ctx);
-    if (st != GABP_OK) return st;
+namespace {
+
+// Issue n iterations on stream s, starting from iteration iter0 held in
+// buffer cur0, with iteration numbers relative to the device counter's value
+// tbase when they run.  Frozen contexts run two iterations per launch while
+// at least three remain and the last one or two singly, so that the two
+// buffers end on m^{t-1} and m^t.  Touches no context state; reports the
+// launch counts and whether the t = 2 reference change was taken.
+gabp_status enqueue_iters(gabp_ctx *ctx, int32_t n, double damping, hipStream_t s, int64_t iter0,
+                          int cur0, uint32_t tbase, int &pairs, int &singles, bool &ref) {
+    const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
+    int64_t it = iter0;
+    int cur = cur0;
+    pairs = singles = 0;
+    ref = false;
+    int32_t k = 0;
+    while (k < n) {
+        const void *src = ctx->msg[cur];
+        void *dst = ctx->msg[cur ^ 1];
+        if (ctx->frozen && ctx->pair > 0 && it >= 2 && n - k >= 3) {
+            GABP_HIP(ctx, gabp::launch_iter_theta2(dt, ctx->pair, ctx->L, src, dst, ctx->gain,
+                                                   ctx->b_w, damping, ctx->flags, ctx->flags + 3,
+                                                   (uint32_t)(it - tbase), s));
+            it += 2;
+            k += 2;
+            ++pairs;
+        } else {
+            const int64_t t = it + 1;
+            if (ctx->frozen)
+                GABP_HIP(ctx, gabp::launch_iter_theta(dt, ctx->rpt, ctx->L, src, dst, ctx->gain,
+                                                      ctx->b_w, damping, ctx->flags,
+                                                      ctx->flags + 3, (uint32_t)(t - tbase), s));
+            else
+                GABP_HIP(ctx, gabp::launch_iter(dt, ctx->rpt, ctx->L, src, dst, ctx->adiag_w,
+                                                ctx->b_w, damping, ctx->flags, ctx->flags + 3,
+                                                (uint32_t)(t - tbase), s));
+            it = t;
+            ++k;
+            ++singles;
+            if (t == 2) {
+                const int64_t m = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
+                GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[0], ctx->msg[1], m,
+                                                      ctx->partials, kNumPartials, ctx->red + 4,
+                                                      s));
+                ref = true;
+            }
+        }
+        cur ^= 1;
+    }
+    return GABP_OK;
+}
+
+// Adaptive chunk lengths as kmin * 2^j, so that few chunk graphs are recorded.
+int64_t quantize_chunk(int64_t next, int64_t kmin) {
+    int64_t q = kmin;
+    while (q * 2 <= next) q *= 2;
+    return q;
+}
+
+// Context state after n iterations issued by enqueue_iters.
+void advance_state(gabp_ctx *ctx, int32_t n, int pairs, int singles, bool ref) {
+    ctx->runs.push_back({ctx->iter, ctx->cur, pairs, singles});
+    ctx->iter += n;
+    ctx->cur ^= (pairs + singles) & 1;
+    if (ref) ctx->have_ref = true;
+    if (n > 0) ctx->prev_valid = true;
+}
+
+gabp_status check_iterate_args(gabp_ctx *ctx, int32_t n_iters, double damping) {
     if (n_iters < 0) return fail(ctx, GABP_E_INVALID, "n_iters must be >= 0");
     if (!(damping > 0.0) || !(damping <= 1.0))
         return fail(ctx, GABP_E_INVALID, "damping must be in (0, 1]");
     if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
     if (ctx->iter + n_iters >= (int64_t)UINT32_MAX)
         return fail(ctx, GABP_E_INVALID, "iteration counter overflow");
-    const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
-    ctx->runs.push_back({ctx->iter, ctx->cur, 0, 0});
-    int32_t k = 0;
-    while (k < n_iters) {
-        const void *src = ctx->msg[ctx->cur];
-        void *dst = ctx->msg[ctx->cur ^ 1];
-        if (ctx->frozen && ctx->pair > 0 && ctx->iter >= 2 && n_iters - k >= 3) {
-            // two iterations per launch; the last one or two iterations of a
-            // call run singly so that the buffers end on m^{t-1} and m^t
-            GABP_HIP(ctx, gabp::launch_iter_theta2(dt, ctx->pair, ctx->L, src, dst, ctx->gain,
-                                                   ctx->b_w, damping, ctx->flags,
-                                                   (uint32_t)ctx->iter, ctx->stream));
-            ctx->iter += 2;
-            k += 2;
-            ctx->cur ^= 1;
-            ++ctx->runs.back().pairs;
-            continue;
-        }
-        const int64_t t = ctx->iter + 1;
-        if (ctx->frozen)
-            GABP_HIP(ctx, gabp::launch_iter_theta(dt, ctx->rpt, ctx->L, src, dst, ctx->gain,
-                                                  ctx->b_w, damping, ctx->flags, (uint32_t)t,
-                                                  ctx->stream));
-        else
-            GABP_HIP(ctx, gabp::launch_iter(dt, ctx->rpt, ctx->L, src, dst, ctx->adiag_w,
-                                            ctx->b_w, damping, ctx->flags, (uint32_t)t,
-                                            ctx->stream));
-        ctx->iter = t;
-        ctx->cur ^= 1;
-        ++ctx->runs.back().singles;
-        ++k;
-        if (t == 2) {
-            const int64_t n = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
-            GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[0], ctx->msg[1], n, ctx->partials,
-                                                  kNumPartials, ctx->red + 4, ctx->stream));
-            ctx->have_ref = true;
-        }
+    return GABP_OK;
+}
+
+// k iterations as one captured graph (recorded once per chunk length,
+// starting buffer, phase, tile shape and damping; replayed after), else
+// eagerly.  The graph ends by advancing the device iteration counter.
+gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping) {
+    gabp_status st = check_iterate_args(ctx, k, damping);
+    if (st != GABP_OK) return st;
+    if (!ctx->graphs || k < 2 || ctx->iter < 2) return gabp_iterate(ctx, k, damping);
+    if (ctx->tbase != (uint32_t)ctx->iter) {
+        GABP_HIP(ctx, gabp::launch_set_u32(ctx->flags + 3, (uint32_t)ctx->iter, ctx->stream));
+        ctx->tbase = (uint32_t)ctx->iter;
     }
-    if (n_iters > 0) ctx->prev_valid = true;
+    gabp_ctx::Chunk *c = nullptr;
+    for (auto &e : ctx->chunks)
+        if (e.k == k && e.cur == ctx->cur && e.frozen == (int)ctx->frozen && e.rpt == ctx->rpt &&
+            e.pair == ctx->pair && e.eta == damping)
+            c = &e;
+    if (!c) {
+        if (ctx->chunks.size() >= 16) drop_chunks(ctx);
+        if (!ctx->side)
+            GABP_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        gabp_ctx::Chunk e{k, ctx->cur, (int)ctx->frozen, ctx->rpt, ctx->pair, damping, nullptr, 0, 0};
+        bool ref = false;
+        GABP_HIP(ctx, hipStreamBeginCapture(ctx->side, hipStreamCaptureModeThreadLocal));
+        // relative numbering: the counter holds the chunk's first iteration
+        st = enqueue_iters(ctx, k, damping, ctx->side, ctx->iter, ctx->cur, (uint32_t)ctx->iter,
+                           e.pairs, e.singles, ref);
+        if (st == GABP_OK && gabp::launch_add_u32(ctx->flags + 3, (uint32_t)k, ctx->side) != hipSuccess)
+            st = fail(ctx, GABP_E_DEVICE, "capturing the counter advance failed");
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->side, &g);
+        if (st != GABP_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (ec != hipSuccess || !g) return fail(ctx, GABP_E_DEVICE, "hipStreamEndCapture failed");
+        const hipError_t ei = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return fail(ctx, GABP_E_DEVICE, "hipGraphInstantiate failed");
+        ctx->chunks.push_back(e);
+        c = &ctx->chunks.back();
+    }
+    GABP_HIP(ctx, hipGraphLaunch(c->exec, ctx->stream));
+    ctx->tbase += (uint32_t)k;
+    advance_state(ctx, k, c->pairs, c->singles, false);
+    return GABP_OK;
+}
+
+}  // namespace
+
+gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    st = check_iterate_args(ctx, n_iters, damping);
+    if (st != GABP_OK) return st;
+    int pairs = 0, singles = 0;
+    bool ref = false;
+    st = enqueue_iters(ctx, n_iters, damping, ctx->stream, ctx->iter, ctx->cur, ctx->tbase, pairs,
+                       singles, ref);
+    if (st != GABP_OK) return st;
+    advance_state(ctx, n_iters, pairs, singles, ref);
+    return GABP_OK;
+}
+
+gabp_status gabp_set_graph(gabp_ctx *ctx, int32_t enable) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    ctx->graphs = enable != 0;
+    if (!ctx->graphs) drop_chunks(ctx);
     return GABP_OK;
 }
 
@@ -465,7 +584,7 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
     st = GABP_E_NOT_CONVERGED;
     while (run < max_iters) {
         const int32_t k = (int32_t)std::min<int64_t>(next, max_iters - run);
-        gabp_status s1 = gabp_iterate(ctx, k, damping);
+        gabp_status s1 = run_chunk(ctx, k, damping);
         if (s1 != GABP_OK) {
             st = s1;
             break;
@@ -491,6 +610,7 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
             const double rate = std::log(rel / prev_rel) / (double)(ctx->iter - prev_t);
             const double need = std::log(rel_tol / rel) / rate;   // iterations to rel_tol
             next = std::max<int64_t>(kmin, std::min<int64_t>(kMaxInterval, (int64_t)(0.5 * need)));
+            if (ctx->graphs) next = quantize_chunk(next, kmin);
         }
         prev_rel = rel;
         prev_t = ctx->iter;
@@ -525,7 +645,7 @@ gabp_status gabp_solve_early_stop(gabp_ctx *ctx, int64_t max_iters, double dampi
     st = GABP_E_NOT_CONVERGED;
     while (run < max_iters) {
         const int32_t k = (int32_t)std::min<int64_t>(next, max_iters - run);
-        gabp_status s1 = gabp_iterate(ctx, k, damping);
+        gabp_status s1 = run_chunk(ctx, k, damping);
         if (s1 != GABP_OK) {
             st = s1;
             break;
@@ -549,6 +669,7 @@ gabp_status gabp_solve_early_stop(gabp_ctx *ctx, int64_t max_iters, double dampi
             const double rate = std::log(ratio / prev) / (double)(ctx->iter - prev_t);
             const double need = std::log(tau / ratio) / rate;
             next = std::max<int64_t>(kmin, std::min<int64_t>(kMaxInterval, (int64_t)(0.5 * need)));
+            if (ctx->graphs) next = quantize_chunk(next, kmin);
         }
         if (!ctx->frozen && adaptive) {
             // a residual check is what detects frozen precision messages

@@ -12,21 +12,29 @@ namespace gabp {
 // rpt: rows per thread of the iteration kernel's tile (1, 2, 4 or 8); every
 // choice gives bitwise-identical results.
 constexpr int kRptChoices[] = {1, 2, 4, 8};
+// The iteration kernels number their iterations t = *t_base + t_off (a
+// device counter, so that a captured graph numbers replays correctly); flag
+// receives the first diverged iteration.
 hipError_t launch_iter(int dtype, int rpt, const Lattice &L, const void *m_in, void *m_out,
                        const void *adiag, const void *bw, double eta, uint32_t *flag,
-                       uint32_t t, hipStream_t s);
+                       const uint32_t *t_base, uint32_t t_off, hipStream_t s);
 // Information-only iteration with precomputed edge gains (after the
 // precision messages froze), the gain set-up and a bitwise-change test.
 hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m_in,
                              void *m_out, const void *gain, const void *bw, double eta,
-                             uint32_t *flag, uint32_t t, hipStream_t s);
+                             uint32_t *flag, const uint32_t *t_base, uint32_t t_off,
+                             hipStream_t s);
 // Two information-only iterations (t+1 and t+2) per launch on 64 x th tiles
 // (th = 4, 8, 16 or 32 for FP32, 4 for FP64); m_in and m_out must differ.
 // Bitwise equal to two launch_iter_theta calls.
 constexpr int kPairChoicesF32[] = {4, 8, 16, 32};
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
                               const void *gain, const void *bw, double eta, uint32_t *flag,
-                              uint32_t t, hipStream_t s);
+                              const uint32_t *t_base, uint32_t t_off, hipStream_t s);
+// Device counter helpers for captured chunks (kernels, not memsets, so that
+// they may sit in a graph): *p = v, and *p += k.
+hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s);
+hipError_t launch_add_u32(uint32_t *p, uint32_t k, hipStream_t s);
 hipError_t launch_gain(int dtype, const Lattice &L, const void *m, const void *adiag, void *gain,
                        hipStream_t s);
 hipError_t launch_bits_differ(int dtype, const void *a, const void *b, int64_t n,

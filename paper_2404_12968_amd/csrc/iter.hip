@@ -37,8 +37,9 @@ __global__ __launch_bounds__(256) void k_iter_direct(Lattice L, const T *__restr
                                                      const T *__restrict__ adiag,
                                                      const T *__restrict__ bw, T eta,
                                                      uint32_t *__restrict__ diverged_at,
-                                                     uint32_t t) {
+                                                     const uint32_t *__restrict__ t_base, uint32_t t_off) {
     if (*diverged_at != 0u) return;
+    const uint32_t t = *t_base + t_off;   // this iteration's number
     constexpr int TH = 4 * RPT;
     const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
@@ -108,8 +109,9 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
                                                     const T *__restrict__ gain,
                                                     const T *__restrict__ bw, T eta,
                                                     uint32_t *__restrict__ diverged_at,
-                                                    uint32_t t) {
+                                                    const uint32_t *__restrict__ t_base, uint32_t t_off) {
     if (*diverged_at != 0u) return;
+    const uint32_t t = *t_base + t_off;   // this iteration's number
     constexpr int TH = 4 * RPT;
     const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
@@ -138,10 +140,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
                                                             const T *__restrict__ gain,
                                                             const T *__restrict__ bw, T eta,
                                                             uint32_t *__restrict__ diverged_at,
-                                                            uint32_t t) {
+                                                            const uint32_t *__restrict__ t_base, uint32_t t_off) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
     __shared__ T lds[DEG * TH * 64];
     if (*diverged_at != 0u) return;               // uniform across the workgroup
+    const uint32_t t = *t_base + t_off;           // the iteration the launch starts from
     // Tiles in strip-major order: strips of kStrip tile columns, each walked
     // row by row, and each XCD a contiguous range of that order.  Tiles above
     // and below then run close together on one XCD and share their halo rows
@@ -166,68 +169,70 @@ static inline int tiles_of(const Lattice &L) {
 
 template <typename T, int ALPHA, int RPT>
 static void launch_iter_k(const Lattice &L, const void *m_in, void *m_out, const void *adiag,
-                          const void *bw, double eta, uint32_t *flag, uint32_t t, hipStream_t s) {
+                          const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
+                          uint32_t t_off, hipStream_t s) {
     const int tiles = L.tiles_x * ((L.ny + 4 * RPT - 1) / (4 * RPT));
     hipLaunchKernelGGL((k_iter_direct<T, ALPHA, RPT>), dim3(tiles), dim3(256), 0, s, L,
                        (const T *)m_in, (T *)m_out, (const T *)adiag, (const T *)bw, (T)eta, flag,
-                       t);
+                       t_base, t_off);
 }
 
 template <typename T, int ALPHA>
 static void launch_iter_a(int rpt, const Lattice &L, const void *m_in, void *m_out,
                           const void *adiag, const void *bw, double eta, uint32_t *flag,
-                          uint32_t t, hipStream_t s) {
+                          const uint32_t *t_base, uint32_t t_off, hipStream_t s) {
     switch (rpt) {
-        case 1: launch_iter_k<T, ALPHA, 1>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
-        case 2: launch_iter_k<T, ALPHA, 2>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
-        case 4: launch_iter_k<T, ALPHA, 4>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
-        default: launch_iter_k<T, ALPHA, 8>(L, m_in, m_out, adiag, bw, eta, flag, t, s); break;
+        case 1: launch_iter_k<T, ALPHA, 1>(L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s); break;
+        case 2: launch_iter_k<T, ALPHA, 2>(L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s); break;
+        case 4: launch_iter_k<T, ALPHA, 4>(L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s); break;
+        default: launch_iter_k<T, ALPHA, 8>(L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s); break;
     }
 }
 
 hipError_t launch_iter(int dtype, int rpt, const Lattice &L, const void *m_in, void *m_out,
                        const void *adiag, const void *bw, double eta, uint32_t *flag,
-                       uint32_t t, hipStream_t s) {
+                       const uint32_t *t_base, uint32_t t_off, hipStream_t s) {
     if (dtype == 0) {
-        if (L.alpha == 1) launch_iter_a<float, 1>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
-        else launch_iter_a<float, 2>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
+        if (L.alpha == 1) launch_iter_a<float, 1>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s);
+        else launch_iter_a<float, 2>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s);
     } else {
-        if (L.alpha == 1) launch_iter_a<double, 1>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
-        else launch_iter_a<double, 2>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t, s);
+        if (L.alpha == 1) launch_iter_a<double, 1>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s);
+        else launch_iter_a<double, 2>(rpt, L, m_in, m_out, adiag, bw, eta, flag, t_base, t_off, s);
     }
     return hipGetLastError();
 }
 
 template <typename T, int ALPHA, int RPT>
 static void launch_theta_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
-                           const void *bw, double eta, uint32_t *flag, uint32_t t, hipStream_t s) {
+                           const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
+                           uint32_t t_off, hipStream_t s) {
     const int tiles = L.tiles_x * ((L.ny + 4 * RPT - 1) / (4 * RPT));
     hipLaunchKernelGGL((k_iter_theta<T, ALPHA, RPT>), dim3(tiles), dim3(256), 0, s, L,
                        (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta, flag,
-                       t);
+                       t_base, t_off);
 }
 
 template <typename T, int ALPHA>
 static void launch_theta_a(int rpt, const Lattice &L, const void *m_in, void *m_out,
                            const void *gain, const void *bw, double eta, uint32_t *flag,
-                           uint32_t t, hipStream_t s) {
+                           const uint32_t *t_base, uint32_t t_off, hipStream_t s) {
     switch (rpt) {
-        case 1: launch_theta_k<T, ALPHA, 1>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
-        case 2: launch_theta_k<T, ALPHA, 2>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
-        case 4: launch_theta_k<T, ALPHA, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
-        default: launch_theta_k<T, ALPHA, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s); break;
+        case 1: launch_theta_k<T, ALPHA, 1>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s); break;
+        case 2: launch_theta_k<T, ALPHA, 2>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s); break;
+        case 4: launch_theta_k<T, ALPHA, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s); break;
+        default: launch_theta_k<T, ALPHA, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s); break;
     }
 }
 
 hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m_in,
                              void *m_out, const void *gain, const void *bw, double eta,
-                             uint32_t *flag, uint32_t t, hipStream_t s) {
+                             uint32_t *flag, const uint32_t *t_base, uint32_t t_off, hipStream_t s) {
     if (dtype == 0) {
-        if (L.alpha == 1) launch_theta_a<float, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
-        else launch_theta_a<float, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+        if (L.alpha == 1) launch_theta_a<float, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+        else launch_theta_a<float, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
     } else {
-        if (L.alpha == 1) launch_theta_a<double, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
-        else launch_theta_a<double, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t, s);
+        if (L.alpha == 1) launch_theta_a<double, 1>(rpt, L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+        else launch_theta_a<double, 2>(rpt, L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
     }
     return hipGetLastError();
 }
@@ -236,33 +241,33 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
 // 32 rows on 16
 template <typename T, int ALPHA, int TH>
 static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
-                            const void *bw, double eta, uint32_t *flag, uint32_t t,
-                            hipStream_t s) {
+                            const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
+                            uint32_t t_off, hipStream_t s) {
     constexpr int WAVES = TH == 4 ? 4 : TH == 32 ? 16 : 8;
     const int tiles = L.tiles_x * ((L.ny + TH - 1) / TH);
     hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(tiles), dim3(64 * WAVES), 0, s,
                        L, (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
-                       flag, t);
+                       flag, t_base, t_off);
 }
 
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
                               const void *gain, const void *bw, double eta, uint32_t *flag,
-                              uint32_t t, hipStream_t s) {
+                              const uint32_t *t_base, uint32_t t_off, hipStream_t s) {
     if (dtype == 0) {
         if (L.alpha == 1) {
-            if (th == 32) launch_theta2_k<float, 1, 32>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-            else if (th == 16) launch_theta2_k<float, 1, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-            else if (th == 8) launch_theta2_k<float, 1, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-            else launch_theta2_k<float, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            if (th == 32) launch_theta2_k<float, 1, 32>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (th == 16) launch_theta2_k<float, 1, 16>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (th == 8) launch_theta2_k<float, 1, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else launch_theta2_k<float, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
         } else {
-            if (th == 32) launch_theta2_k<float, 2, 32>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-            else if (th == 16) launch_theta2_k<float, 2, 16>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-            else if (th == 8) launch_theta2_k<float, 2, 8>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-            else launch_theta2_k<float, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+            if (th == 32) launch_theta2_k<float, 2, 32>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (th == 16) launch_theta2_k<float, 2, 16>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (th == 8) launch_theta2_k<float, 2, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else launch_theta2_k<float, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
         }
     } else {
-        if (L.alpha == 1) launch_theta2_k<double, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
-        else launch_theta2_k<double, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t, s);
+        if (L.alpha == 1) launch_theta2_k<double, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+        else launch_theta2_k<double, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
     }
     return hipGetLastError();
 }

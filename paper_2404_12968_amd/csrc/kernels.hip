@@ -300,6 +300,14 @@ __global__ __launch_bounds__(256) void k_upscale_prec(Lattice Lc, const T *__res
     }
 }
 
+__global__ void k_set_u32(uint32_t *p, uint32_t v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_add_u32(uint32_t *p, uint32_t k) {
+    if (threadIdx.x == 0) *p += k;
+}
+
 // --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
@@ -390,6 +398,16 @@ hipError_t launch_setup(int dtype, const Lattice &L, int64_t nobs, const int64_t
     else
         hipLaunchKernelGGL((k_node_init<double>), grid, block, 0, s, L, adiag64, b64, prior_mean,
                            (double *)nullptr, (double *)nullptr, err_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_u32(uint32_t *p, uint32_t k, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(64), 0, s, p, k);
     return hipGetLastError();
 }
 

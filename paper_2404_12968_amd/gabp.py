@@ -90,6 +90,7 @@ _SIGS = {
     "gabp_warm_init": ([_P, _P, ctypes.c_int32], ctypes.c_int),
     "gabp_solve_early_stop": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                ctypes.c_int32, _P, _P], ctypes.c_int),
+    "gabp_set_graph": ([_P, ctypes.c_int32], ctypes.c_int),
     "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "gabp_get_tile": ([_P, _P, _P], ctypes.c_int),
     "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
@@ -531,6 +532,11 @@ def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
                                     _ptr(y) if y.numel() else None, int(nx), int(ny), float(kappa),
                                     _ptr(scratch), _ptr(x), _stream_handle(stream)))
     return x
+
+
+def gabp_set_graph(ctx: Context, enable: bool) -> None:
+    """Record and replay solver chunks as hipGraphs (default) or launch directly."""
+    _check(_lib.gabp_set_graph(ctx.handle, 1 if enable else 0), ctx)
 
 
 def gabp_set_tile(ctx: Context, rows_per_thread: int, pair_rows: int) -> None:

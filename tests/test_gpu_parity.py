@@ -246,6 +246,54 @@ def test_message_change_statistic_matches_oracle(G, oracle_mod):
     assert r == pytest.approx(num / ref, rel=1e-10)
 
 
+@pytest.mark.parametrize("dtype,alpha", [("f32", 2), ("f64", 1), ("f32", 1)])
+def test_graph_chunks_equal_direct_launches(G, dtype, alpha):
+    """gabp_solve replays recorded chunk graphs (eager checks, freeze probes
+    and gain set-up between the replays); the result equals launching every
+    kernel directly, bit for bit, before and after the precision messages
+    froze (two-iteration launches inside the graphs)."""
+    # the frozen-phase test's problem: its precision messages freeze bitwise
+    # in every precision and order
+    prob = I.small_lattice(190, 130, alpha, bc_x=I.BC_PERIODIC, kappa=0.1, tracks=5, run=4,
+                           sigma=0.05, seed=77, dtype=dtype)
+    a = G.gabp_create_problem(prob)
+    b = G.gabp_create_problem(prob)
+    G.gabp_set_graph(b, False)
+    ra = G.gabp_solve(a, 600, 0.5, 0.0, 10)
+    rb = G.gabp_solve(b, 600, 0.5, 0.0, 10)
+    assert ra == rb and ra[1] == 600
+    assert G.gabp_precision_frozen(a) == G.gabp_precision_frozen(b) > 0
+    pa, ia = G.gabp_get_messages(a)
+    pb, ib = G.gabp_get_messages(b)
+    assert torch.equal(pa, pb) and torch.equal(ia, ib)
+    # adaptive chunks (powers of two with graphs) against plain iterations
+    c = G.gabp_create_problem(prob)
+    st, it, rel = G.gabp_solve(c, 100000, 0.5, 1e-5 if dtype == "f32" else 1e-9, -10)
+    assert st == G.GABP_OK
+    d = G.gabp_create_problem(prob)
+    G.gabp_iterate(d, it, 0.5)
+    assert torch.equal(G.gabp_get_messages(c)[1], G.gabp_get_messages(d)[1])
+
+
+def test_divergence_inside_a_replayed_chunk(G, oracle_mod):
+    """A run that diverges inside a replayed chunk graph reports the oracle's
+    iteration (numbered from the device counter) and keeps the messages of
+    that iteration."""
+    # c = 2 with learning rate 0.2 diverges at iteration 19 (oracle)
+    prob = I.small_lattice(16, 16, 2, kappa=0.05, c=2.0, frac=0.05, sigma=0.05, seed=7, dtype="f64")
+    og = oracle_mod.OracleGaBP.from_problem(prob)
+    assert og.iterate(200, 0.2) == oracle_mod.STATUS_DIVERGED
+    ctx = G.gabp_create_problem(prob)
+    st, it, _ = G.gabp_solve(ctx, 200, 0.2, 0.0, 4)
+    assert st == G.GABP_E_DIVERGED and it == og.diverged_at and it > 8
+    prec, _ = G.gabp_get_messages(ctx)
+    d, y, x, e = plane_slot_map(prob, og.g)
+    pg = prec.cpu().numpy()[d, y, x]
+    fin = np.isfinite(pg) & np.isfinite(og.lam[e])
+    assert fin.sum() > 100
+    np.testing.assert_allclose(pg[fin], og.lam[e][fin], rtol=1e-9)
+
+
 def test_early_stop_rule_stops_where_the_oracle_does(G, oracle_mod):
     """The paper's early stop (mean |m^t - m^(t-1)| < tau mean |m^2 - m^1|),
     checked every iteration, ends at the first iteration where the oracle's
