@@ -478,7 +478,11 @@ gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping) {
             e.pair == ctx->pair && e.eta == damping)
             c = &e;
     if (!c) {
-        if (ctx->chunks.size() >= 16) drop_chunks(ctx);
+        if (ctx->chunks.size() >= 16) {
+            // replays of the recorded graphs may still be in flight
+            GABP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            drop_chunks(ctx);
+        }
         if (!ctx->side)
             GABP_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         gabp_ctx::Chunk e{k, ctx->cur, (int)ctx->frozen, ctx->rpt, ctx->pair, damping, nullptr, 0, 0};
@@ -528,7 +532,10 @@ gabp_status gabp_set_graph(gabp_ctx *ctx, int32_t enable) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;
     ctx->graphs = enable != 0;
-    if (!ctx->graphs) drop_chunks(ctx);
+    if (!ctx->graphs && !ctx->chunks.empty()) {
+        GABP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        drop_chunks(ctx);
+    }
     return GABP_OK;
 }
 
