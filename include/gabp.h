@@ -148,7 +148,10 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping);
  * |check_every|, at most 2000; with graphs on, rounded down to
  * |check_every| * 2^j).  Each chunk of iterations is recorded once as a
  * hipGraph (per chunk length, starting buffer, phase, tile shape and
- * damping) and replayed (see gabp_set_graph).  iters_done (total iterations
+ * damping) and replayed (see gabp_set_graph).  Once the precision messages
+ * froze, a chunk may end on a two-iteration launch, so that afterwards the
+ * two buffers need not hold consecutive iterations: gabp_message_change then
+ * returns INVALID until gabp_iterate has run.  iters_done (total iterations
  * of the context) and rel_residual (last residual) may be NULL.
  * Synchronises the stream at every check. */
 gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double rel_tol,

@@ -77,10 +77,11 @@ struct gabp_ctx {
     hipStream_t side = nullptr;
     struct Chunk {
         int32_t k;
-        int cur, frozen, rpt, pair;
+        int cur, frozen, rpt, pair, tail;
         double eta;
         hipGraphExec_t exec;
         int pairs, singles;
+        bool last_single;
     };
     std::vector<Chunk> chunks;
     int64_t iter = 0;
@@ -387,28 +388,34 @@ namespace {
 
 // Issue n iterations on stream s, starting from iteration iter0 held in
 // buffer cur0, with iteration numbers relative to the device counter's value
-// tbase when they run.  Frozen contexts run two iterations per launch while
-// at least three remain and the last one or two singly, so that the two
-// buffers end on m^{t-1} and m^t.  Touches no context state; reports the
-// launch counts and whether the t = 2 reference change was taken.
+// tbase when they run.  Frozen contexts run two iterations per launch; with
+// tail_single the last one or two run singly, so that the two buffers end on
+// m^{t-1} and m^t (the message-change statistic and the freeze probe need
+// that), else pairs run while two iterations remain.  Touches no context
+// state; reports the launch counts, whether the last launch was single and
+// whether the t = 2 reference change was taken.
 gabp_status enqueue_iters(gabp_ctx *ctx, int32_t n, double damping, hipStream_t s, int64_t iter0,
-                          int cur0, uint32_t tbase, int &pairs, int &singles, bool &ref) {
+                          int cur0, uint32_t tbase, bool tail_single, int &pairs, int &singles,
+                          bool &last_single, bool &ref) {
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
     int64_t it = iter0;
     int cur = cur0;
     pairs = singles = 0;
     ref = false;
+    last_single = true;
+    const int32_t min_left = tail_single ? 3 : 2;
     int32_t k = 0;
     while (k < n) {
         const void *src = ctx->msg[cur];
         void *dst = ctx->msg[cur ^ 1];
-        if (ctx->frozen && ctx->pair > 0 && it >= 2 && n - k >= 3) {
+        if (ctx->frozen && ctx->pair > 0 && it >= 2 && n - k >= min_left) {
             GABP_HIP(ctx, gabp::launch_iter_theta2(dt, ctx->pair, ctx->L, src, dst, ctx->gain,
                                                    ctx->b_w, damping, ctx->flags, ctx->flags + 3,
                                                    (uint32_t)(it - tbase), s));
             it += 2;
             k += 2;
             ++pairs;
+            last_single = false;
         } else {
             const int64_t t = it + 1;
             if (ctx->frozen)
@@ -422,6 +429,7 @@ gabp_status enqueue_iters(gabp_ctx *ctx, int32_t n, double damping, hipStream_t 
             it = t;
             ++k;
             ++singles;
+            last_single = true;
             if (t == 2) {
                 const int64_t m = (int64_t)(2 * ctx->L.deg) * ctx->L.plane;
                 GABP_HIP(ctx, gabp::launch_abs_change(dt, ctx->msg[0], ctx->msg[1], m,
@@ -442,13 +450,15 @@ int64_t quantize_chunk(int64_t next, int64_t kmin) {
     return q;
 }
 
-// Context state after n iterations issued by enqueue_iters.
-void advance_state(gabp_ctx *ctx, int32_t n, int pairs, int singles, bool ref) {
+// Context state after n iterations issued by enqueue_iters (runs of pairs
+// then singles; a chunk that ends on a pair leaves m^{t-2} in the other
+// buffer).
+void advance_state(gabp_ctx *ctx, int32_t n, int pairs, int singles, bool last_single, bool ref) {
     ctx->runs.push_back({ctx->iter, ctx->cur, pairs, singles});
     ctx->iter += n;
     ctx->cur ^= (pairs + singles) & 1;
     if (ref) ctx->have_ref = true;
-    if (n > 0) ctx->prev_valid = true;
+    if (n > 0) ctx->prev_valid = last_single;
 }
 
 gabp_status check_iterate_args(gabp_ctx *ctx, int32_t n_iters, double damping) {
@@ -464,10 +474,18 @@ gabp_status check_iterate_args(gabp_ctx *ctx, int32_t n_iters, double damping) {
 // k iterations as one captured graph (recorded once per chunk length,
 // starting buffer, phase, tile shape and damping; replayed after), else
 // eagerly.  The graph ends by advancing the device iteration counter.
-gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping) {
+gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping, bool tail_single) {
     gabp_status st = check_iterate_args(ctx, k, damping);
     if (st != GABP_OK) return st;
-    if (!ctx->graphs || k < 2 || ctx->iter < 2) return gabp_iterate(ctx, k, damping);
+    if (!ctx->graphs || k < 2 || ctx->iter < 2) {
+        int pairs = 0, singles = 0;
+        bool last = true, ref = false;
+        st = enqueue_iters(ctx, k, damping, ctx->stream, ctx->iter, ctx->cur, ctx->tbase,
+                           tail_single, pairs, singles, last, ref);
+        if (st != GABP_OK) return st;
+        advance_state(ctx, k, pairs, singles, last, ref);
+        return GABP_OK;
+    }
     if (ctx->tbase != (uint32_t)ctx->iter) {
         GABP_HIP(ctx, gabp::launch_set_u32(ctx->flags + 3, (uint32_t)ctx->iter, ctx->stream));
         ctx->tbase = (uint32_t)ctx->iter;
@@ -475,7 +493,7 @@ gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping) {
     gabp_ctx::Chunk *c = nullptr;
     for (auto &e : ctx->chunks)
         if (e.k == k && e.cur == ctx->cur && e.frozen == (int)ctx->frozen && e.rpt == ctx->rpt &&
-            e.pair == ctx->pair && e.eta == damping)
+            e.pair == ctx->pair && e.tail == (int)tail_single && e.eta == damping)
             c = &e;
     if (!c) {
         if (ctx->chunks.size() >= 16) {
@@ -485,12 +503,13 @@ gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping) {
         }
         if (!ctx->side)
             GABP_HIP(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        gabp_ctx::Chunk e{k, ctx->cur, (int)ctx->frozen, ctx->rpt, ctx->pair, damping, nullptr, 0, 0};
+        gabp_ctx::Chunk e{k,       ctx->cur, (int)ctx->frozen, ctx->rpt, ctx->pair,
+                          (int)tail_single, damping, nullptr, 0, 0, true};
         bool ref = false;
         GABP_HIP(ctx, hipStreamBeginCapture(ctx->side, hipStreamCaptureModeThreadLocal));
         // relative numbering: the counter holds the chunk's first iteration
         st = enqueue_iters(ctx, k, damping, ctx->side, ctx->iter, ctx->cur, (uint32_t)ctx->iter,
-                           e.pairs, e.singles, ref);
+                           tail_single, e.pairs, e.singles, e.last_single, ref);
         if (st == GABP_OK && gabp::launch_add_u32(ctx->flags + 3, (uint32_t)k, ctx->side) != hipSuccess)
             st = fail(ctx, GABP_E_DEVICE, "capturing the counter advance failed");
         hipGraph_t g = nullptr;
@@ -508,7 +527,7 @@ gabp_status run_chunk(gabp_ctx *ctx, int32_t k, double damping) {
     }
     GABP_HIP(ctx, hipGraphLaunch(c->exec, ctx->stream));
     ctx->tbase += (uint32_t)k;
-    advance_state(ctx, k, c->pairs, c->singles, false);
+    advance_state(ctx, k, c->pairs, c->singles, c->last_single, false);
     return GABP_OK;
 }
 
@@ -520,11 +539,11 @@ gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping) {
     st = check_iterate_args(ctx, n_iters, damping);
     if (st != GABP_OK) return st;
     int pairs = 0, singles = 0;
-    bool ref = false;
-    st = enqueue_iters(ctx, n_iters, damping, ctx->stream, ctx->iter, ctx->cur, ctx->tbase, pairs,
-                       singles, ref);
+    bool last = true, ref = false;
+    st = enqueue_iters(ctx, n_iters, damping, ctx->stream, ctx->iter, ctx->cur, ctx->tbase, true,
+                       pairs, singles, last, ref);
     if (st != GABP_OK) return st;
-    advance_state(ctx, n_iters, pairs, singles, ref);
+    advance_state(ctx, n_iters, pairs, singles, last, ref);
     return GABP_OK;
 }
 
@@ -591,7 +610,7 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
     st = GABP_E_NOT_CONVERGED;
     while (run < max_iters) {
         const int32_t k = (int32_t)std::min<int64_t>(next, max_iters - run);
-        gabp_status s1 = run_chunk(ctx, k, damping);
+        gabp_status s1 = run_chunk(ctx, k, damping, false);
         if (s1 != GABP_OK) {
             st = s1;
             break;
@@ -652,7 +671,7 @@ gabp_status gabp_solve_early_stop(gabp_ctx *ctx, int64_t max_iters, double dampi
     st = GABP_E_NOT_CONVERGED;
     while (run < max_iters) {
         const int32_t k = (int32_t)std::min<int64_t>(next, max_iters - run);
-        gabp_status s1 = run_chunk(ctx, k, damping);
+        gabp_status s1 = run_chunk(ctx, k, damping, true);
         if (s1 != GABP_OK) {
             st = s1;
             break;
