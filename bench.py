@@ -53,10 +53,11 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(phase, rpt):
+def measured_traffic(phase, rpt, workload="global8192"):
     """HBM bytes per launch of the timed kernel (its tile shape) from the
-    committed PMC summary, if that was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    committed PMC summary of the 8192 x 4096 workload, if that was taken on
+    the current kernel source."""
+    if workload != "global8192" or not os.path.exists(TRAFFIC_SUMMARY):
         return None
     text = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
@@ -250,7 +251,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="global8192",
-                    choices=["global8192", "tracks2048", "batch256", "table1"])
+                    choices=["global8192", "tracks2048", "batch256", "table1", "global32k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-solve", action="store_true",
@@ -415,17 +416,17 @@ def main(argv=None):
         kname = "k_iter_theta2"
         launch_ms = kernels[f"theta_pair{pair}"]["launch_ms"]
         alg_launch = alg_theta
-        traffic = measured_traffic("theta2", pair)
+        traffic = measured_traffic("theta2", pair, prob.name)
     elif phase == "theta":
         kname = "k_iter_theta"
         launch_ms = kernels["theta"]["iter_ms"]
         alg_launch = alg_theta
-        traffic = measured_traffic("theta", rpt)
+        traffic = measured_traffic("theta", rpt, prob.name)
     else:
         kname = "k_iter_direct"
         launch_ms = kernels["full"]["iter_ms"]
         alg_launch = alg_full
-        traffic = measured_traffic("full", rpt)
+        traffic = measured_traffic("full", rpt, prob.name)
     achieved = alg_launch / (launch_ms * 1e-3) / 1e9
 
     out = {

@@ -202,7 +202,8 @@ def observe(truth: np.ndarray, cells: np.ndarray, sigma: float,
 # named workloads
 # --------------------------------------------------------------------------
 
-WORKLOADS = ("parity64", "tracks2048", "global8192", "batch256", "warm1024", "table1")
+WORKLOADS = ("parity64", "tracks2048", "global8192", "batch256", "warm1024", "table1",
+             "global32k")
 _WORKLOAD_K = {name: k + 1 for k, name in enumerate(WORKLOADS)}
 
 # re-weighting constant by prior order: plain GaBP for the 5-point prior, the
@@ -249,6 +250,25 @@ def global8192(instance: int = 0, nx: int = 8192, ny: int = 4096,
                    truth=truth if keep_truth else None,
                    dtype="f32", damping=0.5, rel_tol=1e-6, check_every=10,
                    seed=3000 + instance)
+
+
+def global32k(instance: int = 0, nx: int = 32768, ny: int = 24576) -> Problem:
+    """The global-scale workload at 32768 x 24576 (805 M nodes, 9.7 G directed
+    edges, about 225 GB of solver state in FP32): periodic in x, zero-flux in
+    y, 13-point prior, kappa 0.02, 240 tracks of 7 cells (~5 %), sigma 0.05.
+    The truth is a sum of 64 random plane waves (a spectral synthesis would
+    need an FFT of the whole grid on the host); only throughput is measured
+    on it."""
+    rng = np.random.default_rng(1000 * 7 + instance)
+    truth = fourier_modes_field(nx, ny, rng, n_modes=64, max_freq=48)
+    cells = track_cells(nx, ny, 240, 7, rng)
+    sigma = 0.05
+    y = observe(truth, cells, sigma, rng)
+    del truth
+    return Problem("global32k", nx, ny, BC_PERIODIC, BC_NEUMANN, alpha=2, kappa=0.02,
+                   tau=1.0, c=DEFAULT_C[2], sigma=sigma, cells=cells, y=y, truth=None,
+                   dtype="f32", damping=0.5, rel_tol=1e-6, check_every=10,
+                   seed=7000 + instance)
 
 
 def batch256(count: int = 256, side_lo: int = 64, side_hi: int = 1024) -> List[Problem]:
@@ -338,5 +358,5 @@ def workload(name: str, instance: int = 0):
     """Named workload by its name (see WORKLOADS)."""
     fn = {"parity64": parity64, "tracks2048": tracks2048, "global8192": global8192,
           "batch256": lambda instance=0: batch256(), "warm1024": warm1024,
-          "table1": lambda instance=0: table1(instance=instance)}[name]
+          "table1": lambda instance=0: table1(instance=instance), "global32k": global32k}[name]
     return fn(instance)
