@@ -4,7 +4,8 @@
         --out paper_2404_12968_amd/weights/warm1024.npz --eval 6
 
 1. Draws `n-train` problems of the 1024 x 1024 warm-start workload (seeds
-   0..n-1) and solves them to 1e-6 with the batched solver.
+   seed-base .. seed-base + n-1) and solves them to 1e-6 with the batched
+   solver.
 2. Trains the network (Adam, cosine schedule) on random 256 x 256 crops of
    those solutions.
 3. Solves `eval` held-out problems (seeds 100000 + k) cold and warm (network
@@ -36,6 +37,10 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lam-weight", type=float, default=0.1)
     ap.add_argument("--eval", type=int, default=6)
+    ap.add_argument("--seed-base", type=int, default=0,
+                    help="training problems are seeds seed_base .. seed_base + n_train - 1")
+    ap.add_argument("--init", default=None,
+                    help="continue from these weights (npz) instead of a fresh network")
     ap.add_argument("--out", default=None)
     ap.add_argument("--summary", default=None)
     args = ap.parse_args(argv)
@@ -45,7 +50,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    probs = [I.warm1024(instance=k, n=args.side) for k in range(args.n_train)]
+    probs = [I.warm1024(instance=args.seed_base + k, n=args.side) for k in range(args.n_train)]
     log(f"[warm] generated {len(probs)} problems in {time.time() - t0:.1f}s")
     chunk = 64
     ts = Wm.TrainingSet()
@@ -54,7 +59,7 @@ def main(argv=None):
         for f in ("x", "mu", "lam", "valid", "iters"):
             getattr(ts, f).extend(getattr(part, f))
     log(f"[warm] training set: {len(ts)} solutions, iterations median {int(np.median(ts.iters))}")
-    net = Wm.WarmNet(seed=0)
+    net = Wm.WarmNet.load(args.init) if args.init else Wm.WarmNet(seed=0)
     t1 = time.time()
     hist = Wm.train(net, ts, args.steps, batch=args.batch, crop=args.crop, lr=args.lr,
                     lam_weight=args.lam_weight, log=log, log_every=200)
@@ -65,7 +70,8 @@ def main(argv=None):
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         net.save(args.out, meta={"n_train": args.n_train, "steps": args.steps,
                                  "batch": args.batch, "crop": args.crop, "lr": args.lr,
-                                 "side": args.side, "final_loss": hist[-1]})
+                                 "side": args.side, "seed_base": args.seed_base,
+                                 "init": args.init or "", "final_loss": hist[-1]})
         log(f"[warm] saved {args.out}")
     evals = []
     for k in range(args.eval):
@@ -84,7 +90,8 @@ def main(argv=None):
             f" | mean-only {wm['iterations']} it")
     cold_t = sum(e["cold_s"] for e in evals)
     warm_t = sum(e["warm_s"] for e in evals)
-    summary = {"n_train": args.n_train, "steps": args.steps, "train_seconds": train_s,
+    summary = {"n_train": args.n_train, "seed_base": args.seed_base, "init": args.init,
+               "steps": args.steps, "train_seconds": train_s,
                "loss_first": hist[0], "loss_last": hist[-1], "eval": evals,
                "cold_seconds_total": cold_t, "warm_seconds_total": warm_t,
                "speedup": cold_t / warm_t if warm_t > 0 else None}
