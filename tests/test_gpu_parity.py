@@ -5,12 +5,11 @@ FP64 runs match the oracle to 1e-12 relative L2 at equal iteration count
 sparse direct solve to 1e-5.
 """
 import os
-import sys
 
 import numpy as np
 import pytest
 
-from conftest import DIRS, n_dirs, plane_slot_map
+from conftest import plane_slot_map
 from paper_2404_12968_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
