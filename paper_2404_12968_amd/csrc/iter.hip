@@ -41,8 +41,9 @@ __global__ __launch_bounds__(256) void k_iter_direct(Lattice L, const T *__restr
     if (*diverged_at != 0u) return;
     const uint32_t t = *t_base + t_off;   // this iteration's number
     constexpr int TH = 4 * RPT;
-    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+    int tx, ty;
+    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, (L.ny + TH - 1) / TH, tx,
+                ty);
     const int x = tx * 64 + (int)(threadIdx.x & 63u);
     const int y0 = ty * TH + (int)(threadIdx.x >> 6);
     const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * TH >= 2 &&
@@ -113,8 +114,9 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
     if (*diverged_at != 0u) return;
     const uint32_t t = *t_base + t_off;   // this iteration's number
     constexpr int TH = 4 * RPT;
-    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+    int tx, ty;
+    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, (L.ny + TH - 1) / TH, tx,
+                ty);
     const int x = tx * 64 + (int)(threadIdx.x & 63u);
     const int y0 = ty * TH + (int)(threadIdx.x >> 6);
     const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * TH >= 2 &&
@@ -145,19 +147,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
     __shared__ T lds[DEG * TH * 64];
     if (*diverged_at != 0u) return;               // uniform across the workgroup
     const uint32_t t = *t_base + t_off;           // the iteration the launch starts from
-    // Tiles in strip-major order: strips of kStrip tile columns, each walked
-    // row by row, and each XCD a contiguous range of that order.  Tiles above
-    // and below then run close together on one XCD and share their halo rows
-    // in its L2.
+    // strip-major tile order: tiles above and below share their halo rows
+    // in one XCD's L2
     int tx, ty;
-    {
-        const int t_ = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-        const int rows = (L.ny + TH - 1) / TH;
-        const int strip = t_ / (kStrip * rows), r = t_ - strip * kStrip * rows;
-        const int width = min(kStrip, L.tiles_x - strip * kStrip);
-        ty = r / width;
-        tx = strip * kStrip + r % width;
-    }
+    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, (L.ny + TH - 1) / TH, tx,
+                ty);
     bool bad1 = false, bad2 = false;
     pair_tile<T, ALPHA, TH, WAVES>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);

@@ -11,6 +11,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "internal.h"
 #include "lattice.h"
 #include "numerics.h"
@@ -50,8 +52,11 @@ __global__ __launch_bounds__(256) void k_post(Lattice L, const T *__restrict__ m
 
 // --------------------------------------------------------------------------
 // FP64 residual r = A mu - b of the posterior-mean equations, A = Q + diag(p).
-// Each workgroup sums r^2 and b^2 over a fixed set of tiles in a fixed order
-// (wave64 butterfly, then LDS across the four waves): deterministic partials.
+// Workgroup g (after XCD remapping) owns the g-th contiguous run of 64 x 4
+// tiles in strip-major order, so the mean rows a tile shares with the tiles
+// above, below and beside it are read once into its XCD's L2.  It sums r^2
+// and b^2 over its tiles in a fixed order (wave64 butterfly, then LDS across
+// the four waves) into partials[g]: deterministic partials.
 // --------------------------------------------------------------------------
 template <int ALPHA>
 __global__ __launch_bounds__(256) void k_resid(Lattice L, const double *__restrict__ mu,
@@ -60,8 +65,13 @@ __global__ __launch_bounds__(256) void k_resid(Lattice L, const double *__restri
                                                double *__restrict__ partials, int ntiles) {
     __shared__ double sh[2][4];
     double rr = 0.0, bb = 0.0;
-    for (int tile = (int)blockIdx.x; tile < ntiles; tile += (int)gridDim.x) {
-        const int tx = tile % L.tiles_x, ty = tile / L.tiles_x;
+    const int nb = (int)gridDim.x, g = xcd_remap((int)blockIdx.x, nb);
+    const int per = ntiles / nb, extra = ntiles % nb;
+    const int t0 = g * per + min(g, extra), t1 = t0 + per + (g < extra ? 1 : 0);
+    const int rows = (L.ny + 3) / 4;
+    for (int tile = t0; tile < t1; ++tile) {
+        int tx, ty;
+        strip_order(tile, L.tiles_x, rows, tx, ty);
         const int x = tx * 64 + (int)(threadIdx.x & 63u);
         const int y = ty * 4 + (int)(threadIdx.x >> 6);
         const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * 4 >= 2 &&
@@ -80,8 +90,8 @@ __global__ __launch_bounds__(256) void k_resid(Lattice L, const double *__restri
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
-        partials[2 * blockIdx.x + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+        partials[2 * g] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        partials[2 * g + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
     }
 }
 
@@ -355,11 +365,34 @@ hipError_t launch_post(int dtype, const Lattice &L, const void *m, const double 
     return hipGetLastError();
 }
 
+// Workgroups of the residual kernel that are resident at once on the current
+// device (its occupancy times the CU count), so that its one wave of
+// workgroups has no tail; cached per device and stencil.
+static int resident_resid_blocks(int alpha) {
+    static std::atomic<int> cache[16][2];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+    const int a = alpha == 1 ? 0 : 1;
+    int v = cache[dev][a].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int per_cu = 0, cus = 0;
+    const hipError_t e1 =
+        alpha == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resid<1>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resid<2>, 256, 0);
+    const hipError_t e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e1 != hipSuccess || e2 != hipSuccess || per_cu <= 0 || cus <= 0) return 0;
+    v = per_cu * cus;
+    cache[dev][a].store(v, std::memory_order_relaxed);
+    return v;
+}
+
 hipError_t launch_resid(const Lattice &L, const double *mu, const double *adiag64,
                         const double *b64, double *partials, int npart, double *out,
                         hipStream_t s) {
     const int nt = tiles_of(L);
-    const int nb = nt < npart ? nt : npart;
+    int nb = nt < npart ? nt : npart;
+    const int resident = resident_resid_blocks(L.alpha);
+    if (resident > 0 && resident < nb) nb = resident;
     if (L.alpha == 1)
         hipLaunchKernelGGL((k_resid<1>), dim3(nb), dim3(256), 0, s, L, mu, adiag64, b64, partials,
                            nt);

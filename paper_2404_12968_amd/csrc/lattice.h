@@ -118,6 +118,21 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// Strip-major tile order: strips of kStrip tile columns (the last one
+// narrower), each walked row by row.  Logical index t of a grid of
+// tiles_x x rows tiles -> (tx, ty); with xcd_remap, each XCD then walks a
+// contiguous run of whole rows of strips, so tiles above and below a tile
+// run close together on the same L2.  On the 8192-wide lattice a strip is
+// exactly one XCD's share.
+constexpr int kStrip = 16;
+
+__device__ __forceinline__ void strip_order(int t, int tiles_x, int rows, int &tx, int &ty) {
+    const int strip = t / (kStrip * rows), r = t - strip * kStrip * rows;
+    const int width = min(kStrip, tiles_x - strip * kStrip);
+    ty = r / width;
+    tx = strip * kStrip + r % width;
+}
+
 // Wave64 sum in a fixed order (butterfly over lane masks 32..1).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

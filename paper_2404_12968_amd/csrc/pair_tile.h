@@ -42,8 +42,6 @@ __device__ __forceinline__ void record_divergence(uint32_t *p, uint32_t v) {
     }
 }
 
-constexpr int kStrip = 16;  // tile columns per strip of the two-iteration kernel's order
-
 __device__ __forceinline__ int wrap_coord(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
