@@ -57,31 +57,57 @@ __device__ __forceinline__ void post_node(const Lattice &L, const T *__restrict_
 }
 
 // Residual contribution of node (x, y): r = (A mu - b)_i with A = Q + diag(p),
-// the 13- or 5-point FP64 stencil of the prior plus the diagonal.
+// the 13- or 5-point FP64 stencil of the prior plus the diagonal.  Split into
+// the loads (resid_load) and the arithmetic (resid_accum) so that a caller
+// can issue the loads of several nodes before the first use; resid_node is
+// the two in sequence.
+template <int ALPHA>
+struct ResidIn {
+    static constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    double v[DEG], a, m0, b;
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+};
+
+template <int ALPHA, bool INTERIOR>
+__device__ __forceinline__ void resid_load(const Lattice &L, const double *__restrict__ mu,
+                                           const double *__restrict__ adiag64,
+                                           const double *__restrict__ b64, int x, int y,
+                                           ResidIn<ALPHA> &in) {
+    constexpr int DEG = ResidIn<ALPHA>::DEG;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    uint32_t j[DEG];
+    node_nbrs<DEG, INTERIOR>(L, x, y, j, in.xs, in.ys, in.ok);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) in.v[d] = mu[j[d]];
+    in.a = adiag64[i];
+    in.m0 = mu[i];
+    in.b = b64[i];
+}
+
+template <int ALPHA>
+__device__ __forceinline__ void resid_accum(const Lattice &L, int x, int y,
+                                            const ResidIn<ALPHA> &in, double &rr, double &bb) {
+    constexpr int DEG = ResidIn<ALPHA>::DEG;
+    double s = in.a * in.m0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        const double q = q_off<double>(L, d, x, y, in.xs[d], in.ys[d]);
+        s += in.ok[d] ? q * in.v[d] : 0.0;
+    }
+    const double r = s - in.b;
+    rr += r * r;
+    bb += in.b * in.b;
+}
+
 template <int ALPHA, bool INTERIOR>
 __device__ __forceinline__ void resid_node(const Lattice &L, const double *__restrict__ mu,
                                            const double *__restrict__ adiag64,
                                            const double *__restrict__ b64, int x, int y,
                                            double &rr, double &bb) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
-    const uint32_t i = (uint32_t)(y * L.pitch + x);
-    uint32_t j[DEG];
-    int xs[DEG], ys[DEG];
-    bool ok[DEG];
-    node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
-    double v[DEG];
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) v[d] = mu[j[d]];
-    const double a = adiag64[i], m0 = mu[i], b = b64[i];
-    double s = a * m0;
-#pragma unroll
-    for (int d = 0; d < DEG; ++d) {
-        const double q = q_off<double>(L, d, x, y, xs[d], ys[d]);
-        s += ok[d] ? q * v[d] : 0.0;
-    }
-    const double r = s - b;
-    rr += r * r;
-    bb += b * b;
+    ResidIn<ALPHA> in;
+    resid_load<ALPHA, INTERIOR>(L, mu, adiag64, b64, x, y, in);
+    resid_accum<ALPHA>(L, x, y, in, rr, bb);
 }
 
 }  // namespace gabp

@@ -54,32 +54,122 @@ __global__ __launch_bounds__(256) void k_post(Lattice L, const T *__restrict__ m
 // FP64 residual r = A mu - b of the posterior-mean equations, A = Q + diag(p).
 // Workgroup g (after XCD remapping) owns the g-th contiguous run of 64 x 4
 // tiles in strip-major order, so the mean rows a tile shares with the tiles
-// above, below and beside it are read once into its XCD's L2.  It sums r^2
-// and b^2 over its tiles in a fixed order (wave64 butterfly, then LDS across
-// the four waves) into partials[g]: deterministic partials.
+// above, below and beside it are read once into its XCD's L2.  It takes its
+// tiles kResidUnroll at a time: every thread first loads its share of each
+// tile's (64 + 2R) x (4 + 2R) window of the mean (wrapped on periodic axes,
+// zero outside the lattice) and its own node's diagonal and data term, then
+// the windows go to LDS and every node reads its stencil from there.  Each
+// node's arithmetic (resid_accum) and the order of the sums (tile by tile)
+// are those of resid_node, so the r^2 and b^2 partials (wave64 butterfly,
+// then LDS across the four waves, into partials[g]) are deterministic and do
+// not depend on the staging.
 // --------------------------------------------------------------------------
+constexpr int kResidUnroll = 4;
+
 template <int ALPHA>
 __global__ __launch_bounds__(256) void k_resid(Lattice L, const double *__restrict__ mu,
                                                const double *__restrict__ adiag64,
                                                const double *__restrict__ b64,
                                                double *__restrict__ partials, int ntiles) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    constexpr int R = ALPHA == 1 ? 1 : 2;
+    constexpr int WX = 64 + 2 * R, WY = 4 + 2 * R, WN = WX * WY;
+    constexpr int LPT = (WN + 255) / 256;          // window loads per thread and tile
+    constexpr int U = kResidUnroll;
+    __shared__ double win[U][WY][WX];
     __shared__ double sh[2][4];
     double rr = 0.0, bb = 0.0;
     const int nb = (int)gridDim.x, g = xcd_remap((int)blockIdx.x, nb);
     const int per = ntiles / nb, extra = ntiles % nb;
     const int t0 = g * per + min(g, extra), t1 = t0 + per + (g < extra ? 1 : 0);
     const int rows = (L.ny + 3) / 4;
-    for (int tile = t0; tile < t1; ++tile) {
-        int tx, ty;
-        strip_order(tile, L.tiles_x, rows, tx, ty);
-        const int x = tx * 64 + (int)(threadIdx.x & 63u);
-        const int y = ty * 4 + (int)(threadIdx.x >> 6);
-        const bool interior = tx * 64 >= 2 && tx * 64 + 66 <= L.nx && ty * 4 >= 2 &&
-                              ty * 4 + 6 <= L.ny;
-        if (interior)
-            resid_node<ALPHA, true>(L, mu, adiag64, b64, x, y, rr, bb);
-        else if (x < L.nx && y < L.ny)
-            resid_node<ALPHA, false>(L, mu, adiag64, b64, x, y, rr, bb);
+    const int lane = (int)(threadIdx.x & 63u), wrow = (int)(threadIdx.x >> 6);
+    const bool px = L.bcx == BC_PERIODIC, py = L.bcy == BC_PERIODIC;
+    // A tile is interior when its stencil never leaves the lattice.  Every
+    // node of such a tile and its +-1 neighbours lie off the boundary rows
+    // and columns, where ell takes one value, so the off-diagonal entries of
+    // its rows depend on the direction only: q_in[d], evaluated as q_off does
+    // at an interior position.
+    auto interior_tile = [&](int tx0, int ty0) {
+        return tx0 >= 2 * R && tx0 + 64 + 2 * R <= L.nx && ty0 >= 2 * R && ty0 + 4 + 2 * R <= L.ny;
+    };
+    double q_in[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d)
+        q_in[d] = q_off<double>(L, d, 2 * R, 2 * R, 2 * R + dir_dx(d), 2 * R + dir_dy(d));
+    for (int base = t0; base < t1; base += U) {
+        const int n = min(U, t1 - base);
+        int x0[U], y0[U];
+        double wv[U][LPT], a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = 0.0;
+            b[u] = 0.0;
+#pragma unroll
+            for (int q = 0; q < LPT; ++q) wv[u][q] = 0.0;
+            if (u >= n) continue;
+            int tx, ty;
+            strip_order(base + u, L.tiles_x, rows, tx, ty);
+            x0[u] = tx * 64;
+            y0[u] = ty * 4;
+#pragma unroll
+            for (int q = 0; q < LPT; ++q) {
+                const int e = (int)threadIdx.x + 256 * q;
+                if (e >= WN) continue;
+                int gx = x0[u] + e % WX - R, gy = y0[u] + e / WX - R;
+                bool in = true;
+                if (gx < 0 || gx >= L.nx) {
+                    if (px) gx = (gx % L.nx + L.nx) % L.nx;   // the window may be wider
+                    else in = false;                            // than the lattice
+                }
+                if (gy < 0 || gy >= L.ny) {
+                    if (py) gy = (gy % L.ny + L.ny) % L.ny;
+                    else in = false;
+                }
+                if (in) wv[u][q] = mu[(uint32_t)(gy * L.pitch + gx)];
+            }
+            const int x = x0[u] + lane, y = y0[u] + wrow;
+            if (x < L.nx && y < L.ny) {
+                const uint32_t i = (uint32_t)(y * L.pitch + x);
+                a[u] = adiag64[i];
+                b[u] = b64[i];
+            }
+        }
+        __syncthreads();   // the previous round's readers are done with win
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int q = 0; q < LPT; ++q) {
+                const int e = (int)threadIdx.x + 256 * q;
+                if (e < WN) win[u][e / WX][e % WX] = wv[u][q];
+            }
+        }
+        __syncthreads();
+        for (int u = 0; u < n; ++u) {
+            const int x = x0[u] + lane, y = y0[u] + wrow;
+            if (x >= L.nx || y >= L.ny) continue;
+            if (interior_tile(x0[u], y0[u])) {
+                // the arithmetic of resid_accum with every neighbour present
+                double s = a[u] * win[u][wrow + R][lane + R];
+#pragma unroll
+                for (int d = 0; d < DEG; ++d)
+                    s += q_in[d] * win[u][wrow + R + dir_dy(d)][lane + R + dir_dx(d)];
+                const double r = s - b[u];
+                rr += r * r;
+                bb += b[u] * b[u];
+                continue;
+            }
+            ResidIn<ALPHA> in;
+            uint32_t j[DEG];
+            node_nbrs<DEG, false>(L, x, y, j, in.xs, in.ys, in.ok);
+#pragma unroll
+            for (int d = 0; d < DEG; ++d)
+                in.v[d] = win[u][wrow + R + dir_dy(d)][lane + R + dir_dx(d)];
+            in.a = a[u];
+            in.m0 = win[u][wrow + R][lane + R];
+            in.b = b[u];
+            resid_accum<ALPHA>(L, x, y, in, rr, bb);
+        }
     }
     rr = wave_sum(rr);
     bb = wave_sum(bb);
