@@ -123,6 +123,34 @@ def test_fp64_converged_mean_equals_direct_solve(G, oracle_mod, alpha, bcx, bcy,
     assert rel_l2(mu.cpu().numpy(), exact) <= 1e-5
 
 
+@pytest.mark.parametrize("nx,ny,alpha,bcx,bcy", [
+    (200, 40, 1, I.BC_NEUMANN, I.BC_NEUMANN),
+    (200, 40, 2, I.BC_PERIODIC, I.BC_NEUMANN),
+    (300, 24, 2, I.BC_NEUMANN, I.BC_DIRICHLET),
+    (261, 17, 2, I.BC_DIRICHLET, I.BC_PERIODIC),
+    (133, 13, 2, I.BC_PERIODIC, I.BC_PERIODIC),
+])
+def test_residual_matches_the_oracle_system(G, oracle_mod, nx, ny, alpha, bcx, bcy):
+    """gabp_residual against |A mu - b| / |b| with the oracle's own assembled
+    A and b (sparse product of the 1-D Laplacians) and the GPU's FP64 mean, on
+    lattices wide enough for tiles whose stencil stays inside (the residual
+    kernel evaluates the prior there from per-direction constants) as well as
+    boundary tiles."""
+    prob = I.small_lattice(nx, ny, alpha, bc_x=bcx, bc_y=bcy, kappa=0.2, frac=0.1, sigma=0.1,
+                           seed=nx + 7 * ny, dtype="f64", hx=1.0, hy=1.3)
+    ctx = G.gabp_create_problem(prob)
+    G.gabp_iterate(ctx, 30, 0.5)
+    rel, ab = G.gabp_residual(ctx)
+    mu, _ = G.gabp_posterior(ctx, want_var=False)
+    A, b = oracle_mod.posterior_system(prob)
+    r = A @ mu.cpu().numpy().ravel() - b
+    want_abs = np.linalg.norm(r)
+    want_rel = want_abs / np.linalg.norm(b)
+    assert want_rel > 1e-4          # a residual far from zero: every term matters
+    assert ab == pytest.approx(want_abs, rel=1e-11)
+    assert rel == pytest.approx(want_rel, rel=1e-11)
+
+
 FP32_CASES = [
     (200, 150, 1, I.BC_NEUMANN, I.BC_NEUMANN, 1.0, 0.5, 0.2, 300),
     (193, 130, 2, I.BC_PERIODIC, I.BC_NEUMANN, 10.0, 0.5, 0.05, 1000),
