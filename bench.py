@@ -148,6 +148,8 @@ def bench_batch(G, I, torch, dev, args):
     Es = np.array([edge_count(p.nx, p.ny, p.alpha, p.bc_x, p.bc_y) for p in probs], dtype=np.int64)
     Ns = np.array([p.n for p in probs], dtype=np.int64)
     b = G.gabp_batch_create(probs, device=dev)
+    if args.freeze_slots > 0:
+        G.gabp_batch_set_freeze_tolerance(b, args.freeze_slots, args.freeze_rel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, its, rels, sts = G.gabp_batch_solve(b, max(args.solve_max_iters, 300000), 0.5, 1e-6, -10)
@@ -165,6 +167,8 @@ def bench_batch(G, I, torch, dev, args):
                                "kappa ~ U[0.02,0.3], 1-20% observed, sigma ~ U[0.02,0.2], "
                                "each to 1e-6, checks adaptive (every 10 until all running instances "
                                "froze, then growing with the slowest one's residual decay)",
+                   "freeze_tolerance": {"max_slots": args.freeze_slots,
+                                        "max_rel": args.freeze_rel if args.freeze_slots > 0 else 0.0},
                    "nodes": int(Ns.sum()), "directed_edges": int(Es.sum()),
                    "parallelism": "single GPU"},
         "batch": {"seconds_to_all_converged": wall, "status": G.gabp_status_string(st),
@@ -173,6 +177,7 @@ def bench_batch(G, I, torch, dev, args):
                   "iterations_alpha1": [int(its[~a2].min()), int(np.median(its[~a2])), int(its[~a2].max())],
                   "iterations_alpha2": [int(its[a2].min()), int(np.median(its[a2])), int(its[a2].max())],
                   "frozen_at_median": float(np.median([f for f in frozen if f >= 0])) if any(f >= 0 for f in frozen) else None,
+                  "frozen_instances": int(sum(f >= 0 for f in frozen)),
                   "max_rel_residual": float(rels.max()),
                   "not_converged": [{"instance": int(i), "side": probs[i].nx, "alpha": probs[i].alpha,
                                      "kappa": probs[i].kappa, "sigma": probs[i].sigma,
@@ -260,6 +265,11 @@ def main(argv=None):
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
     ap.add_argument("--warm-instances", type=int, default=3)
+    ap.add_argument("--freeze-slots", type=int, default=64,
+                    help="batch256: freeze an instance's precision messages when at most this many "
+                         "changed in the last iteration (0: only when none did)")
+    ap.add_argument("--freeze-rel", type=float, default=1e-6,
+                    help="batch256: ... each by at most this relative change")
     ap.add_argument("--table1-truths", type=int, default=3,
                     help="ground truths per Table 1 configuration")
     ap.add_argument("--no-table1", action="store_true",

@@ -164,8 +164,24 @@ gabp_status gabp_solve(gabp_ctx *ctx, int64_t max_iters, double damping, double 
  * unchanged; the precision recursion involves neither the information
  * messages nor the data, so they then stay fixed for ever and later
  * iterations update only the information messages, with precomputed edge
- * gains (bitwise the same results, 12 instead of 16 bytes per FP32 edge). */
+ * gains (bitwise the same results, 12 instead of 16 bytes per FP32 edge).
+ * See gabp_set_freeze_tolerance for a relaxed form of that test. */
 gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_residual);
+
+/* Freeze tolerance of the precision messages.  In FP32 the precision
+ * recursion can settle to a state where a few messages keep changing in
+ * their last bits for ever, and then never freezes under the bitwise test
+ * of gabp_residual.  With max_slots > 0, the precision messages also freeze
+ * when the last iteration changed at most max_slots of them, each by at most
+ * max_rel relative to the larger of its two values; the edge gains are then
+ * taken from the current messages (which both message buffers keep from
+ * then on, as after a bitwise freeze), and later results differ from those of
+ * the unfrozen iteration by amounts of the order of those last-bit changes
+ * (convergence is still decided by the FP64 residual).  max_slots = 0 (the
+ * default) keeps the bitwise test.  INVALID for max_slots < 0 or a max_rel
+ * that is negative or not finite.  Applies from the next residual check;
+ * an already frozen context stays frozen. */
+gabp_status gabp_set_freeze_tolerance(gabp_ctx *ctx, int64_t max_slots, double max_rel);
 
 /* The paper's stopping rule (Alg. 2, Iterate MP Until Convergence, with the
  * Early Stop of Appendix A): iterate until mean|m^t - m^{t-1}| <
@@ -354,6 +370,10 @@ gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *
 /* Tile-shape autotuner of the batched iteration, as gabp_autotune (advances
  * every running instance by 1 + 8 * trials iterations). */
 gabp_status gabp_batch_autotune(gabp_batch *b, int32_t trials, double damping, int32_t *chosen);
+
+/* The batch's freeze tolerance, as gabp_set_freeze_tolerance's, for every
+ * instance (default max_slots = 0: bitwise test). */
+gabp_status gabp_batch_set_freeze_tolerance(gabp_batch *b, int64_t max_slots, double max_rel);
 
 /* Iterations applied to instance i, the iteration its precision messages
  * froze at (-1 if not), and whether it is still running. */

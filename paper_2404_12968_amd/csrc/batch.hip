@@ -330,6 +330,8 @@ struct gabp_batch {
     int *p_lists = nullptr;     // staging for act / prefixes / frozen / probe
     int rpt = 4;
     int pair = 0;               // tile height of the two-iteration kernel, 0 = unused
+    int64_t freeze_slots = 0;   // freeze tolerance (gabp_batch_set_freeze_tolerance)
+    double freeze_rel = 0.0;
     int64_t t = 0;              // iterations applied to the running set
     // current work lists
     int nact = 0, wtotal = 0, ptotal = 0;
@@ -559,8 +561,9 @@ gabp_status launch_check(gabp_batch *b) {
     return GABP_OK;
 }
 
-// Bitwise precision-message change test of every running, not yet frozen
-// instance whose previous buffer is valid (outside the captured graph).
+// Precision-message change (count and largest relative change) of every
+// running, not yet frozen instance whose previous buffer is valid (outside
+// the captured graph).
 gabp_status launch_probes(gabp_batch *b) {
     bool any = false;
     for (int i = 0; i < b->n; ++i) {
@@ -569,12 +572,13 @@ gabp_status launch_probes(gabp_batch *b) {
         any = true;
         const int dt = b->dtype == GABP_F32 ? 0 : 1;
         char *base = b->ws + H.base;
-        BHIP(b, gabp::launch_bits_differ(dt, base + H.lay.msg[H.iters & 1],
+        BHIP(b, gabp::launch_prec_change(dt, base + H.lay.msg[H.iters & 1],
                                          base + H.lay.msg[(H.iters - 1) & 1],
-                                         (int64_t)H.L.deg * H.L.plane, b->d_bits + i, b->stream));
+                                         (int64_t)H.L.deg * H.L.plane, b->d_bits + i,
+                                         b->d_bits + b->n + i, b->stream));
     }
     if (any)
-        BHIP(b, hipMemcpyAsync(b->p_bits, b->d_bits, sizeof(uint32_t) * (size_t)b->n,
+        BHIP(b, hipMemcpyAsync(b->p_bits, b->d_bits, sizeof(uint32_t) * 2 * (size_t)b->n,
                                hipMemcpyDeviceToHost, b->stream));
     return GABP_OK;
 }
@@ -649,10 +653,11 @@ static gabp_status batch_layout(int32_t n, const gabp_instance *inst, int32_t dt
         off = round_up(off + lay.total, kAlign);
     }
     *tables_off = off;
-    // instance table, 5 int lists, 4 uint flag arrays, partials, results
+    // instance table, int lists, uint arrays (divergence, change counts and
+    // largest changes, counter, error), partials, results
     off = round_up(off + sizeof(BatchInst) * (size_t)n, kAlign);
     off = round_up(off + sizeof(int) * (size_t)lists_ints(n), kAlign);
-    off = round_up(off + sizeof(uint32_t) * (size_t)(3 * n + 2), kAlign);
+    off = round_up(off + sizeof(uint32_t) * (size_t)(4 * n + 2), kAlign);
     off = round_up(off + sizeof(double) * 2 * pc, kAlign);
     off = round_up(off + sizeof(double) * 2 * (size_t)n, kAlign);
     *total = off;
@@ -766,15 +771,15 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     b->d_wpreff[1] = b->d_actf[1] + n;
     off = round_up(off + sizeof(int) * (size_t)lists_ints(n), kAlign);
     b->d_div = (uint32_t *)(b->ws + off);
-    b->d_bits = b->d_div + n;
-    b->d_t = b->d_bits + n;
+    b->d_bits = b->d_div + n;       // [i] changed precision messages, [n + i] largest change
+    b->d_t = b->d_bits + 2 * n;
     b->d_err = b->d_t + 1;
-    off = round_up(off + sizeof(uint32_t) * (size_t)(3 * n + 2), kAlign);
+    off = round_up(off + sizeof(uint32_t) * (size_t)(4 * n + 2), kAlign);
     b->d_partials = (double *)(b->ws + off);
     off = round_up(off + sizeof(double) * 2 * pc, kAlign);
     b->d_out = (double *)(b->ws + off);
-    // pinned mirror: out[2n], div[n], bits[n], t, lists
-    const size_t pin_bytes = sizeof(double) * 2 * (size_t)n + sizeof(uint32_t) * (2 * (size_t)n + 2) +
+    // pinned mirror: out[2n], div[n], bits[2n], t, lists
+    const size_t pin_bytes = sizeof(double) * 2 * (size_t)n + sizeof(uint32_t) * (3 * (size_t)n + 2) +
                              sizeof(int) * (size_t)lists_ints(n) + 64;
     if (hipHostMalloc((void **)&b->p_out, pin_bytes, hipHostMallocDefault) != hipSuccess) {
         b->p_out = nullptr;
@@ -783,7 +788,7 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     }
     b->p_div = (uint32_t *)(b->p_out + 2 * n);
     b->p_bits = b->p_div + n;
-    b->p_t = b->p_bits + n;
+    b->p_t = b->p_bits + 2 * n;
     b->p_lists = (int *)(b->p_t + 2);
     if (hipMemsetAsync(b->ws, 0, total, b->stream) != hipSuccess) {
         b->err = "hipMemsetAsync failed";
@@ -913,7 +918,8 @@ static bool fold_check(gabp_batch *b, double rel_tol, bool probed) {
             changed = true;
             continue;
         }
-        if (probed && !H.frozen && H.prev_valid && H.iters >= 2 && b->p_bits[i] == 0u) {
+        if (probed && !H.frozen && H.prev_valid && H.iters >= 2 &&
+            freeze_now(b->p_bits[i], b->p_bits[b->n + i], b->freeze_slots, b->freeze_rel)) {
             H.frozen = true;
             H.frozen_at = H.iters;
             changed = true;
@@ -979,7 +985,7 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
         BHIP(b, hipStreamSynchronize(b->stream));
         const bool changed = fold_check(b, rel_tol, need_probe);
         if (need_probe) {
-            BHIP(b, hipMemsetAsync(b->d_bits, 0, sizeof(uint32_t) * (size_t)b->n, b->stream));
+            BHIP(b, hipMemsetAsync(b->d_bits, 0, sizeof(uint32_t) * 2 * (size_t)b->n, b->stream));
             for (int i = 0; i < b->n; ++i) {
                 InstHost &H = b->h[i];
                 if (H.frozen && H.frozen_at == H.iters) {
@@ -989,6 +995,15 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
                                               b->dtype == GABP_F32 ? (void *)(base + H.lay.adiag_w)
                                                                    : (void *)(base + H.lay.adiag64),
                                               base + H.lay.gain, b->stream));
+                    // frozen within the tolerance: both buffers get the
+                    // precision messages the gains come from
+                    if (b->p_bits[i] != 0u)
+                        BHIP(b, hipMemcpyAsync(base + H.lay.msg[(H.iters - 1) & 1],
+                                               base + H.lay.msg[H.iters & 1],
+                                               (size_t)H.L.deg * (size_t)H.L.plane *
+                                                   (b->dtype == GABP_F32 ? sizeof(float)
+                                                                         : sizeof(double)),
+                                               hipMemcpyDeviceToDevice, b->stream));
                 }
             }
         }
@@ -1046,6 +1061,15 @@ gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *
     char *base = b->ws + H.base;
     BHIP(b, gabp::launch_msgs_get(b->dtype == GABP_F32 ? 0 : 1, H.L, base + H.lay.msg[H.iters & 1],
                                   prec, info, b->stream));
+    return GABP_OK;
+}
+
+gabp_status gabp_batch_set_freeze_tolerance(gabp_batch *b, int64_t max_slots, double max_rel) {
+    if (!b) return GABP_E_INVALID;
+    if (max_slots < 0 || !(max_rel >= 0.0) || !std::isfinite(max_rel))
+        return bfail(b, GABP_E_INVALID, "need max_slots >= 0 and a finite max_rel >= 0");
+    b->freeze_slots = max_slots;
+    b->freeze_rel = max_rel;
     return GABP_OK;
 }
 

@@ -26,7 +26,7 @@ thread_local std::string g_create_error;
 
 struct HostMirror {
     double red[8];
-    uint32_t flags[4];
+    uint32_t flags[8];
 };
 
 std::string fmt(const char *f, double a = 0, double b = 0) {
@@ -54,7 +54,9 @@ struct gabp_ctx {
     void *adiag_w = nullptr, *b_w = nullptr;
     double *partials = nullptr, *red = nullptr;
     uint32_t *flags = nullptr;     // [0] diverged-at iteration, [1] input error,
-                                   // [2] precision messages changed in the last iteration
+                                   // [3] iteration counter of the launches, [4] precision
+                                   // messages changed by the last iteration and [5] their
+                                   // largest relative change (float bits)
     HostMirror *host = nullptr;    // pinned
     int rpt = 4;                   // rows per thread of the iteration kernel's tile
     int pair = 0;                  // tile height of the two-iteration kernel, 0 = unused
@@ -88,8 +90,10 @@ struct gabp_ctx {
     bool diverged = false;
     bool prev_valid = false;       // the other buffer holds m^{iter-1}
     bool have_ref = false;         // sum |m^2 - m^1| recorded in red[4]
-    bool frozen = false;           // precision messages bitwise stationary
+    bool frozen = false;           // precision messages frozen (gains stored)
     int64_t frozen_at = -1;
+    int64_t freeze_slots = 0;      // freeze tolerance: at most this many precision
+    double freeze_rel = 0.0;       // messages changed, each by at most this (relative)
     std::string err;
 };
 
@@ -120,7 +124,7 @@ gabp_status ctx_ok(gabp_ctx *ctx) {
 // Copy the device flags (and reduction results) to the pinned mirror, wait,
 // and fold a recorded divergence into the host state.
 gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
-    GABP_HIP(ctx, hipMemcpyAsync(ctx->host->flags, ctx->flags, 4 * sizeof(uint32_t),
+    GABP_HIP(ctx, hipMemcpyAsync(ctx->host->flags, ctx->flags, 8 * sizeof(uint32_t),
                                  hipMemcpyDeviceToHost, ctx->stream));
     if (with_red)
         GABP_HIP(ctx, hipMemcpyAsync(ctx->host->red, ctx->red, 8 * sizeof(double),
@@ -563,14 +567,14 @@ gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_resid
     if (st != GABP_OK) return st;
     if (ctx->diverged) return fail(ctx, GABP_E_DIVERGED, "run has diverged");
     const int dt = ctx->dtype == GABP_F32 ? 0 : 1;
-    // Did the last iteration leave every precision message bitwise unchanged?
+    // How many precision messages did the last iteration change, and by how
+    // much at most?
     const bool probe = !ctx->frozen && ctx->prev_valid && ctx->iter >= 2;
     if (probe) {
-        GABP_HIP(ctx, hipMemsetAsync(ctx->flags + 2, 0, sizeof(uint32_t), ctx->stream));
-        GABP_HIP(ctx, gabp::launch_bits_differ(dt, ctx->msg[ctx->cur],
-                                               ctx->msg[ctx->cur ^ 1],
-                                               (int64_t)ctx->L.deg * ctx->L.plane, ctx->flags + 2,
-                                               ctx->stream));
+        GABP_HIP(ctx, hipMemsetAsync(ctx->flags + 4, 0, 2 * sizeof(uint32_t), ctx->stream));
+        GABP_HIP(ctx, gabp::launch_prec_change(dt, ctx->msg[ctx->cur], ctx->msg[ctx->cur ^ 1],
+                                               (int64_t)ctx->L.deg * ctx->L.plane,
+                                               ctx->flags + 4, ctx->flags + 5, ctx->stream));
     }
     GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64,
                                     ctx->frozen ? ctx->bel64 : nullptr, ctx->mu64, nullptr,
@@ -579,10 +583,18 @@ gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_resid
                                      kNumPartials, ctx->red, ctx->stream));
     st = sync_flags(ctx, true);
     if (st != GABP_OK) return st;
-    if (probe && ctx->host->flags[2] == 0u) {
+    if (probe && freeze_now(ctx->host->flags[4], ctx->host->flags[5], ctx->freeze_slots,
+                            ctx->freeze_rel)) {
         // frozen: from now on only the information messages change
         GABP_HIP(ctx, gabp::launch_gain(dt, ctx->L, cur_msgs(ctx), ctx->adiag_w, ctx->gain,
                                         ctx->stream));
+        // frozen within the tolerance: the other buffer's precision messages
+        // still differ in a few places; make both buffers hold the ones the
+        // gains come from
+        if (ctx->host->flags[4] != 0u)
+            GABP_HIP(ctx, hipMemcpyAsync(ctx->msg[ctx->cur ^ 1], ctx->msg[ctx->cur],
+                                         (size_t)ctx->L.deg * (size_t)ctx->L.plane * ctx->esize,
+                                         hipMemcpyDeviceToDevice, ctx->stream));
         ctx->frozen = true;
         ctx->frozen_at = ctx->iter;
     }
@@ -855,6 +867,16 @@ gabp_status gabp_get_tile(const gabp_ctx *ctx, int32_t *rows_per_thread, int32_t
     if (!ctx) return GABP_E_INVALID;
     if (rows_per_thread) *rows_per_thread = ctx->rpt;
     if (pair_rows) *pair_rows = ctx->pair;
+    return GABP_OK;
+}
+
+gabp_status gabp_set_freeze_tolerance(gabp_ctx *ctx, int64_t max_slots, double max_rel) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (max_slots < 0 || !(max_rel >= 0.0) || !std::isfinite(max_rel))
+        return fail(ctx, GABP_E_INVALID, "need max_slots >= 0 and a finite max_rel >= 0");
+    ctx->freeze_slots = max_slots;
+    ctx->freeze_rel = max_rel;
     return GABP_OK;
 }
 

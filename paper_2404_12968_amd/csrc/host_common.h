@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <string>
 
 #include "gabp.h"
@@ -30,6 +31,22 @@ struct Layout {
     size_t adiag64 = 0, b64 = 0, mu64 = 0, bel64 = 0, adiag_w = 0, b_w = 0;
     size_t partials = 0, red = 0, flags = 0, total = 0;
 };
+
+// Freeze decision from one precision-change probe: `changed` messages
+// differed bitwise between the last two iterations, the largest relative
+// change being the float with bits `maxrel_bits`.  With max_slots = 0 only a
+// bitwise stationary iteration freezes (the information-only iteration is
+// then bitwise the full one); otherwise at most max_slots changes of at most
+// max_rel each are tolerated.
+inline bool freeze_now(uint32_t changed, uint32_t maxrel_bits, int64_t max_slots,
+                       double max_rel) {
+    if (changed == 0u) return true;
+    if (max_slots <= 0 || (int64_t)changed > max_slots) return false;
+    float rel;
+    static_assert(sizeof rel == sizeof maxrel_bits, "float bits");
+    std::memcpy(&rel, &maxrel_bits, sizeof rel);
+    return std::isfinite(rel) && (double)rel <= max_rel;
+}
 
 inline Layout make_layout(int64_t nx, int64_t ny, int deg, size_t esize, bool f32) {
     Layout l;
@@ -57,7 +74,7 @@ inline Layout make_layout(int64_t nx, int64_t ny, int deg, size_t esize, bool f3
     }
     l.partials = take((size_t)kNumPartials * 2 * sizeof(double));
     l.red = take(8 * sizeof(double));
-    l.flags = take(4 * sizeof(uint32_t));
+    l.flags = take(8 * sizeof(uint32_t));
     l.total = off;
     return l;
 }

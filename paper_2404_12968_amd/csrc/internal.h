@@ -37,8 +37,11 @@ hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s);
 hipError_t launch_add_u32(uint32_t *p, uint32_t k, hipStream_t s);
 hipError_t launch_gain(int dtype, const Lattice &L, const void *m, const void *adiag, void *gain,
                        hipStream_t s);
-hipError_t launch_bits_differ(int dtype, const void *a, const void *b, int64_t n,
-                              uint32_t *flag, hipStream_t s);
+// Precision-message change between buffers a and b (n elements): adds the
+// number of bitwise differing elements to *count and raises *maxrel (float
+// bits) to their largest relative change.  The caller zeroes both first.
+hipError_t launch_prec_change(int dtype, const void *a, const void *b, int64_t n,
+                              uint32_t *count, uint32_t *maxrel, hipStream_t s);
 // Marginals: bel64 != NULL selects the frozen-precision variant that reads
 // the belief precisions from bel64; otherwise bel_out (may be NULL) receives
 // them.

@@ -328,20 +328,40 @@ __global__ __launch_bounds__(256) void k_msgs_set(Lattice L, T *__restrict__ m,
     }
 }
 
-// Sets *flag when any of n elements differs bitwise between a and b.
+// Change of the precision messages between two buffers: *count += the
+// number of the n elements whose bits differ, *maxrel = max of the relative
+// changes |a - b| / max(|a|, |b|) over them, as the bits of a non-negative
+// float (+inf for a non-finite element), so that unsigned comparison orders
+// them.  Both are independent of the order of the atomics.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bits_differ(const T *__restrict__ a,
+__global__ __launch_bounds__(256) void k_prec_change(const T *__restrict__ a,
                                                      const T *__restrict__ b, int64_t n,
-                                                     uint32_t *__restrict__ flag) {
+                                                     uint32_t *__restrict__ count,
+                                                     uint32_t *__restrict__ maxrel) {
     const int64_t stride = (int64_t)gridDim.x * 256;
-    bool diff = false;
+    uint32_t c = 0u;
+    float mr = 0.0f;
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) {
-        if (sizeof(T) == 4)
-            diff |= __float_as_uint((float)a[k]) != __float_as_uint((float)b[k]);
-        else
-            diff |= __double_as_longlong((double)a[k]) != __double_as_longlong((double)b[k]);
+        const T x = a[k], y = b[k];
+        const bool diff = sizeof(T) == 4
+                              ? __float_as_uint((float)x) != __float_as_uint((float)y)
+                              : __double_as_longlong((double)x) != __double_as_longlong((double)y);
+        if (!diff) continue;
+        ++c;
+        const double dx = (double)x, dy = (double)y, d = fabs(dx - dy);
+        const double m = fmax(fabs(dx), fabs(dy));
+        const float rel = !isfinite(d) || !isfinite(m) ? INFINITY : d == 0.0 ? 0.0f : (float)(d / m);
+        mr = fmaxf(mr, rel);
     }
-    if (diff) *flag = 1u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        c += (uint32_t)__shfl_xor((int)c, o, 64);
+        mr = fmaxf(mr, __shfl_xor(mr, o, 64));
+    }
+    if ((threadIdx.x & 63u) == 0u && c != 0u) {
+        atomicAdd(count, c);
+        atomicMax(maxrel, __float_as_uint(mr));
+    }
 }
 
 // Multigrid transfer: coarse node (i, j) sits on fine node (2i, 2j); every
@@ -415,16 +435,16 @@ static inline int tiles_of(const Lattice &L) {
     return L.tiles_x * ((L.ny + 3) / 4);
 }
 
-hipError_t launch_bits_differ(int dtype, const void *a, const void *b, int64_t n,
-                              uint32_t *flag, hipStream_t s) {
+hipError_t launch_prec_change(int dtype, const void *a, const void *b, int64_t n,
+                              uint32_t *count, uint32_t *maxrel, hipStream_t s) {
     int64_t want = (n + 255) / 256;
     const int nb = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
     if (dtype == 0)
-        hipLaunchKernelGGL((k_bits_differ<float>), dim3(nb), dim3(256), 0, s, (const float *)a,
-                           (const float *)b, n, flag);
+        hipLaunchKernelGGL((k_prec_change<float>), dim3(nb), dim3(256), 0, s, (const float *)a,
+                           (const float *)b, n, count, maxrel);
     else
-        hipLaunchKernelGGL((k_bits_differ<double>), dim3(nb), dim3(256), 0, s, (const double *)a,
-                           (const double *)b, n, flag);
+        hipLaunchKernelGGL((k_prec_change<double>), dim3(nb), dim3(256), 0, s, (const double *)a,
+                           (const double *)b, n, count, maxrel);
     return hipGetLastError();
 }
 

@@ -92,6 +92,8 @@ _SIGS = {
                                ctypes.c_int32, _P, _P], ctypes.c_int),
     "gabp_set_graph": ([_P, ctypes.c_int32], ctypes.c_int),
     "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "gabp_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
+    "gabp_batch_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_get_tile": ([_P, _P, _P], ctypes.c_int),
     "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
                                 ctypes.c_int),
@@ -542,6 +544,17 @@ def gabp_set_graph(ctx: Context, enable: bool) -> None:
 def gabp_set_tile(ctx: Context, rows_per_thread: int, pair_rows: int) -> None:
     """Tile configuration of the iteration kernels (results never depend on it)."""
     _check(_lib.gabp_set_tile(ctx.handle, int(rows_per_thread), int(pair_rows)), ctx)
+
+
+def gabp_set_freeze_tolerance(ctx: Context, max_slots: int, max_rel: float) -> None:
+    """Freeze the precision messages also when at most max_slots of them
+    changed in the last iteration, each by at most max_rel (0: bitwise)."""
+    _check(_lib.gabp_set_freeze_tolerance(ctx.handle, int(max_slots), float(max_rel)), ctx)
+
+
+def gabp_batch_set_freeze_tolerance(b: Batch, max_slots: int, max_rel: float) -> None:
+    """gabp_set_freeze_tolerance for every instance of a batch."""
+    _bcheck(_lib.gabp_batch_set_freeze_tolerance(b.handle, int(max_slots), float(max_rel)), b)
 
 
 def gabp_get_tile(ctx: Context) -> Tuple[int, int]:

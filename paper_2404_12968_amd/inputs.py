@@ -271,25 +271,28 @@ def global32k(instance: int = 0, nx: int = 32768, ny: int = 24576) -> Problem:
                    seed=7000 + instance)
 
 
+def batch256_instance(inst: int, side_lo: int = 64, side_hi: int = 1024) -> Problem:
+    """Instance `inst` of the uneven batch: square side ~ U{64..1024}, alpha ~
+    U{1,2}, kappa ~ U[0.02,0.3], observed fraction ~ U[1 %, 20 %] (uniform
+    cells), sigma ~ U[0.02, 0.2]."""
+    rng = np.random.default_rng(1000 * 4 + inst)
+    side = int(rng.integers(side_lo, side_hi + 1))
+    alpha = int(rng.integers(1, 3))
+    kappa = float(rng.uniform(0.02, 0.3))
+    frac = float(rng.uniform(0.01, 0.20))
+    sigma = float(rng.uniform(0.02, 0.2))
+    truth = spectral_field(side, side, kappa, alpha, rng)
+    cells = uniform_cells(side * side, frac, rng)
+    y = observe(truth, cells, sigma, rng)
+    return Problem(f"batch256[{inst}]", side, side, BC_NEUMANN, BC_NEUMANN,
+                   alpha=alpha, kappa=kappa, tau=1.0, c=DEFAULT_C[alpha],
+                   sigma=sigma, cells=cells, y=y, truth=None, dtype="f32",
+                   damping=0.5, rel_tol=1e-6, seed=4000 + inst)
+
+
 def batch256(count: int = 256, side_lo: int = 64, side_hi: int = 1024) -> List[Problem]:
-    """Uneven batch: square side ~ U{64..1024}, alpha ~ U{1,2}, kappa ~ U[0.02,0.3],
-    observed fraction ~ U[1 %, 20 %] (uniform cells), sigma ~ U[0.02, 0.2]."""
-    out = []
-    for inst in range(count):
-        rng = np.random.default_rng(1000 * 4 + inst)
-        side = int(rng.integers(side_lo, side_hi + 1))
-        alpha = int(rng.integers(1, 3))
-        kappa = float(rng.uniform(0.02, 0.3))
-        frac = float(rng.uniform(0.01, 0.20))
-        sigma = float(rng.uniform(0.02, 0.2))
-        truth = spectral_field(side, side, kappa, alpha, rng)
-        cells = uniform_cells(side * side, frac, rng)
-        y = observe(truth, cells, sigma, rng)
-        out.append(Problem(f"batch256[{inst}]", side, side, BC_NEUMANN, BC_NEUMANN,
-                           alpha=alpha, kappa=kappa, tau=1.0, c=DEFAULT_C[alpha],
-                           sigma=sigma, cells=cells, y=y, truth=None, dtype="f32",
-                           damping=0.5, rel_tol=1e-6, seed=4000 + inst))
-    return out
+    """The uneven batch: `count` instances of batch256_instance."""
+    return [batch256_instance(inst, side_lo, side_hi) for inst in range(count)]
 
 
 def warm1024(instance: int = 0, n: int = 1024, kappa: Optional[float] = None) -> Problem:

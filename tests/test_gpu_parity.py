@@ -653,6 +653,58 @@ def test_batch_solve_matches_single_solves(G, oracle_mod):
         assert torch.equal(mu, mref)
 
 
+def test_freeze_tolerance_freezes_precisions_that_keep_flipping(G, oracle_mod):
+    """Instance 168 of the uneven batch (277^2, 13-point prior): a few FP32
+    precision messages keep changing in their last bit, so the bitwise test
+    never freezes them.  With a tolerance of 64 messages changed by at most
+    1e-6 (relative) they freeze, the solve still reaches the residual
+    tolerance, and the mean is as close to the direct solve as the unfrozen
+    run's."""
+    p = I.batch256_instance(168)
+    strict = G.gabp_create_problem(p)
+    st, it, rel = G.gabp_solve(strict, 30000, 0.5, 1e-6, 10)
+    assert st == G.GABP_OK and G.gabp_precision_frozen(strict) == -1, (st, it)
+    relaxed = G.gabp_create_problem(p)
+    with pytest.raises(G.GabpError):
+        G.gabp_set_freeze_tolerance(relaxed, -1, 0.0)
+    with pytest.raises(G.GabpError):
+        G.gabp_set_freeze_tolerance(relaxed, 8, float("nan"))
+    G.gabp_set_freeze_tolerance(relaxed, 64, 1e-6)
+    st2, it2, rel2 = G.gabp_solve(relaxed, 30000, 0.5, 1e-6, 10)
+    fz = G.gabp_precision_frozen(relaxed)
+    assert st2 == G.GABP_OK and rel2 <= 1e-6
+    assert 0 < fz < it2, (fz, it2)
+    A, b = oracle_mod.posterior_system(p)
+    exact = oracle_mod.direct_solve(A, b)
+    e_s = rel_l2(G.gabp_posterior(strict, want_var=False)[0].cpu().numpy().ravel(), exact)
+    e_r = rel_l2(G.gabp_posterior(relaxed, want_var=False)[0].cpu().numpy().ravel(), exact)
+    assert e_r <= 2 * e_s + 1e-7, (e_r, e_s)
+    G.gabp_destroy(strict)
+    G.gabp_destroy(relaxed)
+
+
+def test_batch_freeze_tolerance_matches_single_contexts(G):
+    """The batch applies the same tolerance at the same checks as lone
+    contexts: iteration counts, freezing iterations and final messages equal
+    bit for bit, and the instance whose precisions keep flipping freezes."""
+    probs = _mixed_problems("f32", 5) + [I.batch256_instance(168)]
+    b = G.gabp_batch_create(probs)
+    G.gabp_batch_set_freeze_tolerance(b, 64, 1e-6)
+    st, its, rels, sts = G.gabp_batch_solve(b, 30000, 0.5, 1e-6, 10)
+    for i, p in enumerate(probs):
+        ctx = G.gabp_create_problem(p)
+        G.gabp_set_freeze_tolerance(ctx, 64, 1e-6)
+        s1, it1, _ = G.gabp_solve(ctx, 30000, 0.5, 1e-6, 10)
+        assert sts[i] == G.GABP_OK and s1 == G.GABP_OK and it1 == its[i], (i, it1, its[i])
+        assert G.gabp_batch_info(b, i)[1] == G.gabp_precision_frozen(ctx), i
+        pa, ia = G.gabp_batch_get_messages(b, i)
+        pb, ib = G.gabp_get_messages(ctx)
+        assert torch.equal(pa, pb) and torch.equal(ia, ib), i
+        G.gabp_destroy(ctx)
+    assert G.gabp_batch_info(b, len(probs) - 1)[1] > 0
+    G.gabp_batch_destroy(b)
+
+
 def test_batch_adaptive_chunks_converge_and_stay_bitwise(G):
     """check_every < 0 grows the chunks once every running instance froze;
     every instance still reaches the tolerance, and its messages equal a lone
