@@ -200,9 +200,11 @@ def bench_table1(G, I, torch, args):
     import numpy as np
     from paper_2404_12968_amd import multigrid as MG
 
+    ft = (args.freeze_slots, args.freeze_rel) if args.freeze_slots > 0 else None
+
     def run(p):
         r = MG.multigrid_solve(p, coarse_stop="message_change", final_stop="message_change",
-                               max_iters=10000, keep_context=True)
+                               max_iters=10000, keep_context=True, freeze_tolerance=ft)
         mu = G.gabp_posterior(r["ctx"], want_var=False)[0].cpu().numpy().ravel()
         G.gabp_destroy(r["ctx"])
         return r, float(np.sqrt(np.mean((mu - p.truth.ravel()) ** 2)))
@@ -245,7 +247,9 @@ def bench_table1(G, I, torch, args):
                                    "length scale 0.15, sigma_f 1.1, sigma_y 0.01, uniform "
                                    "random observations; multigrid from 32^2, c=10, eta=0.6, "
                                    "early stop 1e-3, T=10000 per level",
-                       "truths_per_config": args.table1_truths, "parallelism": "single GPU"},
+                       "truths_per_config": args.table1_truths, "parallelism": "single GPU",
+                       "freeze_tolerance": {"max_slots": ft[0] if ft else 0,
+                                            "max_rel": ft[1] if ft else 0.0}},
             "baseline_note": f"paper: {paper_total:.1f} s on one RTX 3090 (Table 1 MP column)",
             "rows": rows}
 
@@ -266,10 +270,10 @@ def main(argv=None):
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
     ap.add_argument("--warm-instances", type=int, default=3)
     ap.add_argument("--freeze-slots", type=int, default=64,
-                    help="batch256: freeze an instance's precision messages when at most this many "
-                         "changed in the last iteration (0: only when none did)")
+                    help="batch256 and table1: freeze the precision messages when at most this "
+                         "many changed in the last iteration (0: only when none did)")
     ap.add_argument("--freeze-rel", type=float, default=1e-6,
-                    help="batch256: ... each by at most this relative change")
+                    help="batch256 and table1: ... each by at most this relative change")
     ap.add_argument("--table1-truths", type=int, default=3,
                     help="ground truths per Table 1 configuration")
     ap.add_argument("--no-table1", action="store_true",

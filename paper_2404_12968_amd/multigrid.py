@@ -68,16 +68,19 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
                     coarse_tol: Optional[float] = None, max_iters: int = 300000,
                     check_every: int = -10, device="cuda", keep_context: bool = False,
                     coarse_stop: str = "residual", final_stop: str = "residual",
-                    final_tol: Optional[float] = None, transfer: str = "messages"):
+                    final_tol: Optional[float] = None, transfer: str = "messages",
+                    freeze_tolerance: Optional[tuple] = None):
     """Solve coarse-to-fine.  `levels` defaults to halving down to a 32-node
     short side (the paper's base grid); `coarse_tol` defaults to the problem's
     own residual tolerance (1e-3 for the message-change rule).  The target
     level stops at the problem's residual tolerance, or with
     `final_stop="message_change"` by the early-stop rule at `final_tol`
     (default 1e-3), the paper's own setting.  Returns a dict
-    with the final status, the iterations per level (coarsest first), the
+    with the final status, the iterations and the iteration at which the
+    precision messages froze (-1: never) per level (coarsest first), the
     fine-level iterations, the total seconds, and (keep_context) the fine
-    context."""
+    context.  freeze_tolerance = (max_slots, max_rel) is passed to every
+    level's gabp_set_freeze_tolerance."""
     if coarse_stop not in ("residual", "message_change") or \
             final_stop not in ("residual", "message_change"):
         raise ValueError("coarse_stop and final_stop are 'residual' or 'message_change'")
@@ -97,6 +100,8 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
     for lev in reversed(range(levels)):
         p = level_problem(prob, lev)
         ctx = G.gabp_create_problem(p, device=device)
+        if freeze_tolerance is not None:
+            G.gabp_set_freeze_tolerance(ctx, *freeze_tolerance)
         if pred is not None:
             G.gabp_warm_init(ctx, pred, keep_precisions=(transfer == "mean"))
         if lev == 0 and final_stop == "message_change":
@@ -114,7 +119,8 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
             st, it, rel = G.gabp_solve_early_stop(ctx, max_iters, p.damping, coarse_tol,
                                                   check_every)
         per_level.append({"level": lev, "nx": p.nx, "ny": p.ny, "iterations": it,
-                          "status": st, "rel": rel, "observations": int(p.cells.size)})
+                          "status": st, "rel": rel, "observations": int(p.cells.size),
+                          "frozen_at": G.gabp_precision_frozen(ctx)})
         if st == G.GABP_E_DIVERGED:
             break
         if lev > 0:
