@@ -321,12 +321,15 @@ struct gabp_batch {
     int *d_actu = nullptr, *d_wprefu = nullptr;   // running, precision not frozen (1 iteration)
     int *d_actf[2] = {nullptr, nullptr}, *d_wpreff[2] = {nullptr, nullptr};
                                                   // running, frozen, by prior order (2 per launch)
-    uint32_t *d_div = nullptr, *d_bits = nullptr, *d_t = nullptr, *d_err = nullptr;
+    uint32_t *d_div = nullptr, *d_t = nullptr, *d_err = nullptr;
+    unsigned long long *d_cnt = nullptr;   // changed precision messages per instance
+    uint32_t *d_mrel = nullptr;            // their largest relative change (float bits)
     double *d_partials = nullptr, *d_out = nullptr;
     size_t partial_cap = 0;     // work items of the check kernels
     // pinned host mirror
     double *p_out = nullptr;
-    uint32_t *p_div = nullptr, *p_bits = nullptr, *p_t = nullptr;
+    uint32_t *p_div = nullptr, *p_mrel = nullptr, *p_t = nullptr;
+    unsigned long long *p_cnt = nullptr;
     int *p_lists = nullptr;     // staging for act / prefixes / frozen / probe
     int rpt = 4;
     int pair = 0;               // tile height of the two-iteration kernel, 0 = unused
@@ -389,6 +392,8 @@ int tiles_pair_of(const Lattice &L, int th) {
 // lists staging / device layout: act[n] wprefix[n+1] pprefix[n+1] frozen[n]
 // probe[n] actu[n] wprefu[n+1], then actf[n] wpreff[n+1] for alpha = 1 and 2
 constexpr int lists_ints(int n) { return 11 * n + 5; }
+// flag region: div[n], t, err, mrel[n] (uint32), then cnt[n] (uint64, 8-aligned)
+constexpr size_t flag_bytes(int n) { return 4 * (2 * (size_t)n + 2) + 4 + 8 * (size_t)n; }
 
 void drop_graph(gabp_batch *b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -574,12 +579,15 @@ gabp_status launch_probes(gabp_batch *b) {
         char *base = b->ws + H.base;
         BHIP(b, gabp::launch_prec_change(dt, base + H.lay.msg[H.iters & 1],
                                          base + H.lay.msg[(H.iters - 1) & 1],
-                                         (int64_t)H.L.deg * H.L.plane, b->d_bits + i,
-                                         b->d_bits + b->n + i, b->stream));
+                                         (int64_t)H.L.deg * H.L.plane, b->d_cnt + i,
+                                         b->d_mrel + i, b->stream));
     }
-    if (any)
-        BHIP(b, hipMemcpyAsync(b->p_bits, b->d_bits, sizeof(uint32_t) * 2 * (size_t)b->n,
+    if (any) {
+        BHIP(b, hipMemcpyAsync(b->p_cnt, b->d_cnt, sizeof(unsigned long long) * (size_t)b->n,
                                hipMemcpyDeviceToHost, b->stream));
+        BHIP(b, hipMemcpyAsync(b->p_mrel, b->d_mrel, sizeof(uint32_t) * (size_t)b->n,
+                               hipMemcpyDeviceToHost, b->stream));
+    }
     return GABP_OK;
 }
 
@@ -653,11 +661,12 @@ static gabp_status batch_layout(int32_t n, const gabp_instance *inst, int32_t dt
         off = round_up(off + lay.total, kAlign);
     }
     *tables_off = off;
-    // instance table, int lists, uint arrays (divergence, change counts and
-    // largest changes, counter, error), partials, results
+    // instance table, int lists, flag arrays (divergence, counter, error and
+    // largest precision changes as uint32, then 64-bit change counts),
+    // partials, results
     off = round_up(off + sizeof(BatchInst) * (size_t)n, kAlign);
     off = round_up(off + sizeof(int) * (size_t)lists_ints(n), kAlign);
-    off = round_up(off + sizeof(uint32_t) * (size_t)(4 * n + 2), kAlign);
+    off = round_up(off + flag_bytes(n), kAlign);
     off = round_up(off + sizeof(double) * 2 * pc, kAlign);
     off = round_up(off + sizeof(double) * 2 * (size_t)n, kAlign);
     *total = off;
@@ -771,24 +780,27 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     b->d_wpreff[1] = b->d_actf[1] + n;
     off = round_up(off + sizeof(int) * (size_t)lists_ints(n), kAlign);
     b->d_div = (uint32_t *)(b->ws + off);
-    b->d_bits = b->d_div + n;       // [i] changed precision messages, [n + i] largest change
-    b->d_t = b->d_bits + 2 * n;
+    b->d_t = b->d_div + n;
     b->d_err = b->d_t + 1;
-    off = round_up(off + sizeof(uint32_t) * (size_t)(4 * n + 2), kAlign);
+    b->d_mrel = b->d_err + 1;
+    b->d_cnt = (unsigned long long *)(b->ws + round_up(off + sizeof(uint32_t) * (size_t)(2 * n + 2), 8));
+    off = round_up(off + flag_bytes(n), kAlign);
     b->d_partials = (double *)(b->ws + off);
     off = round_up(off + sizeof(double) * 2 * pc, kAlign);
     b->d_out = (double *)(b->ws + off);
-    // pinned mirror: out[2n], div[n], bits[2n], t, lists
-    const size_t pin_bytes = sizeof(double) * 2 * (size_t)n + sizeof(uint32_t) * (3 * (size_t)n + 2) +
+    // pinned mirror: out[2n], cnt[n], div[n], mrel[n], t, lists
+    const size_t pin_bytes = sizeof(double) * 2 * (size_t)n + sizeof(unsigned long long) * (size_t)n +
+                             sizeof(uint32_t) * (2 * (size_t)n + 2) +
                              sizeof(int) * (size_t)lists_ints(n) + 64;
     if (hipHostMalloc((void **)&b->p_out, pin_bytes, hipHostMallocDefault) != hipSuccess) {
         b->p_out = nullptr;
         b->err = "pinned host allocation failed";
         return bail(GABP_E_NOMEM);
     }
-    b->p_div = (uint32_t *)(b->p_out + 2 * n);
-    b->p_bits = b->p_div + n;
-    b->p_t = b->p_bits + 2 * n;
+    b->p_cnt = (unsigned long long *)(b->p_out + 2 * n);
+    b->p_div = (uint32_t *)(b->p_cnt + n);
+    b->p_mrel = b->p_div + n;
+    b->p_t = b->p_mrel + n;
     b->p_lists = (int *)(b->p_t + 2);
     if (hipMemsetAsync(b->ws, 0, total, b->stream) != hipSuccess) {
         b->err = "hipMemsetAsync failed";
@@ -919,7 +931,7 @@ static bool fold_check(gabp_batch *b, double rel_tol, bool probed) {
             continue;
         }
         if (probed && !H.frozen && H.prev_valid && H.iters >= 2 &&
-            freeze_now(b->p_bits[i], b->p_bits[b->n + i], b->freeze_slots, b->freeze_rel)) {
+            freeze_now(b->p_cnt[i], b->p_mrel[i], b->freeze_slots, b->freeze_rel)) {
             H.frozen = true;
             H.frozen_at = H.iters;
             changed = true;
@@ -985,7 +997,8 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
         BHIP(b, hipStreamSynchronize(b->stream));
         const bool changed = fold_check(b, rel_tol, need_probe);
         if (need_probe) {
-            BHIP(b, hipMemsetAsync(b->d_bits, 0, sizeof(uint32_t) * 2 * (size_t)b->n, b->stream));
+            BHIP(b, hipMemsetAsync(b->d_cnt, 0, sizeof(unsigned long long) * (size_t)b->n, b->stream));
+            BHIP(b, hipMemsetAsync(b->d_mrel, 0, sizeof(uint32_t) * (size_t)b->n, b->stream));
             for (int i = 0; i < b->n; ++i) {
                 InstHost &H = b->h[i];
                 if (H.frozen && H.frozen_at == H.iters) {
@@ -997,7 +1010,7 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
                                               base + H.lay.gain, b->stream));
                     // frozen within the tolerance: both buffers get the
                     // precision messages the gains come from
-                    if (b->p_bits[i] != 0u)
+                    if (b->p_cnt[i] != 0u)
                         BHIP(b, hipMemcpyAsync(base + H.lay.msg[(H.iters - 1) & 1],
                                                base + H.lay.msg[H.iters & 1],
                                                (size_t)H.L.deg * (size_t)H.L.plane *

@@ -54,9 +54,9 @@ struct gabp_ctx {
     void *adiag_w = nullptr, *b_w = nullptr;
     double *partials = nullptr, *red = nullptr;
     uint32_t *flags = nullptr;     // [0] diverged-at iteration, [1] input error,
-                                   // [3] iteration counter of the launches, [4] precision
-                                   // messages changed by the last iteration and [5] their
-                                   // largest relative change (float bits)
+                                   // [3] iteration counter of the launches, [4, 5] precision
+                                   // messages changed by the last iteration (64-bit) and
+                                   // [6] their largest relative change (float bits)
     HostMirror *host = nullptr;    // pinned
     int rpt = 4;                   // rows per thread of the iteration kernel's tile
     int pair = 0;                  // tile height of the two-iteration kernel, 0 = unused
@@ -571,10 +571,11 @@ gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_resid
     // much at most?
     const bool probe = !ctx->frozen && ctx->prev_valid && ctx->iter >= 2;
     if (probe) {
-        GABP_HIP(ctx, hipMemsetAsync(ctx->flags + 4, 0, 2 * sizeof(uint32_t), ctx->stream));
+        GABP_HIP(ctx, hipMemsetAsync(ctx->flags + 4, 0, 3 * sizeof(uint32_t), ctx->stream));
         GABP_HIP(ctx, gabp::launch_prec_change(dt, ctx->msg[ctx->cur], ctx->msg[ctx->cur ^ 1],
                                                (int64_t)ctx->L.deg * ctx->L.plane,
-                                               ctx->flags + 4, ctx->flags + 5, ctx->stream));
+                                               (unsigned long long *)(ctx->flags + 4),
+                                               ctx->flags + 6, ctx->stream));
     }
     GABP_HIP(ctx, gabp::launch_post(dt, ctx->L, cur_msgs(ctx), ctx->adiag64, ctx->b64,
                                     ctx->frozen ? ctx->bel64 : nullptr, ctx->mu64, nullptr,
@@ -583,15 +584,16 @@ gabp_status gabp_residual(gabp_ctx *ctx, double *rel_residual, double *abs_resid
                                      kNumPartials, ctx->red, ctx->stream));
     st = sync_flags(ctx, true);
     if (st != GABP_OK) return st;
-    if (probe && freeze_now(ctx->host->flags[4], ctx->host->flags[5], ctx->freeze_slots,
-                            ctx->freeze_rel)) {
+    uint64_t changed = 0;
+    std::memcpy(&changed, ctx->host->flags + 4, sizeof changed);
+    if (probe && freeze_now(changed, ctx->host->flags[6], ctx->freeze_slots, ctx->freeze_rel)) {
         // frozen: from now on only the information messages change
         GABP_HIP(ctx, gabp::launch_gain(dt, ctx->L, cur_msgs(ctx), ctx->adiag_w, ctx->gain,
                                         ctx->stream));
         // frozen within the tolerance: the other buffer's precision messages
         // still differ in a few places; make both buffers hold the ones the
         // gains come from
-        if (ctx->host->flags[4] != 0u)
+        if (changed != 0u)
             GABP_HIP(ctx, hipMemcpyAsync(ctx->msg[ctx->cur ^ 1], ctx->msg[ctx->cur],
                                          (size_t)ctx->L.deg * (size_t)ctx->L.plane * ctx->esize,
                                          hipMemcpyDeviceToDevice, ctx->stream));

@@ -38,10 +38,10 @@ struct Layout {
 // bitwise stationary iteration freezes (the information-only iteration is
 // then bitwise the full one); otherwise at most max_slots changes of at most
 // max_rel each are tolerated.
-inline bool freeze_now(uint32_t changed, uint32_t maxrel_bits, int64_t max_slots,
+inline bool freeze_now(uint64_t changed, uint32_t maxrel_bits, int64_t max_slots,
                        double max_rel) {
     if (changed == 0u) return true;
-    if (max_slots <= 0 || (int64_t)changed > max_slots) return false;
+    if (max_slots <= 0 || changed > (uint64_t)max_slots) return false;
     float rel;
     static_assert(sizeof rel == sizeof maxrel_bits, "float bits");
     std::memcpy(&rel, &maxrel_bits, sizeof rel);

@@ -41,7 +41,7 @@ hipError_t launch_gain(int dtype, const Lattice &L, const void *m, const void *a
 // number of bitwise differing elements to *count and raises *maxrel (float
 // bits) to their largest relative change.  The caller zeroes both first.
 hipError_t launch_prec_change(int dtype, const void *a, const void *b, int64_t n,
-                              uint32_t *count, uint32_t *maxrel, hipStream_t s);
+                              unsigned long long *count, uint32_t *maxrel, hipStream_t s);
 // Marginals: bel64 != NULL selects the frozen-precision variant that reads
 // the belief precisions from bel64; otherwise bel_out (may be NULL) receives
 // them.

@@ -329,17 +329,18 @@ __global__ __launch_bounds__(256) void k_msgs_set(Lattice L, T *__restrict__ m,
 }
 
 // Change of the precision messages between two buffers: *count += the
-// number of the n elements whose bits differ, *maxrel = max of the relative
+// number of the n elements whose bits differ (64-bit: n may exceed 2^32),
+// *maxrel = max of the relative
 // changes |a - b| / max(|a|, |b|) over them, as the bits of a non-negative
 // float (+inf for a non-finite element), so that unsigned comparison orders
 // them.  Both are independent of the order of the atomics.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prec_change(const T *__restrict__ a,
                                                      const T *__restrict__ b, int64_t n,
-                                                     uint32_t *__restrict__ count,
+                                                     unsigned long long *__restrict__ count,
                                                      uint32_t *__restrict__ maxrel) {
     const int64_t stride = (int64_t)gridDim.x * 256;
-    uint32_t c = 0u;
+    uint32_t c = 0u;   // per thread: at most n / stride + 1 elements
     float mr = 0.0f;
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += stride) {
         const T x = a[k], y = b[k];
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void k_prec_change(const T *__restrict__ a,
         mr = fmaxf(mr, __shfl_xor(mr, o, 64));
     }
     if ((threadIdx.x & 63u) == 0u && c != 0u) {
-        atomicAdd(count, c);
+        atomicAdd(count, (unsigned long long)c);
         atomicMax(maxrel, __float_as_uint(mr));
     }
 }
@@ -436,7 +437,7 @@ static inline int tiles_of(const Lattice &L) {
 }
 
 hipError_t launch_prec_change(int dtype, const void *a, const void *b, int64_t n,
-                              uint32_t *count, uint32_t *maxrel, hipStream_t s) {
+                              unsigned long long *count, uint32_t *maxrel, hipStream_t s) {
     int64_t want = (n + 255) / 256;
     const int nb = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
     if (dtype == 0)
