@@ -158,6 +158,24 @@ def bench_batch(G, I, torch, dev, args):
     updates = float((Es * its).sum())
     frozen = [G.gabp_batch_info(b, i)[1] for i in range(len(probs))]
     a2 = np.array([p.alpha == 2 for p in probs])
+    del b
+    mg = None
+    if not args.no_multigrid:
+        from paper_2404_12968_amd import multigrid as MG
+        ft = (args.freeze_slots, args.freeze_rel) if args.freeze_slots > 0 else None
+        r = MG.multigrid_batch_solve(probs, max_iters=max(args.solve_max_iters, 300000),
+                                     freeze_tolerance=ft)
+        fi = np.asarray(r["iterations"])
+        mg = {"seconds": r["seconds"], "status": G.gabp_status_string(r["status"]),
+              "converged": int((np.asarray(r["statuses"]) == G.GABP_OK).sum()),
+              "speedup": wall / r["seconds"],
+              "fine_iterations_alpha1": [int(fi[~a2].min()), int(np.median(fi[~a2])), int(fi[~a2].max())],
+              "fine_iterations_alpha2": [int(fi[a2].min()), int(np.median(fi[a2])), int(fi[a2].max())],
+              "max_rel_residual": float(np.max(r["rel"])),
+              "levels": [{"level": lv["level"], "instances": lv["instances"],
+                          "max_iterations": max(lv["iterations"])} for lv in r["levels"]],
+              "note": "every level's batch set-up (inputs to device) and the transfers are "
+                      "inside the time; the one-level time above excludes its set-up"}
     return {
         "metric": METRIC, "value": updates / wall, "unit": "edge-message updates/s",
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3,
@@ -184,6 +202,7 @@ def bench_batch(G, I, torch, dev, args):
                                      "coverage": probs[i].coverage, "rel": float(rels[i]),
                                      "iterations": int(its[i])}
                                     for i in np.nonzero(sts != G.GABP_OK)[0]]},
+        "multigrid": mg,
     }
 
 

@@ -371,6 +371,19 @@ gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *
  * every running instance by 1 + 8 * trials iterations). */
 gabp_status gabp_batch_autotune(gabp_batch *b, int32_t trials, double damping, int32_t *chosen);
 
+/* gabp_warm_init for instance i of a batch (its current messages; the
+ * prediction has the instance's own nx, ny): the instance's freeze state is
+ * reset.  Asynchronous on the batch's stream.  INVALID for an index out of
+ * range or a NULL pred, DIVERGED for an instance that diverged. */
+gabp_status gabp_batch_warm_init(gabp_batch *b, int32_t i, const float *pred,
+                                 int32_t keep_precisions);
+
+/* gabp_upscale_precisions from instance i of a batch (as the coarse
+ * context) into a finer prediction pred[nyf][nxf][16].  Asynchronous on the
+ * batch's stream; INVALID as gabp_upscale_precisions. */
+gabp_status gabp_batch_upscale_precisions(gabp_batch *b, int32_t i, float *pred, int64_t nxf,
+                                          int64_t nyf, double scale);
+
 /* The batch's freeze tolerance, as gabp_set_freeze_tolerance's, for every
  * instance (default max_slots = 0: bitwise test). */
 gabp_status gabp_batch_set_freeze_tolerance(gabp_batch *b, int64_t max_slots, double max_rel);

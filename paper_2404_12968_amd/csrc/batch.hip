@@ -1077,6 +1077,43 @@ gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *
     return GABP_OK;
 }
 
+gabp_status gabp_batch_warm_init(gabp_batch *b, int32_t i, const float *pred,
+                                 int32_t keep_precisions) {
+    if (!b) return GABP_E_INVALID;
+    if (i < 0 || i >= b->n || !pred) return bfail(b, GABP_E_INVALID, "need 0 <= i < n and a pred");
+    StreamJoin join(b);
+    if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
+    InstHost &H = b->h[i];
+    if (H.status == GABP_E_DIVERGED) return bfail(b, GABP_E_DIVERGED, "instance has diverged");
+    char *base = b->ws + H.base;
+    BHIP(b, gabp::launch_warm_init(b->dtype == GABP_F32 ? 0 : 1, H.L, pred, keep_precisions ? 1 : 0,
+                                   base + H.lay.msg[H.iters & 1], b->stream));
+    H.prev_valid = false;
+    if (H.frozen) b->lists_dirty = true;
+    H.frozen = false;
+    H.frozen_at = -1;
+    return GABP_OK;
+}
+
+gabp_status gabp_batch_upscale_precisions(gabp_batch *b, int32_t i, float *pred, int64_t nxf,
+                                          int64_t nyf, double scale) {
+    if (!b) return GABP_E_INVALID;
+    if (i < 0 || i >= b->n || !pred) return bfail(b, GABP_E_INVALID, "need 0 <= i < n and a pred");
+    const InstHost &H = b->h[i];
+    if (nxf < 1 || nyf < 1 || (nxf + 1) / 2 != H.L.nx || (nyf + 1) / 2 != H.L.ny)
+        return bfail(b, GABP_E_INVALID,
+                     "upscale_precisions: need ceil(nxf / 2) = nx and ceil(nyf / 2) = ny of the instance");
+    if (!(scale > 0.0) || !std::isfinite(scale))
+        return bfail(b, GABP_E_INVALID, "upscale_precisions: scale must be finite and > 0");
+    StreamJoin join(b);
+    if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
+    char *base = b->ws + H.base;
+    BHIP(b, gabp::launch_upscale_prec(b->dtype == GABP_F32 ? 0 : 1, H.L,
+                                      base + H.lay.msg[H.iters & 1], (float)scale, pred, (int)nxf,
+                                      (int)nyf, b->stream));
+    return GABP_OK;
+}
+
 gabp_status gabp_batch_set_freeze_tolerance(gabp_batch *b, int64_t max_slots, double max_rel) {
     if (!b) return GABP_E_INVALID;
     if (max_slots < 0 || !(max_rel >= 0.0) || !std::isfinite(max_rel))

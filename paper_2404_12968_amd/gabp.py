@@ -94,6 +94,9 @@ _SIGS = {
     "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "gabp_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_batch_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
+    "gabp_batch_warm_init": ([_P, ctypes.c_int32, _P, ctypes.c_int32], ctypes.c_int),
+    "gabp_batch_upscale_precisions": ([_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_double], ctypes.c_int),
     "gabp_get_tile": ([_P, _P, _P], ctypes.c_int),
     "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
                                 ctypes.c_int),
@@ -348,6 +351,7 @@ class Batch:
         self.dtype = dtype
         self.device = device
         self.stream = stream
+        self._keep = {}               # predictions read by queued warm starts
 
     @property
     def n(self) -> int:
@@ -423,6 +427,27 @@ def gabp_batch_posterior(b: Batch, i: int, want_var: bool = True):
     var = torch.empty((ny, nx), dtype=torch.float64, device=b.device) if want_var else None
     _bcheck(_lib.gabp_batch_posterior(b.handle, int(i), _ptr(mean), _ptr(var)), b)
     return mean, var
+
+
+def gabp_batch_warm_init(b: Batch, i: int, pred: torch.Tensor,
+                         keep_precisions: bool = False) -> None:
+    """gabp_warm_init for instance i: pred FP32 [ny, nx, 16] of that instance."""
+    nx, ny, _ = b.shapes[i]
+    if pred.dtype != torch.float32 or tuple(pred.shape) != (ny, nx, 16) or not pred.is_cuda:
+        raise ValueError("pred must be a CUDA float32 tensor of shape (ny, nx, 16)")
+    pred = pred.contiguous()
+    _bcheck(_lib.gabp_batch_warm_init(b.handle, int(i), _ptr(pred), int(bool(keep_precisions))), b)
+    b._keep[int(i)] = pred
+
+
+def gabp_batch_upscale_precisions(b: Batch, i: int, pred: torch.Tensor, scale: float) -> None:
+    """gabp_upscale_precisions with instance i as the coarse lattice."""
+    if pred.dtype != torch.float32 or pred.dim() != 3 or pred.shape[2] != 16 or \
+            not pred.is_contiguous():
+        raise ValueError("pred must be a contiguous float32 [nyf, nxf, 16] tensor")
+    nyf, nxf, _ = pred.shape
+    _bcheck(_lib.gabp_batch_upscale_precisions(b.handle, int(i), _ptr(pred), int(nxf), int(nyf),
+                                               float(scale)), b)
 
 
 def gabp_batch_get_messages(b: Batch, i: int):

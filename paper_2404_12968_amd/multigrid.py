@@ -136,3 +136,64 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
     if keep_context:
         out["ctx"] = ctx
     return out
+
+
+def multigrid_batch_solve(probs: List[I.Problem], levels: Optional[int] = None,
+                          max_iters: int = 300000, check_every: int = -10, device="cuda",
+                          freeze_tolerance: Optional[tuple] = None, keep_batch: bool = False):
+    """Every instance solved coarse to fine as multigrid_solve does (every
+    level to the instances' residual tolerance, precision messages carried
+    over), one batch per level: the batch of level l holds the instances that
+    have a level l (each has max_levels(p) levels, at most `levels`), and each
+    of them starts from its own level-(l+1) solution.  The instances must
+    share damping and tolerance.  Returns a dict with the final statuses,
+    iterations and residuals (input order), per-level instance counts and
+    iterations, the total seconds (level set-up and transfers included) and
+    (keep_batch) the final batch."""
+    n = len(probs)
+    damping, rel_tol = probs[0].damping, probs[0].rel_tol
+    if any(p.damping != damping or p.rel_tol != rel_tol for p in probs):
+        raise ValueError("batch instances must share damping and rel_tol")
+    nlev = [max_levels(p, coarsest=32) for p in probs]
+    if levels is not None:
+        nlev = [min(levels, k) for k in nlev]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    preds: List[Optional[torch.Tensor]] = [None] * n
+    per_level: List[dict] = []
+    out = None
+    for lev in reversed(range(max(nlev))):
+        members = [i for i in range(n) if nlev[i] > lev]
+        lp = [level_problem(probs[i], lev) for i in members]
+        b = G.gabp_batch_create(lp, device=device)
+        if freeze_tolerance is not None:
+            G.gabp_batch_set_freeze_tolerance(b, *freeze_tolerance)
+        for k, i in enumerate(members):
+            if preds[i] is not None:
+                G.gabp_batch_warm_init(b, k, preds[i], keep_precisions=False)
+                preds[i] = None
+        st, its, rels, sts = G.gabp_batch_solve(b, max_iters, damping, rel_tol, check_every)
+        per_level.append({"level": lev, "instances": len(members),
+                          "iterations": [int(v) for v in its],
+                          "status": [int(v) for v in sts]})
+        if lev > 0:
+            for k, i in enumerate(members):
+                if sts[k] == G.GABP_E_DIVERGED:
+                    continue             # the next level starts cold
+                mean, _ = G.gabp_batch_posterior(b, k, want_var=False)
+                fine = level_problem(probs[i], lev - 1)
+                pred = G.gabp_upsample_mean(mean, lp[k].bc_x, lp[k].bc_y, fine.nx, fine.ny)
+                G.gabp_batch_upscale_precisions(b, k, pred, 4.0 ** (probs[i].alpha - 1))
+                preds[i] = pred
+            torch.cuda.synchronize()
+            G.gabp_batch_destroy(b)
+        else:
+            out = {"status": st, "statuses": sts, "iterations": its, "rel": rels, "batch": b}
+    torch.cuda.synchronize()
+    res = {"status": out["status"], "statuses": out["statuses"], "iterations": out["iterations"],
+           "rel": out["rel"], "levels": per_level, "seconds": time.perf_counter() - t0}
+    if keep_batch:
+        res["batch"] = out["batch"]
+    else:
+        G.gabp_batch_destroy(out["batch"])
+    return res

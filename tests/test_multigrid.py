@@ -185,3 +185,41 @@ def test_multigrid_paper_early_stop_rule():
     assert res["levels"][-1]["rel"] <= 1e-6
     with pytest.raises(ValueError):
         MG.multigrid_solve(p, 2, coarse_stop="bogus")
+
+
+@pytest.mark.gpu
+def test_multigrid_batch_solve_reaches_the_tolerance(oracle_mod):
+    """Batched multigrid: one batch per level holding the instances that have
+    that level (here 3 of 4; the 40 x 40 instance has only its own level),
+    each warm-started from its own coarser solution.  Every instance ends at
+    the residual tolerance of the oracle's assembled system, in fewer
+    iterations in all than a cold batch."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp as G
+    probs = [I.small_lattice(128, 96, 2, kappa=0.3, tracks=4, run=3, sigma=0.05, seed=21,
+                             dtype="f32"),
+             I.small_lattice(192, 64, 2, bc_x=I.BC_PERIODIC, kappa=0.25, tracks=4, run=3,
+                             sigma=0.05, seed=22, dtype="f32"),
+             I.small_lattice(100, 70, 1, kappa=0.2, frac=0.05, sigma=0.05, seed=23, dtype="f32"),
+             I.small_lattice(40, 40, 2, kappa=0.4, frac=0.1, sigma=0.05, seed=24, dtype="f32")]
+    for p in probs:
+        p.rel_tol = 1e-6
+        p.damping = 0.5
+    res = MG.multigrid_batch_solve(probs, keep_batch=True)
+    assert res["status"] == G.GABP_OK and all(s == G.GABP_OK for s in res["statuses"])
+    assert [lv["instances"] for lv in res["levels"]] == [3, 4]
+    b = res["batch"]
+    for k, p in enumerate(probs):
+        A, rhs = oracle_mod.posterior_system(p)
+        mu = G.gabp_batch_posterior(b, k, want_var=False)[0].cpu().numpy().ravel()
+        assert np.linalg.norm(A @ mu - rhs) / np.linalg.norm(rhs) <= 1.01e-6, k
+    cold = G.gabp_batch_create(probs)
+    st, cold_its, _, _ = G.gabp_batch_solve(cold, 300000, 0.5, 1e-6, -10)
+    assert st == G.GABP_OK
+    assert int(np.sum(res["iterations"])) < int(np.sum(cold_its))
+    with pytest.raises(ValueError):
+        q = [I.small_lattice(40, 40, 2, seed=1, dtype="f32"), I.small_lattice(40, 40, 2, seed=2, dtype="f32")]
+        q[1].damping = 0.7
+        MG.multigrid_batch_solve(q)
