@@ -172,12 +172,24 @@ class TrainingSet:
 
 
 def solve_training_set(problems: Sequence[I.Problem], max_iters: int = 300000,
-                       rel_tol: float = 1e-6, device="cuda", log=print) -> TrainingSet:
-    """Solve the problems with the batched solver and keep features + targets."""
+                       rel_tol: float = 1e-6, device="cuda", log=print,
+                       multigrid: bool = False) -> TrainingSet:
+    """Solve the problems with the batched solver (multigrid: batched
+    coarse-to-fine, the same fixed points at the same residual tolerance) and
+    keep features + targets."""
     ts = TrainingSet()
     t0 = time.time()
-    b = G.gabp_batch_create(list(problems), device=device)
-    st, its, rels, sts = G.gabp_batch_solve(b, max_iters, 0.5, rel_tol, -10)
+    if multigrid:
+        from . import multigrid as MG
+        probs = list(problems)
+        for p in probs:
+            p.rel_tol = rel_tol
+        res = MG.multigrid_batch_solve(probs, max_iters=max_iters, device=device,
+                                       keep_batch=True)
+        b, its, sts = res["batch"], np.asarray(res["iterations"]), np.asarray(res["statuses"])
+    else:
+        b = G.gabp_batch_create(list(problems), device=device)
+        st, its, rels, sts = G.gabp_batch_solve(b, max_iters, 0.5, rel_tol, -10)
     torch.cuda.synchronize()
     log(f"[warm] solved {len(problems)} problems in {time.time() - t0:.1f}s: "
         f"{int((sts == G.GABP_OK).sum())} converged, iterations median {int(np.median(its))}")

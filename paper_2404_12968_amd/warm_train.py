@@ -41,6 +41,8 @@ def main(argv=None):
                     help="training problems are seeds seed_base .. seed_base + n_train - 1")
     ap.add_argument("--init", default=None,
                     help="continue from these weights (npz) instead of a fresh network")
+    ap.add_argument("--multigrid", action="store_true",
+                    help="solve the training problems by batched multigrid")
     ap.add_argument("--out", default=None)
     ap.add_argument("--summary", default=None)
     args = ap.parse_args(argv)
@@ -55,7 +57,7 @@ def main(argv=None):
     chunk = 64
     ts = Wm.TrainingSet()
     for c0 in range(0, len(probs), chunk):
-        part = Wm.solve_training_set(probs[c0:c0 + chunk], log=log)
+        part = Wm.solve_training_set(probs[c0:c0 + chunk], log=log, multigrid=args.multigrid)
         for f in ("x", "mu", "lam", "valid", "iters"):
             getattr(ts, f).extend(getattr(part, f))
     log(f"[warm] training set: {len(ts)} solutions, iterations median {int(np.median(ts.iters))}")
