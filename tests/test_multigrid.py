@@ -223,3 +223,17 @@ def test_multigrid_batch_solve_reaches_the_tolerance(oracle_mod):
         q = [I.small_lattice(40, 40, 2, seed=1, dtype="f32"), I.small_lattice(40, 40, 2, seed=2, dtype="f32")]
         q[1].damping = 0.7
         MG.multigrid_batch_solve(q)
+    # the batch transfer entry points reject bad indices and sizes
+    pred = torch.zeros((96, 128, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(G.GabpError):
+        G._bcheck(G._lib.gabp_batch_warm_init(b.handle, 7, G._ptr(pred), 0), b)
+    with pytest.raises(G.GabpError):
+        G._bcheck(G._lib.gabp_batch_warm_init(b.handle, 0, None, 0), b)
+    with pytest.raises(G.GabpError):       # instance 0 is 128 x 96: its fine level would be 256 x 192
+        G.gabp_batch_upscale_precisions(b, 0, pred, 2.0)
+    fine = torch.zeros((192, 256, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(G.GabpError):
+        G.gabp_batch_upscale_precisions(b, 0, fine, 0.0)
+    G.gabp_batch_upscale_precisions(b, 0, fine, 4.0)
+    torch.cuda.synchronize()
+    assert torch.isfinite(fine[:, :, 1:13]).any()
