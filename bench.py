@@ -46,10 +46,16 @@ def edge_count(nx, ny, alpha, bcx, bcy):
 
 
 def kernel_source_digest():
+    """Digest of the iteration kernels' source with // comments, trailing
+    blanks and empty lines removed (a comment edit leaves it unchanged; the
+    files hold no block comments and no // inside literals)."""
     h = hashlib.sha256()
     for f in ("iter.hip", "iter_node.h", "pair_tile.h", "numerics.h", "lattice.h"):
-        with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -26,9 +26,12 @@ namespace gabp {
 
 enum { BC_NEUMANN = 0, BC_PERIODIC = 1, BC_DIRICHLET = 2 };
 
-// Stencil directions: plane d at (x, y) holds the message INTO (x, y) FROM
-// (x + DX[d], y + DY[d]); the opposite direction is d ^ 1.  Directions 0..3
-// are the 5-point stencil, 4..11 complete the 13-point stencil.
+// Stencil directions d with offsets off_d = (dir_dx(d), dir_dy(d)); the
+// opposite direction is d ^ 1.  Directions 0..3 are the 5-point stencil,
+// 4..11 complete the 13-point stencil.  The message planes are
+// sender-indexed: plane d at (x, y) holds the message FROM (x, y) TO
+// (x, y) + off_d.  (The C ABI's checkpoint layout is receiver-indexed: slot d
+// of (x, y) is the message INTO (x, y) FROM (x, y) + off_d.)
 __host__ __device__ constexpr int dir_dx(int d) {
     return d == 0 ? 1 : d == 1 ? -1 : d == 4 ? 2 : d == 5 ? -2 :
            d == 8 ? 1 : d == 9 ? -1 : d == 10 ? 1 : d == 11 ? -1 : 0;
