@@ -51,3 +51,17 @@ def test_spectral_field_unit_variance_and_seeded():
     f2 = I.spectral_field(64, 48, 0.1, 2, np.random.default_rng(3))
     assert f1.shape == (48, 64) and np.array_equal(f1, f2)
     assert abs(f1.std() - 1.0) < 1e-12 and abs(f1.mean()) < 1e-12
+
+
+def test_batch256_instance_is_the_batch_member():
+    """One instance generated alone equals the same member of the batch
+    (same seed stream), and instance 168 is the 277^2 13-point problem the
+    freeze-tolerance tests use."""
+    batch = I.batch256(count=3)
+    for i in range(3):
+        a, b = batch[i], I.batch256_instance(i)
+        assert (a.nx, a.ny, a.alpha, a.kappa, a.sigma) == (b.nx, b.ny, b.alpha, b.kappa, b.sigma)
+        np.testing.assert_array_equal(a.cells, b.cells)
+        np.testing.assert_array_equal(a.y, b.y)
+    p = I.batch256_instance(168)
+    assert (p.nx, p.ny, p.alpha) == (277, 277, 2)
