@@ -385,7 +385,8 @@ gabp_status gabp_batch_upscale_precisions(gabp_batch *b, int32_t i, float *pred,
                                           int64_t nyf, double scale);
 
 /* The batch's freeze tolerance, as gabp_set_freeze_tolerance's, for every
- * instance (default max_slots = 0: bitwise test). */
+ * instance (default max_slots = 0: bitwise test); INVALID for the same
+ * arguments.  Applies from the next check of gabp_batch_solve. */
 gabp_status gabp_batch_set_freeze_tolerance(gabp_batch *b, int64_t max_slots, double max_rel);
 
 /* Iterations applied to instance i, the iteration its precision messages
