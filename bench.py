@@ -315,7 +315,7 @@ def main(argv=None):
         print(kernel_source_digest())
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the lattice would shard into row strips with a halo exchange; not built).",
               file=sys.stderr)
         return 2
