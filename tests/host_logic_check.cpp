@@ -1,0 +1,75 @@
+// Host-side checks of the library's host logic, compiled and run by
+// tests/test_host_logic.py: the precision-freeze decision
+// (gabp::host::freeze_now) and the device workspace layout
+// (gabp::host::make_layout).  Exit status 0 and "ok" when every case holds.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "host_common.h"
+
+using gabp::host::freeze_now;
+using gabp::host::Layout;
+using gabp::host::make_layout;
+
+static uint32_t bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, sizeof u);
+    return u;
+}
+
+#define CHECK(cond)                                             \
+    do {                                                        \
+        if (!(cond)) {                                          \
+            std::printf("failed: %s (line %d)\n", #cond, __LINE__); \
+            return 1;                                           \
+        }                                                       \
+    } while (0)
+
+int main() {
+    // a bitwise stationary iteration freezes under any tolerance
+    CHECK(freeze_now(0, 0, 0, 0.0));
+    CHECK(freeze_now(0, bits(INFINITY), 64, 1e-6));
+    // max_slots = 0: only a bitwise stationary iteration freezes
+    CHECK(!freeze_now(1, 0, 0, 1.0));
+    CHECK(!freeze_now(1, bits(0.0f), 0, 1.0));
+    // within the tolerance
+    CHECK(freeze_now(64, bits(1e-7f), 64, 1e-6));
+    CHECK(freeze_now(1, bits(1e-6f), 64, 1e-6));   // float(1e-6) <= 1e-6
+    // too many messages changed, or one by too much
+    CHECK(!freeze_now(65, bits(1e-7f), 64, 1e-6));
+    CHECK(!freeze_now(10, bits(2e-6f), 64, 1e-6));
+    // a non-finite change never freezes
+    CHECK(!freeze_now(1, bits(INFINITY), 64, 1e30));
+    CHECK(!freeze_now(1, bits(NAN), 64, 1e30));
+    // counts beyond 32 bits are compared as they are
+    CHECK(!freeze_now((uint64_t)1 << 33, bits(1e-9f), 64, 1e-6));
+    CHECK(!freeze_now(((uint64_t)1 << 32) + 1, bits(1e-9f), 64, 1e-6));
+    // workspace layout: rows and planes 256-byte aligned, each message plane
+    // one 256-byte skew longer than the node area, regions in order and
+    // disjoint, for both precisions, both stencils and ragged sizes
+    const int64_t sizes[][2] = {{8192, 4096}, {1, 1}, {5, 7}, {65, 3}, {1000, 999}, {32768, 64}};
+    for (const auto &sz : sizes) {
+        for (int deg : {4, 12}) {
+            for (int f32 = 0; f32 < 2; ++f32) {
+                const size_t es = f32 ? 4 : 8;
+                const Layout l = make_layout(sz[0], sz[1], deg, es, f32 != 0);
+                CHECK(l.pitch >= sz[0] && (l.pitch * es) % 256 == 0 && (l.pitch - sz[0]) * es < 256);
+                const size_t node = (size_t)l.pitch * (size_t)sz[1];
+                CHECK((size_t)l.plane >= node + 256 / es && ((size_t)l.plane * es) % 256 == 0);
+                const size_t regions[] = {l.msg[0], l.msg[1], l.gain, l.adiag64, l.b64, l.mu64,
+                                          l.bel64, l.partials, l.red, l.flags, l.total};
+                for (size_t r : regions) CHECK(r % 256 == 0);
+                const size_t buf = 2 * (size_t)deg * (size_t)l.plane * es;
+                CHECK(l.msg[0] + buf <= l.msg[1] && l.msg[1] + buf <= l.gain);
+                CHECK(l.gain + (size_t)deg * (size_t)l.plane * es <= l.adiag64);
+                CHECK(l.adiag64 + node * 8 <= l.b64 && l.b64 + node * 8 <= l.mu64);
+                CHECK(l.mu64 + node * 8 <= l.bel64 && l.bel64 + node * 8 <= l.partials);
+                if (f32) CHECK(l.adiag_w >= l.bel64 + node * 8 && l.b_w >= l.adiag_w + node * 4);
+                CHECK(l.flags + 8 * sizeof(uint32_t) <= l.total);
+            }
+        }
+    }
+    std::printf("ok\n");
+    return 0;
+}
