@@ -306,7 +306,19 @@ class OracleGaBP:
         return 5, self.residual()[0]
 
     def abs_change(self, lam_a, th_a, lam_b, th_b) -> float:
+        """Sum over every directed edge of |lam_a - lam_b| + |th_a - th_b|."""
         return float(lib().oracle_abs_change(self.g.nnz, _p(np.ascontiguousarray(lam_a)),
                                              _p(np.ascontiguousarray(th_a)),
                                              _p(np.ascontiguousarray(lam_b)),
                                              _p(np.ascontiguousarray(th_b))))
+
+    def early_stop_statistic(self, prev, m1, m2) -> float:
+        """The paper's early-stopping statistic (Appendix A, Early Stop):
+        mean|m^t - m^{t-1}| / mean|m^2 - m^1| for the current messages m^t,
+        prev = m^{t-1} and m1, m2 the first two iterations, each a pair
+        (lam, th).  Both components of every directed message are pooled in
+        one mean (reading of "mean(abs(...))"); both means run over the same
+        entries, so the ratio is that of the sums."""
+        num = self.abs_change(self.lam, self.th, prev[0], prev[1])
+        den = self.abs_change(m2[0], m2[1], m1[0], m1[1])
+        return num / den

@@ -57,3 +57,19 @@ def test_adam_first_step_moves_by_lr():
     w1, m, v = C.adam(w, g, np.zeros(3), np.zeros(3), 0.01, 0.9, 0.999, 1e-12, 1)
     # bias-corrected first step is lr * sign(g)
     np.testing.assert_allclose(w1, w - 0.01 * np.sign(g), rtol=1e-8)
+
+
+def test_adam_constant_gradient_bias_corrected_steps():
+    """Under a constant gradient g the moments are m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected estimates are exactly g and
+    g^2 at every step and each step moves w by lr * g / (|g| + eps): with a
+    negligible eps, lr * sign(g) at steps 1 to 5 (a wrong power in either
+    correction, or no correction, fails from step 2 on)."""
+    w0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -4.0, 1e-3, -0.02])
+    w, m, v = w0.copy(), np.zeros(4), np.zeros(4)
+    for step in range(1, 6):
+        w, m, v = C.adam(w, g, m, v, 0.01, 0.9, 0.999, 1e-12, step)
+        np.testing.assert_allclose(w, w0 - 0.01 * step * np.sign(g), rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(m, (1 - 0.9 ** step) * g, rtol=1e-12)
+        np.testing.assert_allclose(v, (1 - 0.999 ** step) * g * g, rtol=1e-12)

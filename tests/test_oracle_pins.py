@@ -530,11 +530,76 @@ def test_iterations_compose(oracle_mod):
     assert np.array_equal(a.lam, b.lam) and np.array_equal(a.th, b.th)
 
 
-def test_abs_change_statistic(oracle_mod):
-    pr = I.small_lattice(10, 9, 1, kappa=0.2, frac=0.1, sigma=0.1, seed=8)
-    og = oracle_mod.OracleGaBP.from_problem(pr)
-    og.iterate(1, 0.5)
-    l1, t1 = og.lam.copy(), og.th.copy()
-    og.iterate(1, 0.5)
-    s = og.abs_change(og.lam, og.th, l1, t1)
-    assert s == pytest.approx(np.abs(og.lam - l1).sum() + np.abs(og.th - t1).sum(), rel=1e-12)
+def _run_with_history(og, eta, t):
+    """Messages m^0..m^t of an oracle run, one iteration at a time."""
+    hist = [(og.lam.copy(), og.th.copy())]
+    for _ in range(t):
+        og.iterate(1, eta)
+        hist.append((og.lam.copy(), og.th.copy()))
+    return hist
+
+
+@pytest.mark.parametrize("eta", [0.3, 0.5, 0.8])
+def test_early_stop_statistic_two_node_closed_form(oracle_mod, eta):
+    """Two nodes, c = 1.  The cavity of edge i -> j excludes the only incoming
+    message, so it is the constant (A_ii, b_i); the target message m~ is then
+    constant and m^t = (1 - (1 - eta)^t) m~ from zero messages.  Hence
+    m^t - m^{t-1} = eta (1 - eta)^{t-1} m~ and the paper's statistic
+    mean|m^t - m^{t-1}| / mean|m^2 - m^1| equals (1 - eta)^{t-2} exactly,
+    whatever A and b are."""
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        a1, a2 = rng.uniform(1.0, 3.0, size=2)
+        r = rng.uniform(-0.9, 0.9) * np.sqrt(a1 * a2)
+        b = rng.normal(size=2)
+        og = oracle_mod.OracleGaBP(_graph(oracle_mod, [[a1, r], [r, a2]], b), 1.0)
+        hist = _run_with_history(og, eta, 2)
+        m1, m2 = hist[1], hist[2]
+        prev = m2
+        for t in range(3, 9):
+            og.iterate(1, eta)
+            got = og.early_stop_statistic(prev, m1, m2)
+            assert got == pytest.approx((1.0 - eta) ** (t - 2), rel=1e-12), (t, got)
+            prev = (og.lam.copy(), og.th.copy())
+
+
+def test_early_stop_statistic_three_node_chain_by_hand(oracle_mod):
+    """Chain 1 - 2 - 3, A = [[2,-1,0],[-1,2,-1],[0,-1,2]], b = (1, 0, 2),
+    c = 1, eta = 1/2, zero initial messages.  Derived by hand:
+
+    * leaf messages (cavity = (A_ii, b_i), constant): m_{1->2}^t =
+      (1 - 2^-t)(-1/2, 1/2), m_{3->2}^t = (1 - 2^-t)(-1/2, 1);
+    * middle messages: the cavity of 2 -> 1 is (2 + Lam_{3->2}, 0 + th_{3->2})
+      of the previous iteration, target (-1/Lam_c, th_c/Lam_c), damped by 1/2
+      (and 2 -> 3 likewise with 1 -> 2):
+        t = 1: m_{2->1} = m_{2->3} = (-1/4, 0)
+        t = 2: m_{2->1} = (-23/56, 1/7),      m_{2->3} = (-23/56, 1/14)
+        t = 3: m_{2->1} = (-747/1456, 55/182), m_{2->3} = (-747/1456, 55/364)
+    * sum|m^3 - m^2| = 1101/1456 and sum|m^2 - m^1| = 65/56 over the 8
+      entries, so the pooled statistic at t = 3 is 1101/1690.
+
+    The two components move at different rates here (precision part 571/1014,
+    information part 621/858), so averaging per-component ratios (0.643)
+    instead of pooling (0.651) fails this pin."""
+    A = [[2, -1, 0], [-1, 2, -1], [0, -1, 2]]
+    g = _graph(oracle_mod, A, [1, 0, 2])
+    og = oracle_mod.OracleGaBP(g, 1.0)
+    hist = _run_with_history(og, 0.5, 3)
+    # hand-derived messages, keyed by (sender, receiver) in 0-based nodes
+    want = {
+        1: {(0, 1): (-1 / 4, 1 / 4), (2, 1): (-1 / 4, 1 / 2), (1, 0): (-1 / 4, 0.0), (1, 2): (-1 / 4, 0.0)},
+        2: {(0, 1): (-3 / 8, 3 / 8), (2, 1): (-3 / 8, 3 / 4), (1, 0): (-23 / 56, 1 / 7),
+            (1, 2): (-23 / 56, 1 / 14)},
+        3: {(0, 1): (-7 / 16, 7 / 16), (2, 1): (-7 / 16, 7 / 8), (1, 0): (-747 / 1456, 55 / 182),
+            (1, 2): (-747 / 1456, 55 / 364)},
+    }
+    for t, msgs in want.items():
+        lam, th = hist[t]
+        for (snd, rcv), (wl, wt) in msgs.items():
+            # slot e = (i, j) of the oracle holds the message INTO i FROM j
+            e = [k for k in range(g.nnz) if g.rows[k] == rcv and g.col[k] == snd][0]
+            assert lam[e] == pytest.approx(wl, abs=1e-15) and th[e] == pytest.approx(wt, abs=1e-15)
+    got = og.early_stop_statistic(hist[2], hist[1], hist[2])
+    assert got == pytest.approx(1101 / 1690, rel=1e-13)
+    per_comp = 0.5 * (571 / 1014 + 621 / 858)
+    assert abs(got - per_comp) > 5e-3
