@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "edge-message updates/s + HBM GB/s; time to 1e-6 rel. residual, warm vs cold"
 ITERS_PER_STEP = 10
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_iter_global8192_traffic.md")
-PHASE_KERNEL = {"full": "k_iter_direct", "theta": "k_iter_theta", "theta2": "k_iter_theta2"}
+PHASE_KERNEL = {"full": "k_iter_direct", "theta": "k_iter_theta", "theta2": "k_iter_theta2",
+                "theta2w": "k_iter_theta2w"}
 
 
 def edge_count(nx, ny, alpha, bcx, bcy):
@@ -50,7 +51,7 @@ def kernel_source_digest():
     blanks and empty lines removed (a comment edit leaves it unchanged; the
     files hold no block comments and no // inside literals)."""
     h = hashlib.sha256()
-    for f in ("iter.hip", "iter_node.h", "pair_tile.h", "numerics.h", "lattice.h"):
+    for f in ("iter.hip", "iter_node.h", "pair_tile.h", "walk_strip.h", "numerics.h", "lattice.h"):
         with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].rstrip()
@@ -67,12 +68,38 @@ def measured_traffic(phase, rpt, workload="global8192"):
         return None
     text = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
-    shape = f"pair{rpt}" if phase == "theta2" else f"rpt{rpt}"
+    shape = {"theta2": f"pair{rpt}", "theta2w": f"walk{-rpt}"}.get(phase, f"rpt{rpt}")
     key = f"{PHASE_KERNEL[phase]}_{shape}_traffic_bytes_per_launch"
     t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_source_digest():
         return None
     return float(t.group(1))
+
+
+def rel_err(a, b):
+    """||a - b||_2 / ||b||_2 of two device FP64 arrays (a reported figure)."""
+    import torch
+    a = a.reshape(-1).to(torch.float64)
+    b = b.reshape(-1).to(torch.float64)
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def fp64_reference(prob, tol=1e-10):
+    """The posterior mean an FP32 result is compared with: the same problem
+    solved with FP64 messages (the path pinned to the oracle at 1e-12) by
+    multigrid to a 1e-10 relative residual.  Returns (mean on the device,
+    description)."""
+    import dataclasses
+
+    from paper_2404_12968_amd import gabp as G
+    from paper_2404_12968_amd import multigrid as MG
+    p64 = dataclasses.replace(prob, dtype="f64", rel_tol=tol)
+    r = MG.multigrid_solve(p64, keep_context=True, max_iters=2000000)
+    mu = G.gabp_posterior(r["ctx"], want_var=False)[0]
+    G.gabp_destroy(r["ctx"])
+    return mu, {"reference": "FP64 messages, multigrid to the residual below",
+                "rel_residual": r["rel"], "status": G.gabp_status_string(r["status"]),
+                "fine_iterations": r["iterations"], "seconds": r["seconds"]}
 
 
 def cpu_baseline(prob, seconds=10.0):
@@ -105,9 +132,11 @@ def cpu_baseline(prob, seconds=10.0):
                       f"{its} iterations after 2 warm-up, {el:.1f} s"}
 
 
-def bench_warm(I, n):
+def bench_warm(I, n, freeze=None, fp64_ref=True):
     """Time to 1e-6 on held-out 1024^2 warm-start problems, cold vs the trained
-    network's warm start (inference and the fallback probe included)."""
+    network's warm start (inference and the fallback probe included) vs
+    multigrid; each FP32 mean's relative L2 error against the FP64 reference."""
+    from paper_2404_12968_amd import gabp as G
     from paper_2404_12968_amd import multigrid as MG
     from paper_2404_12968_amd import warm as Wm
     path = os.path.join(ROOT, "paper_2404_12968_amd", "weights", "warm1024.npz")
@@ -115,34 +144,51 @@ def bench_warm(I, n):
     rows = []
     for k in range(n):
         p = I.warm1024(instance=300000 + k)
-        c = Wm.cold_solve(p)
-        w = Wm.warm_solve(net, p)
+        c = Wm.cold_solve(p, freeze_tolerance=freeze, keep_mean=fp64_ref)
+        w = Wm.warm_solve(net, p, freeze_tolerance=freeze, keep_mean=fp64_ref)
         rows.append({"instance": 300000 + k, "kappa": round(p.kappa, 4),
                      "cold_iters": c["iterations"], "cold_s": c["seconds"],
-                     "warm_iters": w["iterations"], "warm_s": w["seconds"], "start": w["start"]})
-    for r in rows:
-        m = MG.multigrid_solve(I.warm1024(instance=r["instance"]))
-        r["multigrid_iters"], r["multigrid_s"] = m["iterations"], m["seconds"]
+                     "warm_iters": w["iterations"], "warm_s": w["seconds"], "start": w["start"],
+                     "cold_frozen_at": c["frozen_at"], "warm_frozen_at": w["frozen_at"]})
+        m = MG.multigrid_solve(p, keep_context=fp64_ref, freeze_tolerance=freeze)
+        rows[-1]["multigrid_iters"], rows[-1]["multigrid_s"] = m["iterations"], m["seconds"]
+        if fp64_ref:
+            mm = G.gabp_posterior(m["ctx"], want_var=False)[0]
+            G.gabp_destroy(m["ctx"])
+            ref, info = fp64_reference(p)
+            rows[-1]["error_vs_fp64"] = {"cold": rel_err(c["mean"], ref),
+                                         "warm": rel_err(w["mean"], ref),
+                                         "multigrid": rel_err(mm, ref),
+                                         "reference_rel_residual": info["rel_residual"]}
+            del ref, mm
     cs = sum(r["cold_s"] for r in rows)
     ws = sum(r["warm_s"] for r in rows)
     ms = sum(r["multigrid_s"] for r in rows)
     return {"workload": "warm1024: 1024x1024, alpha=2, kappa ~ U[0.02,0.3], 16 tracks (~6%), "
                         "sigma 0.05, FP32 to 1e-6; held-out seeds",
+            "freeze_tolerance": {"max_slots": freeze[0], "max_rel": freeze[1]} if freeze
+            else "bitwise",
+            "error_vs_fp64_note": "relative L2 of each FP32 mean against the same problem solved "
+                                  "with FP64 messages by multigrid to a 1e-10 residual",
             "cold_seconds": cs, "warm_seconds": ws, "speedup": cs / ws if ws > 0 else None,
             "multigrid_seconds": ms, "multigrid_speedup": cs / ms if ms > 0 else None,
             "instances": rows}
 
 
-def bench_multigrid(G, prob):
+def bench_multigrid(G, prob, ref=None):
     """Time to the problem's tolerance by coarse-to-fine multigrid (all levels
-    and transfers included)."""
+    and transfers included); with ref, the mean's error against it."""
     from paper_2404_12968_amd import multigrid as MG
-    r = MG.multigrid_solve(prob)
-    return {"tol": prob.rel_tol, "status": G.gabp_status_string(r["status"]),
-            "seconds": r["seconds"], "fine_iterations": r["iterations"],
-            "rel_residual": r["rel"],
-            "levels": [{"nx": lv["nx"], "ny": lv["ny"], "iterations": lv["iterations"],
-                        "observations": lv["observations"]} for lv in r["levels"]]}
+    r = MG.multigrid_solve(prob, keep_context=True)
+    out = {"tol": prob.rel_tol, "status": G.gabp_status_string(r["status"]),
+           "seconds": r["seconds"], "fine_iterations": r["iterations"],
+           "rel_residual": r["rel"],
+           "levels": [{"nx": lv["nx"], "ny": lv["ny"], "iterations": lv["iterations"],
+                       "observations": lv["observations"]} for lv in r["levels"]]}
+    if ref is not None:
+        out["error_vs_fp64"] = rel_err(G.gabp_posterior(r["ctx"], want_var=False)[0], ref)
+    G.gabp_destroy(r["ctx"])
+    return out
 
 
 def bench_batch(G, I, torch, dev, args):
@@ -294,6 +340,12 @@ def main(argv=None):
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
     ap.add_argument("--warm-instances", type=int, default=3)
+    ap.add_argument("--warm-freeze-slots", type=int, default=64,
+                    help="warm-start leg: freeze tolerance (messages) of the cold, warm and "
+                         "multigrid solves alike (0: bitwise freeze only)")
+    ap.add_argument("--no-fp64-ref", action="store_true",
+                    help="skip the FP64 reference solves that the FP32 results' errors are "
+                         "measured against")
     ap.add_argument("--freeze-slots", type=int, default=64,
                     help="batch256 and table1: freeze the precision messages when at most this "
                          "many changed in the last iteration (0: only when none did)")
@@ -429,12 +481,13 @@ def main(argv=None):
         ms1 = event_ms(lambda: G.gabp_iterate(ctx, ITERS_PER_STEP, prob.damping), 3) / ITERS_PER_STEP
         kernels["theta"] = {"iter_ms": ms1, "algorithmic_bytes": alg_theta,
                             "gbps": alg_theta / (ms1 * 1e-3) / 1e9, "rows_per_thread": rpt}
-        for p2 in ((4, 8, 16, 32) if prob.dtype == "f32" else (4,)):
+        # tile heights, then the column-strip walker's bands (negative)
+        for p2 in ((4, 8, 16, 32, -2, -4, -8) if prob.dtype == "f32" else (4, -2)):
             G.gabp_set_tile(ctx, rpt, p2)
             m = 10
             ms_call = event_ms(lambda: G.gabp_iterate(ctx, 2 * m + 1, prob.damping), 3)
             ms2 = (ms_call - ms1) / m
-            kernels[f"theta_pair{p2}"] = {
+            kernels[f"theta_pair{p2}" if p2 > 0 else f"theta_walk{-p2}"] = {
                 "launch_ms": ms2, "iters_per_launch": 2, "iter_ms": ms2 / 2,
                 "algorithmic_bytes": alg_theta,
                 "gbps": alg_theta / (ms2 * 1e-3) / 1e9,
@@ -448,14 +501,14 @@ def main(argv=None):
         kernels["full_timed"] = {"iter_ms": iter_ms}
     total_iters = args.steps * ITERS_PER_STEP
     value = E * total_iters / wall
-    if phase == "theta" and pair > 0:
+    if phase == "theta" and pair != 0:
         # two iterations per launch with the intermediate one kept on chip:
         # the launch must read its inputs and write its outputs once, the
         # bytes of one single-iteration pass
-        kname = "k_iter_theta2"
-        launch_ms = kernels[f"theta_pair{pair}"]["launch_ms"]
+        kname = "k_iter_theta2" if pair > 0 else "k_iter_theta2w"
+        launch_ms = kernels[f"theta_pair{pair}" if pair > 0 else f"theta_walk{-pair}"]["launch_ms"]
         alg_launch = alg_theta
-        traffic = measured_traffic("theta2", pair, prob.name)
+        traffic = measured_traffic("theta2" if pair > 0 else "theta2w", pair, prob.name)
     elif phase == "theta":
         kname = "k_iter_theta"
         launch_ms = kernels["theta"]["iter_ms"]
@@ -497,12 +550,17 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "launch_ms": launch_ms, "algorithmic_bytes_per_launch": alg_launch,
-                     "iterations_per_launch": 2 if kname == "k_iter_theta2" else 1,
+                     "iterations_per_launch": 2 if kname.startswith("k_iter_theta2") else 1,
                      "single_pass_equivalent_gbps": (
-                         (2 if kname == "k_iter_theta2" else 1) * alg_launch / (launch_ms * 1e-3)
-                         / 1e9),
+                         (2 if kname.startswith("k_iter_theta2") else 1) * alg_launch
+                         / (launch_ms * 1e-3) / 1e9),
                      "traffic": traffic},
     }
+    del ctx
+    ref = None
+    if not args.no_fp64_ref and (not args.no_solve or not args.no_multigrid):
+        ref, info = fp64_reference(prob)
+        out["fp64_reference"] = info
     if not args.no_solve:
         ctx2 = G.gabp_create_problem(prob, device=dev)
         torch.cuda.synchronize()
@@ -512,14 +570,19 @@ def main(argv=None):
         out["time_to_tol"] = {"tol": prob.rel_tol, "status": G.gabp_status_string(st),
                               "iterations": it, "seconds": time.perf_counter() - t1,
                               "rel_residual": r, "start": "cold"}
+        if ref is not None:
+            out["time_to_tol"]["error_vs_fp64"] = rel_err(
+                G.gabp_posterior(ctx2, want_var=False)[0], ref)
         del ctx2
     if not args.no_multigrid:
-        out["multigrid"] = bench_multigrid(G, prob)
+        out["multigrid"] = bench_multigrid(G, prob, ref)
         if "time_to_tol" in out:
             out["multigrid"]["speedup_vs_cold"] = (out["time_to_tol"]["seconds"] /
                                                    out["multigrid"]["seconds"])
+    del ref
     if not args.no_warm:
-        out["warm_start"] = bench_warm(I, args.warm_instances)
+        wf = (args.warm_freeze_slots, args.freeze_rel) if args.warm_freeze_slots > 0 else None
+        out["warm_start"] = bench_warm(I, args.warm_instances, wf, not args.no_fp64_ref)
     if not args.no_table1:
         t1 = bench_table1(G, I, torch, args)
         out["table1"] = {"seconds": t1["value"], "paper_seconds_rtx3090": t1["value"] / t1["vs_baseline"],

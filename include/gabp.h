@@ -133,8 +133,11 @@ gabp_status gabp_create(const gabp_grid *grid, const gabp_stencil *stencil,
  * m^t = (1 - damping) m^{t-1} + damping * m~ (Section "Update Damping"),
  * damping in (0, 1].  Asynchronous on the context's stream.  n then m
  * iterations give bitwise the same state as n + m.  A divergence is recorded
- * on the device; the state then stays at the diverged iteration and the next
- * synchronising call reports GABP_E_DIVERGED. */
+ * on the device at the first invalid iteration; later launches write nothing,
+ * so the messages kept are those of the launch that produced it (the
+ * iteration itself, or the second iteration of a two-iteration launch; see
+ * gabp_set_tile), and the next synchronising call reports GABP_E_DIVERGED
+ * and names both iterations in gabp_last_error. */
 gabp_status gabp_iterate(gabp_ctx *ctx, int32_t n_iters, double damping);
 
 /* Iterate in chunks until the FP64 relative residual ||A mu - b||_2 / ||b||_2
@@ -224,12 +227,13 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
  * twice over, time them with HIP events on the context's stream, and keep
  * the fastest for this context and for later contexts of the same prior
  * order, dtype and size class in this process.  Once the precision messages
- * have frozen, the two-iteration kernel (tile heights 4, 8, 16 and 32 in
- * FP32, 4 in FP64; see gabp_set_tile) is timed against the best of those,
- * twice over, and kept if faster.  Every shape computes bitwise-identical
- * messages, so these are ordinary iterations: the counter advances by
- * 1 + 8 * trials, plus 8 * trials (FP32) or 2 * trials (FP64) when frozen.  *chosen (may be
- * NULL) receives the rows per thread.  Synchronises. */
+ * have frozen, the two-iteration tile kernel (tile heights 4, 8, 16 and 32
+ * in FP32, 4 in FP64; see gabp_set_tile) is timed against the best of those,
+ * twice over, and the fastest kept (the column-strip walker is not timed).
+ * Every shape computes bitwise-identical messages, so these are ordinary
+ * iterations: the counter advances by 1 + 8 * trials, plus 8 * trials (FP32)
+ * or 2 * trials (FP64) when frozen.  *chosen (may be NULL) receives the rows
+ * per thread.  Synchronises. */
 gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen);
 
 /* Chunk graphs of gabp_solve and gabp_solve_early_stop (Alg. 2, Iterate MP
@@ -245,14 +249,17 @@ gabp_status gabp_set_graph(gabp_ctx *ctx, int32_t enable);
 /* Tile configuration of a context's iteration kernels, a tuning knob that
  * never changes results.  rows_per_thread (1, 2, 4 or 8): rows each thread
  * of a 64-wide, 256-thread tile walks, for the single-iteration kernels.
- * pair_rows (0, 4, or 8, 16 and 32 for FP32 only): once the precision
- * messages have frozen, gabp_iterate runs two information-only iterations
- * per launch on 64 x pair_rows tiles (iteration t+1 of the tile and a halo of
- * the stencil radius kept in LDS, iteration t+2 written out: one HBM pass
- * per two iterations) and the last one or two iterations of each call
- * singly; 0 = always one iteration per launch.  Default: rows 4, pair 8
- * (FP32) or 4 (FP64), or what the autotuner chose for this problem class.
- * INVALID for other values. */
+ * pair_rows: once the precision messages have frozen, gabp_iterate runs
+ * two information-only iterations per launch (one HBM pass per two
+ * iterations) and the last one or two iterations of each call singly.
+ * pair_rows > 0 (4, or 8, 16 and 32 for FP32 only): on independent 64 x
+ * pair_rows tiles (iteration t+1 of the tile and a halo of the stencil
+ * radius kept in LDS, iteration t+2 written out); pair_rows < 0 (-2, or -4
+ * and -8 for FP32 only): persistent workgroups walk 64-column strips
+ * downwards in bands of -pair_rows rows, keeping iteration t+1 of the rows
+ * the next band needs in LDS; 0 = always one iteration per launch.
+ * Default: rows 4, pair 8 (FP32) or 4 (FP64), or what the autotuner chose
+ * for this problem class.  INVALID for other values. */
 gabp_status gabp_set_tile(gabp_ctx *ctx, int32_t rows_per_thread, int32_t pair_rows);
 gabp_status gabp_get_tile(const gabp_ctx *ctx, int32_t *rows_per_thread, int32_t *pair_rows);
 
@@ -296,11 +303,20 @@ gabp_status gabp_upsample_mean(const double *coarse, int64_t nxc, int64_t nyc, i
 gabp_status gabp_upscale_precisions(gabp_ctx *coarse, float *pred, int64_t nxf, int64_t nyf,
                                     double scale);
 
+/* Iteration kernels launched by this context so far (graph replays
+ * included): one-iteration launches of the full update (full) and of the
+ * information-only update once the precision messages froze (theta), and
+ * two-iteration launches on independent tiles (pair_tiles) and by the
+ * column-strip walker (pair_walk); see gabp_set_tile.  Any pointer may be
+ * NULL.  Does not synchronise; counts launches issued, not completed. */
+gabp_status gabp_launch_counts(const gabp_ctx *ctx, int64_t *full, int64_t *theta,
+                               int64_t *pair_tiles, int64_t *pair_walk);
+
 /* Iteration at which the precision messages were found frozen, or -1. */
 gabp_status gabp_precision_frozen(const gabp_ctx *ctx, int64_t *at);
 
-/* Iterations applied so far (synchronises; returns DIVERGED with the
- * diverged iteration if the run diverged). */
+/* Iterations applied so far (synchronises).  After a divergence: returns
+ * DIVERGED and the iteration of the kept messages (see gabp_iterate). */
 gabp_status gabp_iteration_count(gabp_ctx *ctx, int64_t *iters);
 
 /* Number of stencil directions (4 or 12) of a context. */

@@ -187,6 +187,45 @@ def direct_solve(A: sp.spmatrix, b: np.ndarray) -> np.ndarray:
     return spla.splu(sp.csc_matrix(A)).solve(np.asarray(b, dtype=np.float64))
 
 
+def full_coverage_mean(nx: int, ny: int, alpha: int, kappa: float, tau: float, p: float,
+                       yv: np.ndarray, bc_x: int = BC_NEUMANN, bc_y: int = BC_NEUMANN,
+                       hx: float = 1.0, hy: float = 1.0) -> np.ndarray:
+    """Exact posterior mean when every cell is observed once with precision p.
+
+    A = Q + p I and Q = tau (kappa^2 I + G_x/hx^2 + G_y/hy^2)^alpha share the
+    eigenvectors of the 1-D Laplacians G: Fourier modes on a periodic axis
+    (eigenvalues 4 sin^2(pi k / n)) and the DCT-II basis on a zero-flux axis
+    (4 sin^2(pi k / 2n)).  So mu = V [p V^T y / (tau (kappa^2 + lambda)^alpha
+    + p)], one separable transform per axis (FFT or orthonormal DCT-II).
+    Returns mu as [ny, nx]."""
+    import scipy.fft as sfft
+    yv = np.asarray(yv, dtype=np.float64).reshape(ny, nx)
+
+    def fwd(a, axis, bc):
+        if bc == BC_PERIODIC:
+            return np.fft.fft(a, axis=axis)
+        if bc == BC_NEUMANN:
+            return sfft.dct(a, type=2, norm="ortho", axis=axis)
+        raise ValueError("closed form covers periodic and zero-flux axes")
+
+    def inv(a, axis, bc):
+        if bc == BC_PERIODIC:
+            return np.fft.ifft(a, axis=axis)
+        return sfft.idct(a, type=2, norm="ortho", axis=axis)
+
+    def eig(n, bc, h):
+        k = np.arange(n)
+        arg = np.pi * k / n if bc == BC_PERIODIC else np.pi * k / (2 * n)
+        return 4.0 * np.sin(arg) ** 2 / (h * h)
+
+    lam = eig(nx, bc_x, hx)[None, :] + eig(ny, bc_y, hy)[:, None]
+    yh = fwd(fwd(yv.astype(np.complex128) if BC_PERIODIC in (bc_x, bc_y) else yv, 1, bc_x),
+             0, bc_y)
+    mh = p * yh / (tau * (kappa * kappa + lam) ** alpha + p)
+    mu = inv(inv(mh, 0, bc_y), 1, bc_x)
+    return np.real(mu)
+
+
 # --------------------------------------------------------------------------
 # factor graph and message passing
 # --------------------------------------------------------------------------

@@ -296,6 +296,22 @@ struct InstHost {
     double prev_rel = -1.0;     // residual and iteration count at the check before
     int64_t prev_iters = 0;
     bool prev_valid = false;
+    int64_t diverged_at = 0;    // first invalid iteration (0: none)
+    int dbuf = -1;              // after a divergence: the buffer holding the kept state
+};
+
+// Buffer holding an instance's current messages: its iteration's parity,
+// except after a divergence inside a two-iteration launch.
+int state_buf(const InstHost &H) { return H.dbuf >= 0 ? H.dbuf : (int)(H.iters & 1); }
+
+// One run of iterations since the last check read-back: its length, the
+// couples of two-iteration launches it made, and each instance's iteration
+// and frozen flag at its start (-1: not running).
+struct BatchRun {
+    int k = 0;
+    int couples = 0;
+    std::vector<int64_t> t0;
+    std::vector<char> frozen;
 };
 
 struct BatchHostMirror;
@@ -343,6 +359,7 @@ struct gabp_batch {
     // captured chunk
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    std::vector<BatchRun> runs;   // runs since the last check read-back
     int graph_k = 0, graph_rpt = 0;
     double graph_eta = 0.0;
     std::string err;
@@ -520,9 +537,27 @@ gabp_status launch_pair(gabp_batch *b, int s0, int second, double eta) {
 // remain, the others single iterations alongside; the last 1 to 4
 // iterations run singly for everyone, so that every instance ends on its
 // two newest iterations in its two buffers.
+int couples_of(const gabp_batch *b, int k) {
+    return (b->pair > 0 && b->nf[0] + b->nf[1] > 0 && k >= 5) ? (k - 1) / 4 : 0;
+}
+
+// Record a run of k iterations about to be applied to the running set.
+void record_run(gabp_batch *b, int k) {
+    BatchRun r;
+    r.k = k;
+    r.couples = couples_of(b, k);
+    r.t0.resize(b->n);
+    r.frozen.resize(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        r.t0[i] = b->h[i].running ? b->h[i].iters : -1;
+        r.frozen[i] = b->h[i].frozen ? 1 : 0;
+    }
+    b->runs.push_back(std::move(r));
+}
+
 gabp_status launch_iters(gabp_batch *b, int k, double eta) {
     if (b->nact == 0) return GABP_OK;
-    const int couples = (b->pair > 0 && b->nf[0] + b->nf[1] > 0 && k >= 5) ? (k - 1) / 4 : 0;
+    const int couples = couples_of(b, k);
     gabp_status st = GABP_OK;
     int s = 1;
     for (int c = 0; c < couples && st == GABP_OK; ++c, s += 4) {
@@ -889,6 +924,7 @@ gabp_status gabp_batch_iterate(gabp_batch *b, int32_t n_iters, double damping) {
         gabp_status st = upload_lists(b);
         if (st != GABP_OK) return st;
     }
+    if (b->nact > 0 && n_iters > 0) record_run(b, n_iters);
     gabp_status st = launch_iters(b, n_iters, damping);
     if (st != GABP_OK) return st;
     b->t += n_iters;
@@ -908,9 +944,20 @@ static bool fold_check(gabp_batch *b, double rel_tol, bool probed) {
         InstHost &H = b->h[i];
         if (!H.running) continue;
         if (b->p_div[i] != 0u) {
+            const int64_t t = (int64_t)b->p_div[i];
             H.running = false;
             H.status = GABP_E_DIVERGED;
-            H.iters = (int64_t)b->p_div[i];
+            H.diverged_at = t;
+            H.iters = t;
+            H.dbuf = (int)(t & 1);
+            // the kept messages are those of the launch that diverged
+            for (const BatchRun &r : b->runs) {
+                if (r.t0[i] < 0 || t <= r.t0[i] || t > r.t0[i] + r.k) continue;
+                const HeldState hs = held_after_batch_run(r.t0[i], r.frozen[i] != 0, r.couples, t);
+                H.iters = hs.iter;
+                H.dbuf = hs.buf;
+                break;
+            }
             changed = true;
             continue;
         }
@@ -981,6 +1028,7 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
         }
         gabp_status st = ensure_graph(b, k, damping);
         if (st != GABP_OK) return st;
+        record_run(b, k);
         BHIP(b, hipGraphLaunch(b->gexec, b->stream));
         b->t += k;
         for (auto &H : b->h)
@@ -996,6 +1044,7 @@ gabp_status gabp_batch_solve(gabp_batch *b, int64_t max_iters, double damping, d
         }
         BHIP(b, hipStreamSynchronize(b->stream));
         const bool changed = fold_check(b, rel_tol, need_probe);
+        b->runs.clear();
         if (need_probe) {
             BHIP(b, hipMemsetAsync(b->d_cnt, 0, sizeof(unsigned long long) * (size_t)b->n, b->stream));
             BHIP(b, hipMemsetAsync(b->d_mrel, 0, sizeof(uint32_t) * (size_t)b->n, b->stream));
@@ -1059,7 +1108,7 @@ gabp_status gabp_batch_posterior(gabp_batch *b, int32_t i, double *mean, double 
     if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
     const InstHost &H = b->h[i];
     char *base = b->ws + H.base;
-    BHIP(b, gabp::launch_post(b->dtype == GABP_F32 ? 0 : 1, H.L, base + H.lay.msg[H.iters & 1],
+    BHIP(b, gabp::launch_post(b->dtype == GABP_F32 ? 0 : 1, H.L, base + H.lay.msg[state_buf(H)],
                               (const double *)(base + H.lay.adiag64), (const double *)(base + H.lay.b64),
                               H.frozen ? (const double *)(base + H.lay.bel64) : nullptr, nullptr, mean,
                               var, nullptr, b->stream));
@@ -1072,7 +1121,7 @@ gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *
     if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
     const InstHost &H = b->h[i];
     char *base = b->ws + H.base;
-    BHIP(b, gabp::launch_msgs_get(b->dtype == GABP_F32 ? 0 : 1, H.L, base + H.lay.msg[H.iters & 1],
+    BHIP(b, gabp::launch_msgs_get(b->dtype == GABP_F32 ? 0 : 1, H.L, base + H.lay.msg[state_buf(H)],
                                   prec, info, b->stream));
     return GABP_OK;
 }
@@ -1087,7 +1136,7 @@ gabp_status gabp_batch_warm_init(gabp_batch *b, int32_t i, const float *pred,
     if (H.status == GABP_E_DIVERGED) return bfail(b, GABP_E_DIVERGED, "instance has diverged");
     char *base = b->ws + H.base;
     BHIP(b, gabp::launch_warm_init(b->dtype == GABP_F32 ? 0 : 1, H.L, pred, keep_precisions ? 1 : 0,
-                                   base + H.lay.msg[H.iters & 1], b->stream));
+                                   base + H.lay.msg[state_buf(H)], b->stream));
     H.prev_valid = false;
     if (H.frozen) b->lists_dirty = true;
     H.frozen = false;
@@ -1109,7 +1158,7 @@ gabp_status gabp_batch_upscale_precisions(gabp_batch *b, int32_t i, float *pred,
     if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
     char *base = b->ws + H.base;
     BHIP(b, gabp::launch_upscale_prec(b->dtype == GABP_F32 ? 0 : 1, H.L,
-                                      base + H.lay.msg[H.iters & 1], (float)scale, pred, (int)nxf,
+                                      base + H.lay.msg[state_buf(H)], (float)scale, pred, (int)nxf,
                                       (int)nyf, b->stream));
     return GABP_OK;
 }

@@ -86,7 +86,11 @@ struct gabp_ctx {
         bool last_single;
     };
     std::vector<Chunk> chunks;
+    // launches issued so far: one-iteration full and information-only
+    // kernels, two-iteration tile and walker kernels (graph replays included)
+    int64_t launches[4] = {0, 0, 0, 0};
     int64_t iter = 0;
+    int64_t diverged_at = 0;       // first invalid iteration (0: none)
     bool diverged = false;
     bool prev_valid = false;       // the other buffer holds m^{iter-1}
     bool have_ref = false;         // sum |m^2 - m^1| recorded in red[4]
@@ -133,23 +137,26 @@ gabp_status sync_flags(gabp_ctx *ctx, bool with_red) {
     const uint32_t t = ctx->host->flags[0];
     if (t != 0u && !ctx->diverged) {
         ctx->diverged = true;
+        ctx->diverged_at = (int64_t)t;
         ctx->iter = (int64_t)t;
-        // later launches returned without writing: the messages of the
-        // diverged iteration are in the buffer its own launch wrote
+        // later launches returned without writing: the messages kept are
+        // those of the launch that diverged (for a two-iteration launch, its
+        // second iteration), in the buffer it wrote
         for (const auto &r : ctx->runs) {
             const int64_t rel = (int64_t)t - r.start;
             if (rel < 1 || rel > 2 * (int64_t)r.pairs + r.singles) continue;
-            const int64_t k = rel <= 2 * (int64_t)r.pairs ? (rel + 1) / 2
-                                                          : r.pairs + (rel - 2 * (int64_t)r.pairs);
-            ctx->cur = r.buf ^ (int)(k & 1);
+            const HeldState h = held_after_run(r.start, r.buf, r.pairs, (int64_t)t);
+            ctx->iter = h.iter;
+            ctx->cur = h.buf;
             break;
         }
     }
     ctx->runs.clear();
     if (ctx->diverged)
         return fail(ctx, GABP_E_DIVERGED,
-                    fmt("diverged at iteration %.0f (non-positive cavity precision or non-finite message)",
-                        (double)ctx->iter));
+                    fmt("diverged at iteration %.0f (non-positive cavity precision or non-finite "
+                        "message); messages kept at iteration %.0f",
+                        (double)ctx->diverged_at, (double)ctx->iter));
     return GABP_OK;
 }
 
@@ -165,7 +172,10 @@ void drop_chunks(gabp_ctx *ctx) {
 std::mutex g_tune_mu;
 std::map<long long, std::pair<int, int>> g_tune;
 
+// pair > 0: tile height of the two-iteration tile kernel; pair < 0: the
+// column-strip walker with -pair rows per band; 0: one iteration per launch.
 bool pair_ok(int dtype, int pair) {
+    if (pair < 0) return pair == -2 || ((pair == -4 || pair == -8) && dtype == GABP_F32);
     return pair == 0 || pair == 4 || ((pair == 8 || pair == 16 || pair == 32) && dtype == GABP_F32);
 }
 
@@ -412,10 +422,15 @@ gabp_status enqueue_iters(gabp_ctx *ctx, int32_t n, double damping, hipStream_t 
     while (k < n) {
         const void *src = ctx->msg[cur];
         void *dst = ctx->msg[cur ^ 1];
-        if (ctx->frozen && ctx->pair > 0 && it >= 2 && n - k >= min_left) {
-            GABP_HIP(ctx, gabp::launch_iter_theta2(dt, ctx->pair, ctx->L, src, dst, ctx->gain,
-                                                   ctx->b_w, damping, ctx->flags, ctx->flags + 3,
-                                                   (uint32_t)(it - tbase), s));
+        if (ctx->frozen && ctx->pair != 0 && it >= 2 && n - k >= min_left) {
+            if (ctx->pair < 0)
+                GABP_HIP(ctx, gabp::launch_iter_theta2w(dt, -ctx->pair, ctx->L, src, dst,
+                                                        ctx->gain, ctx->b_w, damping, ctx->flags,
+                                                        ctx->flags + 3, (uint32_t)(it - tbase), s));
+            else
+                GABP_HIP(ctx, gabp::launch_iter_theta2(dt, ctx->pair, ctx->L, src, dst, ctx->gain,
+                                                       ctx->b_w, damping, ctx->flags, ctx->flags + 3,
+                                                       (uint32_t)(it - tbase), s));
             it += 2;
             k += 2;
             ++pairs;
@@ -459,6 +474,8 @@ int64_t quantize_chunk(int64_t next, int64_t kmin) {
 // buffer).
 void advance_state(gabp_ctx *ctx, int32_t n, int pairs, int singles, bool last_single, bool ref) {
     ctx->runs.push_back({ctx->iter, ctx->cur, pairs, singles});
+    ctx->launches[ctx->frozen ? 1 : 0] += singles;
+    ctx->launches[ctx->pair > 0 ? 2 : 3] += pairs;
     ctx->iter += n;
     ctx->cur ^= (pairs + singles) & 1;
     if (ref) ctx->have_ref = true;
@@ -828,7 +845,9 @@ gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t
             }
         }
     if (ctx->frozen) {
-        // the two-iteration kernel against the best single-iteration shape
+        // the two-iteration tile kernel against the best single-iteration
+        // shape (the column-strip walker is selectable with gabp_set_tile but
+        // not timed here: it measured slower on every lattice tried)
         for (int pass = 0; pass < 2; ++pass)
             for (int pair : gabp::kPairChoicesF32) {
                 if (!pair_ok(ctx->dtype, pair)) continue;
@@ -859,7 +878,8 @@ gabp_status gabp_set_tile(gabp_ctx *ctx, int32_t rows_per_thread, int32_t pair_r
     for (int r : gabp::kRptChoices) rpt_ok |= r == rows_per_thread;
     if (!rpt_ok) return fail(ctx, GABP_E_INVALID, "rows_per_thread must be 1, 2, 4 or 8");
     if (!pair_ok(ctx->dtype, pair_rows))
-        return fail(ctx, GABP_E_INVALID, "pair_rows must be 0, 4 or (FP32 only) 8, 16 or 32");
+        return fail(ctx, GABP_E_INVALID,
+                    "pair_rows must be 0, 4, -2 or (FP32 only) 8, 16, 32, -4 or -8");
     ctx->rpt = rows_per_thread;
     ctx->pair = pair_rows;
     return GABP_OK;
@@ -879,6 +899,16 @@ gabp_status gabp_set_freeze_tolerance(gabp_ctx *ctx, int64_t max_slots, double m
         return fail(ctx, GABP_E_INVALID, "need max_slots >= 0 and a finite max_rel >= 0");
     ctx->freeze_slots = max_slots;
     ctx->freeze_rel = max_rel;
+    return GABP_OK;
+}
+
+gabp_status gabp_launch_counts(const gabp_ctx *ctx, int64_t *full, int64_t *theta,
+                               int64_t *pair_tiles, int64_t *pair_walk) {
+    if (!ctx) return GABP_E_INVALID;
+    if (full) *full = ctx->launches[0];
+    if (theta) *theta = ctx->launches[1];
+    if (pair_tiles) *pair_tiles = ctx->launches[2];
+    if (pair_walk) *pair_walk = ctx->launches[3];
     return GABP_OK;
 }
 

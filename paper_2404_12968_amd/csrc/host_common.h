@@ -48,6 +48,44 @@ inline bool freeze_now(uint64_t changed, uint32_t maxrel_bits, int64_t max_slots
     return std::isfinite(rel) && (double)rel <= max_rel;
 }
 
+// State kept after a divergence.  Kernels record the first invalid iteration
+// t and every later launch returns without writing, so the messages kept are
+// those written by the launch that produced t: its last iteration, in the
+// buffer it wrote.  HeldState says which (iteration, buffer) that is.
+struct HeldState {
+    int64_t iter;
+    int buf;
+};
+
+// Single-lattice runs: from iteration `start` in buffer `buf0`, `pairs`
+// two-iteration launches then single ones, each launch writing the other
+// buffer.  t in (start, start + 2 pairs + singles].
+inline HeldState held_after_run(int64_t start, int buf0, int64_t pairs, int64_t t) {
+    const int64_t rel = t - start;
+    if (rel <= 2 * pairs) {
+        const int64_t k = (rel + 1) / 2;      // 1-based index of the pair launch
+        return {start + 2 * k, buf0 ^ (int)(k & 1)};
+    }
+    const int64_t k = pairs + (rel - 2 * pairs);
+    return {t, buf0 ^ (int)(k & 1)};
+}
+
+// Batched runs: an instance at iteration t0 (its state in buffer t0 & 1)
+// runs `couples` couples of two-iteration launches if it is frozen (the
+// first reads buffer t0' & 1 and writes the other, the second writes back;
+// t0' the couple's start), then single iterations, each writing buffer
+// t & 1.  Instances not frozen run single iterations throughout.
+inline HeldState held_after_batch_run(int64_t t0, bool frozen, int64_t couples, int64_t t) {
+    const int64_t rel = t - t0;
+    if (frozen && rel >= 1 && rel <= 4 * couples) {
+        const int64_t cc = (rel - 1) / 4, q = (rel - 1) % 4;
+        const int64_t start = t0 + 4 * cc;
+        if (q < 2) return {start + 2, (int)((start & 1) ^ 1)};
+        return {start + 4, (int)(start & 1)};
+    }
+    return {t, (int)(t & 1)};
+}
+
 inline Layout make_layout(int64_t nx, int64_t ny, int deg, size_t esize, bool f32) {
     Layout l;
     const size_t row_elems = kAlign / esize;

@@ -31,6 +31,13 @@ constexpr int kPairChoicesF32[] = {4, 8, 16, 32};
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
                               const void *gain, const void *bw, double eta, uint32_t *flag,
                               const uint32_t *t_base, uint32_t t_off, hipStream_t s);
+// The same two iterations by the column-strip walker: persistent workgroups
+// of rb waves march down 64-column strips in bands of rb rows (rb = 2, 4 or
+// 8 for FP32, 2 for FP64).  Bitwise equal to two launch_iter_theta calls.
+hipError_t launch_iter_theta2w(int dtype, int rb, const Lattice &L, const void *m_in,
+                               void *m_out, const void *gain, const void *bw, double eta,
+                               uint32_t *flag, const uint32_t *t_base, uint32_t t_off,
+                               hipStream_t s);
 // Device counter helpers for captured chunks (kernels, not memsets, so that
 // they may sit in a graph): *p = v, and *p += k.
 hipError_t launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s);

@@ -12,6 +12,8 @@
 // (flooding schedule: every new message depends only on the previous
 // iteration's messages).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -20,6 +22,7 @@
 #include "numerics.h"
 #include "iter_node.h"
 #include "pair_tile.h"
+#include "walk_strip.h"
 
 // Rounding is spelled out: no implicit multiply-add contraction in this file,
 // explicit fused multiply-adds where wanted.  The full iteration and the
@@ -157,6 +160,33 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 
+// Column-strip walker (walk_strip.h): one workgroup per (strip, segment)
+// pair, segment-major so that each XCD's contiguous range of workgroups
+// covers neighbouring strips of the same rows (their overlap columns then
+// meet in one L2).
+template <typename T, int ALPHA, int RB>
+__global__ __launch_bounds__(64 * RB) void k_iter_theta2w(Lattice L, const T *__restrict__ m_in,
+                                                          T *__restrict__ m_out,
+                                                          const T *__restrict__ gain,
+                                                          const T *__restrict__ bw, T eta,
+                                                          uint32_t *__restrict__ diverged_at,
+                                                          const uint32_t *__restrict__ t_base,
+                                                          uint32_t t_off, int seglen) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    constexpr int R = ALPHA == 1 ? 1 : 2;
+    __shared__ T lds[WalkRing<RB>::kRows * DEG * (64 + 2 * R)];
+    if (*diverged_at != 0u) return;               // uniform across the workgroup
+    const uint32_t t = *t_base + t_off;           // the iteration the launch starts from
+    const int g = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int seg = g / L.tiles_x, strip = g - seg * L.tiles_x;
+    const int Y0 = seg * seglen;
+    if (Y0 >= L.ny) return;
+    const int Y1 = min(L.ny, Y0 + seglen);
+    bool bad1 = false, bad2 = false;
+    walk_strip<T, ALPHA, RB>(L, m_in, m_out, gain, bw, eta, strip * 64, Y0, Y1, lds, bad1, bad2);
+    if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
+}
+
 static inline int tiles_of(const Lattice &L) {
     return L.tiles_x * ((L.ny + 3) / 4);
 }
@@ -262,6 +292,54 @@ hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m
     } else {
         if (L.alpha == 1) launch_theta2_k<double, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
         else launch_theta2_k<double, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+    }
+    return hipGetLastError();
+}
+
+// Segments per strip: enough workgroups to fill every compute unit at the
+// kernel's occupancy (a persistent grid), each segment at least 4 bands.
+template <typename T, int ALPHA, int RB>
+static void launch_walk_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
+                          const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
+                          uint32_t t_off, hipStream_t s) {
+    static int resident = 0;   // workgroups resident on the device at once
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, (const void *)k_iter_theta2w<T, ALPHA, RB>, 64 * RB, 0) == hipSuccess &&
+            cus > 0 && per_cu > 0)
+            resident = cus * per_cu;
+        else
+            resident = 512;
+    }
+    const int max_seg = std::max(1, L.ny / (4 * RB));
+    const int nseg = std::min(max_seg, std::max(1, (resident + L.tiles_x / 2) / L.tiles_x));
+    const int seglen = (L.ny + nseg - 1) / nseg;
+    const int blocks = L.tiles_x * ((L.ny + seglen - 1) / seglen);
+    hipLaunchKernelGGL((k_iter_theta2w<T, ALPHA, RB>), dim3(blocks), dim3(64 * RB), 0, s, L,
+                       (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta, flag,
+                       t_base, t_off, seglen);
+}
+
+hipError_t launch_iter_theta2w(int dtype, int rb, const Lattice &L, const void *m_in,
+                               void *m_out, const void *gain, const void *bw, double eta,
+                               uint32_t *flag, const uint32_t *t_base, uint32_t t_off,
+                               hipStream_t s) {
+    if (dtype == 0) {
+        if (L.alpha == 1) {
+            if (rb == 8) launch_walk_k<float, 1, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (rb == 4) launch_walk_k<float, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else launch_walk_k<float, 1, 2>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+        } else {
+            if (rb == 8) launch_walk_k<float, 2, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (rb == 4) launch_walk_k<float, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else launch_walk_k<float, 2, 2>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+        }
+    } else {
+        if (L.alpha == 1) launch_walk_k<double, 1, 2>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+        else launch_walk_k<double, 2, 2>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
     }
     return hipGetLastError();
 }

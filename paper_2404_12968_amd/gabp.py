@@ -92,6 +92,7 @@ _SIGS = {
                                ctypes.c_int32, _P, _P], ctypes.c_int),
     "gabp_set_graph": ([_P, ctypes.c_int32], ctypes.c_int),
     "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "gabp_launch_counts": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "gabp_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_batch_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_batch_warm_init": ([_P, ctypes.c_int32, _P, ctypes.c_int32], ctypes.c_int),
@@ -580,6 +581,14 @@ def gabp_set_freeze_tolerance(ctx: Context, max_slots: int, max_rel: float) -> N
 def gabp_batch_set_freeze_tolerance(b: Batch, max_slots: int, max_rel: float) -> None:
     """gabp_set_freeze_tolerance for every instance of a batch."""
     _bcheck(_lib.gabp_batch_set_freeze_tolerance(b.handle, int(max_slots), float(max_rel)), b)
+
+
+def gabp_launch_counts(ctx: Context) -> dict:
+    """Iteration-kernel launches issued by a context, by kind."""
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    _check(_lib.gabp_launch_counts(ctx.handle, *[ctypes.byref(x) for x in v]), ctx)
+    return {"full": v[0].value, "theta": v[1].value, "pair_tiles": v[2].value,
+            "pair_walk": v[3].value}
 
 
 def gabp_get_tile(ctx: Context) -> Tuple[int, int]:

@@ -253,18 +253,25 @@ def predict(net: WarmNet, prob: I.Problem, device="cuda") -> torch.Tensor:
 
 
 def warm_solve(net: WarmNet, prob: I.Problem, max_iters: int = 300000, probe: int = 100,
-               device="cuda", use_precisions: bool = True):
+               device="cuda", use_precisions: bool = True,
+               freeze_tolerance: Optional[tuple] = None, keep_mean: bool = False):
     """Solve from the network's warm start; cold start is the fallback: after
     `probe` iterations the warm run's residual is compared with a cold run's
     at the same iteration, and the worse of the two is dropped.  Returns a
     dict with status, iterations, seconds (including inference) and which
-    start won."""
+    start won (keep_mean: and the FP64 posterior mean).  freeze_tolerance =
+    (max_slots, max_rel) is given to both contexts' gabp_set_freeze_tolerance
+    (a warm start's precision messages may settle into last-bit flips that the
+    bitwise freeze never accepts)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pred = predict(net, prob, device)
     warm = G.gabp_create_problem(prob, device=device)
     G.gabp_warm_init(warm, pred, keep_precisions=not use_precisions)
     cold = G.gabp_create_problem(prob, device=device)
+    if freeze_tolerance is not None:
+        G.gabp_set_freeze_tolerance(warm, *freeze_tolerance)
+        G.gabp_set_freeze_tolerance(cold, *freeze_tolerance)
     G.gabp_iterate(cold, probe, prob.damping)
     rc, _ = G.gabp_residual(cold)
     try:
@@ -285,14 +292,27 @@ def warm_solve(net: WarmNet, prob: I.Problem, max_iters: int = 300000, probe: in
     st, it, rel = G.gabp_solve(ctx, max_iters - probe, prob.damping, prob.rel_tol,
                                prob.check_every)
     torch.cuda.synchronize()
-    return {"status": st, "iterations": it, "seconds": time.perf_counter() - t0,
-            "rel": rel, "start": which, "probe_residual_warm": rw, "probe_residual_cold": rc}
+    out = {"status": st, "iterations": it, "seconds": time.perf_counter() - t0,
+           "rel": rel, "start": which, "probe_residual_warm": rw, "probe_residual_cold": rc,
+           "frozen_at": G.gabp_precision_frozen(ctx)}
+    if keep_mean:
+        out["mean"] = G.gabp_posterior(ctx, want_var=False)[0]
+    G.gabp_destroy(ctx)
+    return out
 
 
-def cold_solve(prob: I.Problem, max_iters: int = 300000, device="cuda"):
+def cold_solve(prob: I.Problem, max_iters: int = 300000, device="cuda",
+               freeze_tolerance: Optional[tuple] = None, keep_mean: bool = False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx = G.gabp_create_problem(prob, device=device)
+    if freeze_tolerance is not None:
+        G.gabp_set_freeze_tolerance(ctx, *freeze_tolerance)
     st, it, rel = G.gabp_solve(ctx, max_iters, prob.damping, prob.rel_tol, prob.check_every)
     torch.cuda.synchronize()
-    return {"status": st, "iterations": it, "seconds": time.perf_counter() - t0, "rel": rel}
+    out = {"status": st, "iterations": it, "seconds": time.perf_counter() - t0, "rel": rel,
+           "frozen_at": G.gabp_precision_frozen(ctx)}
+    if keep_mean:
+        out["mean"] = G.gabp_posterior(ctx, want_var=False)[0]
+    G.gabp_destroy(ctx)
+    return out

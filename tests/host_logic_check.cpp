@@ -9,6 +9,9 @@
 #include "host_common.h"
 
 using gabp::host::freeze_now;
+using gabp::host::held_after_batch_run;
+using gabp::host::held_after_run;
+using gabp::host::HeldState;
 using gabp::host::Layout;
 using gabp::host::make_layout;
 
@@ -26,7 +29,41 @@ static uint32_t bits(float f) {
         }                                                       \
     } while (0)
 
+static bool held_is(HeldState h, int64_t iter, int buf) { return h.iter == iter && h.buf == buf; }
+
 int main() {
+    // state kept after a divergence at t.  Single lattice: from iteration 10
+    // in buffer 0, three two-iteration launches (writing buffers 1, 0, 1 with
+    // iterations 12, 14, 16), then single launches (17 -> buffer 0, ...).
+    CHECK(held_is(held_after_run(10, 0, 3, 11), 12, 1));   // first half of launch 1
+    CHECK(held_is(held_after_run(10, 0, 3, 12), 12, 1));
+    CHECK(held_is(held_after_run(10, 0, 3, 13), 14, 0));
+    CHECK(held_is(held_after_run(10, 0, 3, 16), 16, 1));
+    CHECK(held_is(held_after_run(10, 0, 3, 17), 17, 0));   // first single
+    CHECK(held_is(held_after_run(10, 0, 3, 18), 18, 1));
+    CHECK(held_is(held_after_run(10, 1, 0, 11), 11, 0));   // singles only
+    CHECK(held_is(held_after_run(10, 1, 0, 14), 14, 1));
+    // Batch: a frozen instance at iteration 10 runs two couples (launches
+    // write buffers 1, 0 with iterations 12, 14, then 1, 0 with 16, 18), then
+    // singles writing buffer t & 1
+    CHECK(held_is(held_after_batch_run(10, true, 2, 11), 12, 1));
+    CHECK(held_is(held_after_batch_run(10, true, 2, 12), 12, 1));
+    CHECK(held_is(held_after_batch_run(10, true, 2, 13), 14, 0));
+    CHECK(held_is(held_after_batch_run(10, true, 2, 14), 14, 0));
+    CHECK(held_is(held_after_batch_run(10, true, 2, 15), 16, 1));
+    CHECK(held_is(held_after_batch_run(10, true, 2, 18), 18, 0));
+    CHECK(held_is(held_after_batch_run(10, true, 2, 19), 19, 1));
+    CHECK(held_is(held_after_batch_run(11, true, 1, 12), 13, 0));   // odd start
+    CHECK(held_is(held_after_batch_run(11, true, 1, 14), 15, 1));
+    // an instance that is not frozen runs single iterations throughout
+    CHECK(held_is(held_after_batch_run(10, false, 2, 11), 11, 1));
+    CHECK(held_is(held_after_batch_run(10, false, 2, 14), 14, 0));
+    // after every whole couple the kept buffer is the iteration's parity
+    for (int64_t t0 = 0; t0 < 4; ++t0)
+        for (int64_t t = t0 + 1; t <= t0 + 8; ++t) {
+            const HeldState h = held_after_batch_run(t0, true, 2, t);
+            CHECK(h.iter >= t && h.iter - t <= 1 && ((h.iter - t0) % 4 == 0 ? h.buf == (int)(h.iter & 1) : h.buf != (int)(h.iter & 1)));
+        }
     // a bitwise stationary iteration freezes under any tolerance
     CHECK(freeze_now(0, 0, 0, 0.0));
     CHECK(freeze_now(0, bits(INFINITY), 64, 1e-6));

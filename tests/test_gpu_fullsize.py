@@ -1,0 +1,217 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations it
+times, against the FP64 oracle.
+
+* 8192 x 4096 global workload after the precision messages froze (the
+  two-iteration kernels, tile and column-strip walker, do the work): sampled
+  windows against oracle runs on crops that contain each window's dependence
+  cone (a message at iteration t depends only on data within 2t cells).
+* 8192 x 4096 with every cell observed: the mean at a 1e-6 residual against
+  the oracle's closed form (separable FFT / DCT-II solve).
+* The 2048 x 2048 track workload: 1000 FP32 iterations through the solver
+  (freeze, two-iteration launches, chunk graphs) against the oracle on the
+  whole lattice at equal t.
+"""
+import numpy as np
+import pytest
+
+from conftest import plane_slot_map
+from paper_2404_12968_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp
+    return gabp
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def max_rel(a, b):
+    """Largest element-wise difference relative to the reference's largest
+    magnitude (a bound on every element, not an average)."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _crop_problem(prob, x0, y0, w, h):
+    """Sub-problem on columns x0..x0+w-1 (mod nx) and rows y0..y0+h-1 with the
+    observations inside; every crop edge zero-flux (the real boundary of the
+    global grid's y axis; artificial edges lie outside the compared window's
+    dependence cone)."""
+    xs = (np.arange(x0, x0 + w) % prob.nx)
+    cx, cy = prob.cells % prob.nx, prob.cells // prob.nx
+    colpos = np.full(prob.nx, -1)
+    colpos[xs] = np.arange(w)
+    inside = (colpos[cx] >= 0) & (cy >= y0) & (cy < y0 + h)
+    cells = (cy[inside] - y0) * w + colpos[cx[inside]]
+    assert prob.bc_y == I.BC_NEUMANN
+    return I.Problem("crop", w, h, I.BC_NEUMANN, I.BC_NEUMANN,
+                     prob.alpha, prob.kappa, prob.tau, prob.c, prob.sigma, cells, prob.y[inside],
+                     dtype="f64")
+
+
+@pytest.fixture(scope="module")
+def global_prob():
+    return I.global8192()
+
+
+@pytest.mark.parametrize("pair", [-4, 16])
+def test_global8192_after_freeze_matches_oracle_windows(G, oracle_mod, global_prob, pair):
+    """Solver checks every 10 iterations until the precision messages froze
+    (bitwise, near iteration 65), then five two-iteration launches per
+    chunk up to t = 150: means, precision and information messages of four
+    windows (interior, periodic seam, top and bottom rows) equal the FP64
+    oracle's on crops with a 2t + 4 margin, to 1e-5 relative L2, with the
+    largest element-wise difference reported and bounded."""
+    prob = global_prob
+    t = 150
+    ctx = G.gabp_create_problem(prob)
+    G.gabp_set_tile(ctx, 1, pair)
+    st, it, _ = G.gabp_solve(ctx, t, prob.damping, 0.0, 10)
+    assert it == t and st == G.GABP_E_NOT_CONVERGED
+    fz = G.gabp_precision_frozen(ctx)
+    assert 0 < fz < t - 50, fz
+    # every chunk after the freeze ran as five two-iteration launches
+    n2 = G.gabp_launch_counts(ctx)["pair_tiles" if pair > 0 else "pair_walk"]
+    assert n2 == 5 * ((t - fz) // 10), (n2, fz)
+    mean, _ = G.gabp_posterior(ctx, want_var=False)
+    prec, info = G.gabp_get_messages(ctx)
+    torch.cuda.synchronize()
+    m = 2 * t + 4
+    w = 40
+    report = []
+    # the top and bottom windows are centred on an observed cell of their
+    # edge row (far from every observation the messages after t iterations
+    # are below the FP32 range: the oracle's are ~1e-48 two hundred cells away)
+    cx, cy = prob.cells % prob.nx, prob.cells // prob.nx
+    top = cx[cy == 0][np.argmin(np.abs(cx[cy == 0] - 100))]
+    bot = cx[cy == prob.ny - 1][np.argmin(np.abs(cx[cy == prob.ny - 1] - 6000))]
+    for (wx, wy) in ((4000, 2000), (8192 - 20, 1000), (int(top) - w // 2, 0),
+                     (int(bot) - w // 2, 4096 - w)):
+        x0 = wx - m
+        y0 = max(0, wy - m)
+        y1 = min(prob.ny, wy + w + m)
+        sub = _crop_problem(prob, x0, y0, w + 2 * m, y1 - y0)
+        og = oracle_mod.OracleGaBP.from_problem(sub)
+        og.iterate(t, prob.damping)
+        mu_o, _ = og.posterior()
+        mu_o = mu_o.reshape(sub.ny, sub.nx)[wy - y0: wy - y0 + w, m: m + w]
+        cols = np.arange(wx, wx + w) % prob.nx
+        mu_g = mean[wy: wy + w][:, cols].cpu().numpy()
+        sd, sy, sx, e = plane_slot_map(sub, og.g)
+        sel = (sy >= wy - y0) & (sy < wy - y0 + w) & (sx >= m) & (sx < m + w)
+        idx = (sd[sel], sy[sel] - (wy - y0), sx[sel] - m)
+        lam_g = prec[:, wy: wy + w][:, :, cols].cpu().double().numpy()[idx]
+        th_g = info[:, wy: wy + w][:, :, cols].cpu().double().numpy()[idx]
+        errs = {"mu": rel_l2(mu_g, mu_o), "lam": rel_l2(lam_g, og.lam[e[sel]]),
+                "th": rel_l2(th_g, og.th[e[sel]]),
+                "mu_max": max_rel(mu_g, mu_o), "th_max": max_rel(th_g, og.th[e[sel]])}
+        report.append(((wx, wy), errs))
+        for k in ("mu", "lam", "th"):
+            assert errs[k] <= 1e-5, (wx, wy, errs)
+        for k in ("mu_max", "th_max"):
+            assert errs[k] <= 1e-4, (wx, wy, errs)
+    print("frozen at", fz, "pair", pair, report)
+    G.gabp_destroy(ctx)
+
+
+def test_global8192_walker_is_bitwise_identical(G, global_prob):
+    """The walker (4-row bands) on the full lattice equals one iteration per
+    launch bit for bit after the same iterations, and so does the FP64
+    residual."""
+    prob = global_prob
+    a = G.gabp_create_problem(prob)
+    b = G.gabp_create_problem(prob)
+    G.gabp_set_tile(a, 1, -4)
+    G.gabp_set_tile(b, 1, 0)
+    fa = fb = -1
+    for ctx in (a, b):
+        while G.gabp_precision_frozen(ctx) < 0:
+            G.gabp_iterate(ctx, 10, 0.5)
+            G.gabp_residual(ctx)
+            assert G.gabp_iteration_count(ctx)[0] < 5000
+    fa, fb = G.gabp_precision_frozen(a), G.gabp_precision_frozen(b)
+    assert fa == fb > 0
+    w0 = G.gabp_launch_counts(a)["pair_walk"]
+    for n in (21, 2):
+        G.gabp_iterate(a, n, prob.damping)
+        G.gabp_iterate(b, n, prob.damping)
+    assert G.gabp_launch_counts(a)["pair_walk"] == w0 + 10
+    assert G.gabp_iteration_count(a) == G.gabp_iteration_count(b)
+    pa, ia = G.gabp_get_messages(a)
+    pb, ib = G.gabp_get_messages(b)
+    assert torch.equal(pa, pb)
+    del pa, pb
+    assert torch.equal(ia, ib)
+    del ia, ib
+    assert G.gabp_residual(a) == G.gabp_residual(b)
+    G.gabp_destroy(a)
+    G.gabp_destroy(b)
+
+
+def test_global8192_full_coverage_closed_form(G, oracle_mod):
+    """Every cell of the 8192 x 4096 global lattice observed once (periodic
+    x, zero-flux y, 13-point prior, kappa 0.02, sigma 0.05): the FP32 solve to
+    a 1e-6 relative residual (the benchmark's autotuned kernels) gives the
+    closed-form posterior mean (FFT along x, DCT-II along y) to 1e-5."""
+    nx, ny = 8192, 4096
+    rng = np.random.default_rng(3100)
+    yv = rng.normal(size=(ny, nx))
+    sigma = 0.05
+    prob = I.Problem("fullcov8192", nx, ny, I.BC_PERIODIC, I.BC_NEUMANN, 2, 0.02, 1.0,
+                     I.DEFAULT_C[2], sigma, np.arange(nx * ny, dtype=np.int64), yv.ravel(),
+                     dtype="f32")
+    ctx = G.gabp_create_problem(prob)
+    st, it, rel = G.gabp_solve(ctx, 20000, 0.5, 1e-6, 10)
+    assert st == G.GABP_OK, (st, it, rel)
+    mean, _ = G.gabp_posterior(ctx, want_var=False)
+    mu = mean.cpu().numpy()
+    G.gabp_destroy(ctx)
+    exact = oracle_mod.full_coverage_mean(nx, ny, 2, 0.02, 1.0, 1.0 / sigma ** 2, yv,
+                                          I.BC_PERIODIC, I.BC_NEUMANN)
+    e2, emax = rel_l2(mu, exact), max_rel(mu, exact)
+    print("full coverage 8192x4096:", it, "iterations, rel residual", rel, "mean error", e2, emax)
+    assert e2 <= 1e-5 and emax <= 1e-4
+
+
+def test_tracks2048_1000_iterations_match_oracle(G, oracle_mod):
+    """The 2048 x 2048 track workload: 1000 FP32 iterations through
+    gabp_solve (checks every 10, precision freeze, two-iteration launches
+    replayed from chunk graphs) against the FP64 oracle on the whole lattice
+    at equal t: means, variances and both message planes to 1e-5 relative
+    L2, element-wise maximum reported and bounded."""
+    prob = I.tracks2048()
+    ctx = G.gabp_create_problem(prob)
+    st, it, _ = G.gabp_solve(ctx, prob.fixed_iters, prob.damping, 0.0, 10)
+    assert it == prob.fixed_iters and G.gabp_precision_frozen(ctx) > 0
+    mean, var = G.gabp_posterior(ctx)
+    prec, info = G.gabp_get_messages(ctx)
+    torch.cuda.synchronize()
+    mu_g, var_g = mean.cpu().numpy().ravel(), var.cpu().numpy().ravel()
+    prec_g, info_g = prec.cpu().double().numpy(), info.cpu().double().numpy()
+    G.gabp_destroy(ctx)
+    del prec, info, mean, var
+    og = oracle_mod.OracleGaBP.from_problem(prob)
+    og.iterate(prob.fixed_iters, prob.damping)
+    mu_o, var_o = og.posterior()
+    d, y, x, e = plane_slot_map(prob, og.g)
+    errs = {"mu": rel_l2(mu_g, mu_o), "var": rel_l2(var_g, var_o),
+            "lam": rel_l2(prec_g[d, y, x], og.lam[e]), "th": rel_l2(info_g[d, y, x], og.th[e]),
+            "mu_max": max_rel(mu_g, mu_o), "th_max": max_rel(info_g[d, y, x], og.th[e])}
+    print("tracks2048 at t = 1000:", errs)
+    for k in ("mu", "var", "lam", "th"):
+        assert errs[k] <= 1e-5, errs
+    for k in ("mu_max", "th_max"):
+        assert errs[k] <= 1e-4, errs

@@ -355,6 +355,30 @@ def test_full_coverage_neumann_cosine(oracle_mod, alpha):
     np.testing.assert_allclose(mu.reshape(ny, nx), expect, rtol=1e-9, atol=1e-11)
 
 
+@pytest.mark.parametrize("alpha,bcx,bcy,hx,hy", [
+    (1, I.BC_PERIODIC, I.BC_NEUMANN, 1.0, 1.0),
+    (2, I.BC_PERIODIC, I.BC_NEUMANN, 1.0, 1.3),
+    (2, I.BC_NEUMANN, I.BC_PERIODIC, 0.7, 1.0),
+    (2, I.BC_NEUMANN, I.BC_NEUMANN, 1.0, 1.0),
+    (1, I.BC_PERIODIC, I.BC_PERIODIC, 1.1, 0.9),
+])
+def test_full_coverage_closed_form_equals_sparse_solve(oracle_mod, alpha, bcx, bcy, hx, hy):
+    """The oracle's separable-transform closed form (used at sizes no direct
+    solve reaches) equals the sparse LU solve of the assembled system on
+    small grids of every periodic / zero-flux combination and h != 1."""
+    nx, ny, kappa, tau, sigma = 13, 10, 0.3, 1.7, 0.4
+    rng = np.random.default_rng(21)
+    yv = rng.normal(size=(ny, nx))
+    cells = np.arange(nx * ny)
+    prob = I.Problem("fc", nx, ny, bcx, bcy, alpha, kappa, tau, I.DEFAULT_C[alpha], sigma,
+                     cells, yv.ravel(), hx=hx, hy=hy)
+    A, b = oracle_mod.posterior_system(prob)
+    exact = oracle_mod.direct_solve(A, b).reshape(ny, nx)
+    got = oracle_mod.full_coverage_mean(nx, ny, alpha, kappa, tau, 1.0 / sigma ** 2, yv, bcx, bcy,
+                                        hx, hy)
+    np.testing.assert_allclose(got, exact, rtol=1e-11, atol=1e-12)
+
+
 # --------------------------------------------------------------------------
 # precision messages, fixed points, invariants
 # --------------------------------------------------------------------------
