@@ -466,6 +466,18 @@ gabp_status gabp_warm_features(int64_t nobs, const int64_t *cell, const double *
                                int64_t ny, double kappa, float *scratch, void *x_bf16,
                                void *stream);
 
+/* gabp_warm_features without the scratch argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops that
+ * forbid allocation): the two scratch planes live in a static device array
+ * of 2 x 2^21 FP32 values (16 MiB per GPU, held until the process ends), so
+ * nx * ny may be at most 2^21 (INVALID beyond).  The call allocates nothing;
+ * the scratch is cleared by a kernel on every call.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams
+ * or threads without ordering) race.  Same arguments and results otherwise. */
+gabp_status gabp_warm_features_noalloc(int64_t nobs, const int64_t *cell, const double *y,
+                                       int64_t nx, int64_t ny, double kappa, void *x_bf16,
+                                       void *stream);
+
 /* Text of the last error of a network primitive. */
 const char *gabp_net_last_error(void);
 

@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "gabp.h"
@@ -273,6 +274,13 @@ __global__ __launch_bounds__(256) void k_feat_scatter(long n, const int64_t *__r
     atomicAdd(&sum[c], (float)yv[k]);
 }
 
+// p[0 .. n) = 0 (a kernel, not a memset, so that callers may capture it in
+// a graph)
+__global__ __launch_bounds__(256) void k_zero_f32(float *__restrict__ p, long n) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
 __global__ __launch_bounds__(256) void k_feat_build(long N, const float *__restrict__ cnt,
                                                     const float *__restrict__ sum, float kfeat,
                                                     __bf16 *__restrict__ x) {
@@ -345,8 +353,54 @@ hipError_t launch_warm_init(int dtype, const Lattice &L, const float *pred, int 
 // ==========================================================================
 // C ABI of the network primitives
 // ==========================================================================
+// Scratch of gabp_warm_features_noalloc: the two FP32 planes (observation
+// counts and sums) of at most kFeatScratchCells cells, 16 MiB that each GPU
+// the library runs on holds until the process ends.  Host code must not pass
+// this name to a kernel (it is a host-side stand-in): the device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr long kFeatScratchCells = 1L << 21;
+static __device__ __align__(256) float scratch[2 * kFeatScratchCells];
+
 namespace {
 thread_local std::string g_net_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// The current device's address of `scratch`, looked up on the device's first
+// call (with that device current); allocates nothing.
+hipError_t scratch_address(float **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (float *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// Input features from observations with cnt/sum scratch planes of N cells
+// (2 N floats, cleared here by a kernel).
+hipError_t features_into(int64_t nobs, const int64_t *cell, const double *y, long N,
+                         double kappa, float *scr, void *x_bf16, hipStream_t s) {
+    hipLaunchKernelGGL(gabp::k_zero_f32, dim3((unsigned)((2 * N + 255) / 256)), dim3(256), 0, s,
+                       scr, 2 * N);
+    if (nobs > 0)
+        hipLaunchKernelGGL(gabp::k_feat_scatter, dim3((unsigned)((nobs + 255) / 256)), dim3(256), 0, s,
+                           (long)nobs, cell, y, N, scr, scr + N);
+    const float kf = (float)(std::log(kappa) + 2.5);
+    hipLaunchKernelGGL(gabp::k_feat_build, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N,
+                       (const float *)scr, (const float *)(scr + N), kf, (__bf16 *)x_bf16);
+    return hipGetLastError();
+}
 
 gabp_status nfail(gabp_status st, const std::string &m) {
     g_net_error = m;
@@ -488,21 +542,27 @@ gabp_status gabp_warm_loss(const float *pred, const float *mu_t, const float *la
 }
 
 gabp_status gabp_warm_features(int64_t nobs, const int64_t *cell, const double *y, int64_t nx,
-                               int64_t ny, double kappa, float *scratch, void *x_bf16,
+                               int64_t ny, double kappa, float *work, void *x_bf16,
                                void *stream) {
-    if (nx < 1 || ny < 1 || !scratch || !x_bf16 || nobs < 0 || (nobs > 0 && (!cell || !y)) ||
+    if (nx < 1 || ny < 1 || !work || !x_bf16 || nobs < 0 || (nobs > 0 && (!cell || !y)) ||
         !(kappa > 0))
         return nfail(GABP_E_INVALID, "warm_features: bad arguments");
-    hipStream_t s = (hipStream_t)stream;
-    const long N = (long)nx * ny;
-    NHIP(hipMemsetAsync(scratch, 0, sizeof(float) * 2 * (size_t)N, s));
-    if (nobs > 0)
-        hipLaunchKernelGGL(gabp::k_feat_scatter, dim3((unsigned)((nobs + 255) / 256)), dim3(256), 0, s,
-                           (long)nobs, cell, y, N, scratch, scratch + N);
-    const float kf = (float)(std::log(kappa) + 2.5);
-    hipLaunchKernelGGL(gabp::k_feat_build, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N,
-                       (const float *)scratch, (const float *)(scratch + N), kf, (__bf16 *)x_bf16);
-    NHIP(hipGetLastError());
+    NHIP(features_into(nobs, cell, y, (long)nx * ny, kappa, work, x_bf16, (hipStream_t)stream));
+    return GABP_OK;
+}
+
+gabp_status gabp_warm_features_noalloc(int64_t nobs, const int64_t *cell, const double *y,
+                                       int64_t nx, int64_t ny, double kappa, void *x_bf16,
+                                       void *stream) {
+    if (nx < 1 || ny < 1 || !x_bf16 || nobs < 0 || (nobs > 0 && (!cell || !y)) ||
+        !(kappa > 0))
+        return nfail(GABP_E_INVALID, "warm_features_noalloc: bad arguments");
+    if (nx > kFeatScratchCells || ny > kFeatScratchCells || nx * ny > kFeatScratchCells)
+        return nfail(GABP_E_INVALID,
+                     "warm_features_noalloc: nx * ny exceeds the static scratch of 2^21 cells");
+    float *scr = nullptr;
+    NHIP(scratch_address(&scr));
+    NHIP(features_into(nobs, cell, y, (long)nx * ny, kappa, scr, x_bf16, (hipStream_t)stream));
     return GABP_OK;
 }
 

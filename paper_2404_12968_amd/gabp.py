@@ -114,6 +114,8 @@ _SIGS = {
                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P], ctypes.c_int),
     "gabp_warm_loss": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _P, _P,
                         _P, _P], ctypes.c_int),
+    "gabp_warm_features_noalloc": ([ctypes.c_int64, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_double, _P, _P], ctypes.c_int),
     "gabp_warm_features": ([ctypes.c_int64, _P, _P, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_double, _P, _P, _P], ctypes.c_int),
     "gabp_net_last_error": ([], ctypes.c_char_p),
@@ -560,6 +562,16 @@ def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
                                     _ptr(y) if y.numel() else None, int(nx), int(ny), float(kappa),
                                     _ptr(scratch), _ptr(x), _stream_handle(stream)))
     return x
+
+
+def gabp_warm_features_noalloc(cells: torch.Tensor, y: torch.Tensor, nx: int, ny: int,
+                               kappa: float, out: torch.Tensor, stream=None) -> None:
+    """gabp_warm_features_noalloc into a caller-owned [ny, nx, 16] bf16 tensor
+    (cells int64 and y float64 device tensors; nothing is allocated)."""
+    _ncheck(_lib.gabp_warm_features_noalloc(int(cells.numel()),
+                                            _ptr(cells) if cells.numel() else None,
+                                            _ptr(y) if y.numel() else None, int(nx), int(ny),
+                                            float(kappa), _ptr(out), _stream_handle(stream)))
 
 
 def gabp_set_graph(ctx: Context, enable: bool) -> None:
