@@ -17,6 +17,8 @@ def _shift(x: np.ndarray, dy: int, dx: int) -> np.ndarray:
     """s[b, y, x] = x[b, y + dy, x + dx], zero outside the image."""
     B, H, W, C = x.shape
     out = np.zeros_like(x)
+    if abs(dy) >= H or abs(dx) >= W:
+        return out     # the whole shifted window lies in the zero padding
     ys = slice(max(0, -dy), min(H, H - dy))
     xs = slice(max(0, -dx), min(W, W - dx))
     yt = slice(max(0, dy), min(H, H + dy))

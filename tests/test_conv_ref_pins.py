@@ -6,8 +6,10 @@ import scipy.signal as ss
 from oracle import conv_ref as C
 
 
-@pytest.mark.parametrize("dil", [1, 2, 3])
+@pytest.mark.parametrize("dil", [1, 2, 3, 10, 27])
 def test_forward_equals_scipy_correlation(dil):
+    """Dilations up to and beyond the image size (taps that fall wholly in
+    the zero padding contribute nothing)."""
     rng = np.random.default_rng(dil)
     B, H, W, Ci, Co = 2, 9, 11, 3, 4
     x = rng.normal(size=(B, H, W, Ci))
