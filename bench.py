@@ -21,6 +21,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -325,13 +327,97 @@ def bench_table1(G, I, torch, args):
             "rows": rows}
 
 
+def net_flops_per_pixel():
+    """FLOPs of one forward pass of the warm-start network per pixel: each
+    layer is a 3x3 convolution computed over all its stored channels (the
+    kernels pad the input to 16 or 32 channels), 2 FLOPs per multiply-add."""
+    from paper_2404_12968_amd import warm as Wm
+    return sum(2 * 9 * ci * co for ci, co in zip(Wm.CIN, Wm.COUT))
+
+
+def bench_warmnet(G, I, torch, args):
+    """The learned warm start's network kernels (BF16 operands, FP32
+    accumulation on the matrix cores): inference on one 1024^2 problem and
+    training steps (forward, both gradients, loss, Adam) on batches of eight
+    256^2 crops, timed with HIP events on the stream the kernels run on."""
+    from paper_2404_12968_amd import warm as Wm
+    net = Wm.WarmNet.load(os.path.join(ROOT, "paper_2404_12968_amd", "weights", "warm1024.npz"))
+    probs = [I.warm1024(instance=310000 + k) for k in range(2)]
+    feats = [G.gabp_warm_features(p.cells, p.y, p.nx, p.ny, p.kappa) for p in probs]
+    stream = torch.cuda.current_stream()
+    fpp = net_flops_per_pixel()
+
+    def events(fn, reps):
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+
+    x1 = feats[0].unsqueeze(0).contiguous()
+    for _ in range(3):
+        net.forward(x1)
+    inf_ms = events(lambda: net.forward(x1), max(5, args.steps))
+    inf_flops = fpp * x1.shape[1] * x1.shape[2]
+    # a training batch: 8 crops of 256^2 with synthetic targets of the real shape
+    B, crop = 8, 256
+    rng = np.random.default_rng(0)
+    xs = []
+    for k in range(B):
+        f = feats[k % 2]
+        cy, cx = int(rng.integers(0, 1024 - crop)), int(rng.integers(0, 1024 - crop))
+        xs.append(f[cy:cy + crop, cx:cx + crop])
+    xb = torch.stack(xs).contiguous()
+    P = B * crop * crop
+    mu = torch.zeros(P, dtype=torch.float32, device=xb.device)
+    lam = torch.zeros((Wm.NDIR, P), dtype=torch.float32, device=xb.device)
+    val = torch.ones_like(lam)
+
+    def train_step():
+        acts, pred = net.forward(xb)
+        _, grad = G.gabp_warm_loss(pred, mu, lam, val, Wm.NDIR, 0.1)
+        dws, dbs = net.backward(acts, grad)
+        net.adam(dws, dbs, 0.0)
+
+    for _ in range(3):
+        train_step()
+    step_ms = events(train_step, max(5, args.steps))
+    # backward: the data gradient of layers 2..6 and the weight gradient of
+    # every layer, each as many FLOPs as that layer's forward pass
+    per_layer = [2 * 9 * ci * co for ci, co in zip(Wm.CIN, Wm.COUT)]
+    train_flops = P * (sum(per_layer) + sum(per_layer[1:]) + sum(per_layer))
+    peak = 2.5e15
+    return {"metric": "warm-start network: inference and training step time, TFLOP/s",
+            "value": train_flops / (step_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
+            "n_gpus": 1, "steps": max(5, args.steps), "warmup": 3, "ms_per_step": step_ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic",
+            "config": {"workload": "warmnet: 6 layers of 3x3 convolutions, 32 channels, "
+                                   "dilations 1,3,9,27,9,1; inference on 1024^2, training "
+                                   "steps on 8 crops of 256^2", "parallelism": "single GPU"},
+            "inference": {"ms": inf_ms, "pixels": int(x1.shape[1] * x1.shape[2]),
+                          "gflop": inf_flops / 1e9,
+                          "tflops": inf_flops / (inf_ms * 1e-3) / 1e12},
+            "training_step": {"ms": step_ms, "pixels": P, "gflop": train_flops / 1e9,
+                              "tflops": train_flops / (step_ms * 1e-3) / 1e12},
+            "roofline": {"bound": "mfma", "kernel": "network forward (inference)",
+                         "achieved": inf_flops / (inf_ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                         "unit": "TFLOP/s",
+                         "frac": inf_flops / (inf_ms * 1e-3) / peak, "traffic": None}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="global8192",
-                    choices=["global8192", "tracks2048", "batch256", "table1", "global32k"])
+                    choices=["global8192", "tracks2048", "batch256", "table1", "global32k",
+                             "warmnet"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-solve", action="store_true",
@@ -400,6 +486,10 @@ def main(argv=None):
         return 0
     if args.workload == "table1":
         print(json.dumps(bench_table1(G, I, torch, args)), flush=True)
+        return 0
+    if args.workload == "warmnet":
+        import numpy as np  # noqa: F401
+        print(json.dumps(bench_warmnet(G, I, torch, args)), flush=True)
         return 0
 
     prob = I.workload(args.workload)

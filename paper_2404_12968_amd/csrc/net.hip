@@ -39,12 +39,17 @@ __device__ __forceinline__ bf16x8 zero_bf16x8() {
 
 // --------------------------------------------------------------------------
 // Convolution, forward: y[p][co] = act(bias[co] + sum_{tap, ci}
-// w[co][tap][ci] x[p + dil * off(tap)][ci]), zero padding.  One wave = 32
-// consecutive pixels of one row and all 32 output-channel rows of the
-// weight matrix (M = channel, N = pixel, K = 9 * CIN).  The same kernel with
-// flipped, transposed weights computes the data gradient.
+// w[co][tap][ci] x[p + dil * off(tap)][ci]), zero padding.  M = output
+// channel (32 weight rows), N = pixel, K = 9 * CIN.  The work-group stages
+// the weight matrix in LDS once (rows padded by 8 values to spread the LDS
+// banks); each wave then computes NP tiles of 32 consecutive pixels of a row
+// (tiles numbered over (image, row, column tile)), reusing each K step's
+// weight fragment for its NP tiles.  The epilogue adds the bias, applies the
+// activation and stores four consecutive channels per lane and row of the
+// accumulator.  The same kernel with flipped, transposed weights computes
+// the data gradient.
 // --------------------------------------------------------------------------
-template <int CIN, int COUT>
+template <int CIN, int COUT, int NP>
 __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ x,
                                                   const __bf16 *__restrict__ w,
                                                   const float *__restrict__ bias, int B, int H,
@@ -52,43 +57,77 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ x,
                                                   __bf16 *__restrict__ yb,
                                                   float *__restrict__ yf) {
     constexpr int K = 9 * CIN;
+    constexpr int KP = K + 8;
+    __shared__ __bf16 wl[32 * KP];
+    for (int e = (int)threadIdx.x; e < 32 * (K / 8); e += 256) {
+        const int row = e / (K / 8), c8 = e % (K / 8);
+        *(bf16x8 *)(wl + row * KP + c8 * 8) = *(const bf16x8 *)(w + (size_t)row * K + c8 * 8);
+    }
+    __syncthreads();
     const int tpr = (W + 31) / 32;
-    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= (long)B * H * tpr) return;
-    const int b = (int)(wave / ((long)H * tpr));
-    const int rem = (int)(wave % ((long)H * tpr));
-    const int y = rem / tpr;
-    const int x0 = (rem % tpr) * 32;
+    const long ntiles = (long)B * H * tpr;
+    const long t0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * NP;
     const int lane = (int)(threadIdx.x & 63u);
     const int n = lane & 31, kh = lane >> 5;
-    const int px = x0 + n;
-    f32x16 acc;
+    int tb[NP], ty[NP], tx[NP];
+    bool tv[NP];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    for (int q = 0; q < NP; ++q) {
+        const long t = t0 + q;
+        tv[q] = t < ntiles;
+        const long tt = tv[q] ? t : 0;
+        tb[q] = (int)(tt / ((long)H * tpr));
+        const int rem = (int)(tt % ((long)H * tpr));
+        ty[q] = rem / tpr;
+        tx[q] = (rem % tpr) * 32 + n;
+    }
+    f32x16 acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
 #pragma unroll 3
     for (int s = 0; s < K / 16; ++s) {
         const int k = s * 16 + kh * 8;
         const int tap = k / CIN, ci0 = k % CIN;
-        const int yy = y + (tap / 3 - 1) * dil, xx = px + (tap % 3 - 1) * dil;
-        const bf16x8 a = *(const bf16x8 *)(w + (size_t)n * K + k);
-        bf16x8 bv = zero_bf16x8();
-        if (px < W && yy >= 0 && yy < H && xx >= 0 && xx < W)
-            bv = *(const bf16x8 *)(x + (((size_t)b * H + yy) * W + xx) * CIN + ci0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
-    }
-    if (px >= W) return;
-    const size_t o = (((size_t)b * H + y) * W + px) * COUT;
+        const int oy = (tap / 3 - 1) * dil, ox = (tap % 3 - 1) * dil;
+        const bf16x8 a = *(const bf16x8 *)(wl + n * KP + k);
+        bf16x8 bv[NP];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int co = 8 * i + 4 * kh + j;
-            if (co >= COUT) continue;
-            float v = acc[4 * i + j] + (bias ? bias[co] : 0.0f);
-            if (relu) v = v > 0.0f ? v : 0.0f;
-            if (yb) yb[o + co] = (__bf16)v;
-            if (yf) yf[o + co] = v;
+        for (int q = 0; q < NP; ++q) {
+            const int yy = ty[q] + oy, xx = tx[q] + ox;
+            bv[q] = zero_bf16x8();
+            if (tv[q] && tx[q] < W && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                bv[q] = *(const bf16x8 *)(x + (((size_t)tb[q] * H + yy) * W + xx) * CIN + ci0);
         }
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv[q], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        if (!tv[q] || tx[q] >= W) continue;
+        const size_t o = (((size_t)tb[q] * H + ty[q]) * W + tx[q]) * COUT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c0 = 8 * i + 4 * kh;    // channels c0 .. c0 + 3 of this lane
+            if (c0 >= COUT) continue;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[j] = acc[q][4 * i + j] + (bias ? bias[c0 + j] : 0.0f);
+                if (relu) v[j] = v[j] > 0.0f ? v[j] : 0.0f;
+            }
+            if (yb) {
+                typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+                bf16x4 pk;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pk[j] = (__bf16)v[j];
+                *(bf16x4 *)(yb + o + c0) = pk;
+            }
+            if (yf) *(float4 *)(yf + o + c0) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
 }
 
 // Flipped, transposed weights for the data gradient:
@@ -106,104 +145,207 @@ __global__ __launch_bounds__(256) void k_flip_weights(const __bf16 *__restrict__
     wt[idx] = v;
 }
 
-// dZ = dY * relu'(y) in BF16 (mask = 1 where the layer has no activation),
-// and its transpose dZT[c][p] for the weight gradient (rows c >= C zero).
-__global__ __launch_bounds__(256) void k_relu_bwd(const float *__restrict__ dy,
-                                                  const __bf16 *__restrict__ y, long P, int C,
-                                                  int relu, __bf16 *__restrict__ dz,
-                                                  __bf16 *__restrict__ dzt, long Ppad) {
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= 32 * Ppad) return;
-    const int c = (int)(idx / Ppad);
-    const long p = idx % Ppad;
-    float v = 0.0f;
-    if (c < C && p < P) {
-        v = dy[p * C + c];
-        if (relu && !((float)y[p * C + c] > 0.0f)) v = 0.0f;
-        dz[p * C + c] = (__bf16)v;
-    }
-    dzt[idx] = (__bf16)v;
-}
+// Backward of one layer, y = act(conv(x, w) + bias).  dZ = dY * relu'(y)
+// (BF16), then three products:
+//   data gradient    dX = conv(dZ, flipped w)          (k_conv_fwd)
+//   weight gradient  dW[co][tap][ci] = sum_p dZ[p][co] x[p + dil off(tap)][ci]
+//   bias gradient    db[co] = sum_p dZ[p][co]
+// The weight gradient is an implicit GEMM on the matrix cores with the pixels
+// as the reduction dimension (M = 32 output channels, N = 9 cin taps x
+// channels, K = pixels): no im2col is formed; each operand fragment is eight
+// consecutive pixels of one channel, read from channel-major copies of dZ
+// and x (dZT, xT: [channel][pixel], made by LDS-tiled transposes) at the
+// tap's pixel shift.  Work-groups take fixed pixel chunks (split-K) and the
+// partial sums are reduced in a fixed order, so the result is deterministic.
 
-// Transposed im2col of x for the weight gradient:
-// xt[tap * CIN + ci][p] = x[p + dil * off(tap)][ci] (0 outside the image),
-// rows up to nrows (multiple of 32) zero beyond 9 * CIN.
-__global__ __launch_bounds__(256) void k_im2col_t(const __bf16 *__restrict__ x, int B, int H,
-                                                  int W, int cin, int dil, int nrows, long Ppad,
-                                                  __bf16 *__restrict__ xt) {
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (long)nrows * Ppad) return;
-    const int r = (int)(idx / Ppad);
-    const long p = idx % Ppad;
-    __bf16 v = (__bf16)0.0f;
-    const long P = (long)B * H * W;
-    if (r < 9 * cin && p < P) {
-        const int tap = r / cin, ci = r % cin;
-        const int b = (int)(p / ((long)H * W));
-        const int rem = (int)(p % ((long)H * W));
-        const int yy = rem / W + (tap / 3 - 1) * dil, xx = rem % W + (tap % 3 - 1) * dil;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-            v = x[(((size_t)b * H + yy) * W + xx) * cin + ci];
-    }
-    xt[idx] = v;
-}
+constexpr int kTP = 64;   // pixels per transpose tile
 
-// Weight gradient as a split-K GEMM on the matrix cores:
-// part[kc][m][n] = sum_{p in chunk kc} dzt[m][p] xt[n][p]  (m < 32, n < N).
-// One wave = one 32 x 32 block of (m, n) over one chunk of pixels.
-__global__ __launch_bounds__(64) void k_gemm_nt(const __bf16 *__restrict__ dzt,
-                                                const __bf16 *__restrict__ xt, long Ppad,
-                                                int N, int chunk, float *__restrict__ part) {
-    const int nb = (int)blockIdx.x, kc = (int)blockIdx.y;
-    const int lane = (int)threadIdx.x;
-    const int r = lane & 31, kh = lane >> 5;
-    const long k0 = (long)kc * chunk;
-    long k1 = k0 + chunk;
-    if (k1 > Ppad) k1 = Ppad;
-    f32x16 acc;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    const __bf16 *arow = dzt + (size_t)r * Ppad;
-    const __bf16 *brow = xt + (size_t)(nb * 32 + r) * Ppad;
-    // wave-uniform trip count (Ppad and chunk are multiples of 16)
-    for (long kb = k0; kb < k1; kb += 16) {
-        const long k = kb + kh * 8;
-        const bf16x8 a = *(const bf16x8 *)(arow + k);
-        const bf16x8 bv = *(const bf16x8 *)(brow + k);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
-    }
-    float *out = part + (size_t)kc * 32 * N;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = 8 * i + 4 * kh + j;
-            out[(size_t)m * N + nb * 32 + r] = acc[4 * i + j];
+// dZ = dY * relu'(y): dz [P][C] BF16 (NHWC) and dzt [32][Ppad] (channel-major;
+// rows c >= C and columns p >= P zero), through a 32 x 64 LDS tile.
+__global__ __launch_bounds__(256) void k_relu_bwd_t(const float *__restrict__ dy,
+                                                    const __bf16 *__restrict__ y, long P, int C,
+                                                    int relu, __bf16 *__restrict__ dz,
+                                                    __bf16 *__restrict__ dzt, long Ppad) {
+    __shared__ __bf16 tile[32][kTP + 2];
+    const long p0 = (long)blockIdx.x * kTP;
+    for (int e = (int)threadIdx.x; e < kTP * 32; e += 256) {
+        const int p = e >> 5, c = e & 31;
+        float v = 0.0f;
+        if (c < C && p0 + p < P) {
+            const long o = (p0 + p) * C + c;
+            v = dy[o];
+            if (relu && !((float)y[o] > 0.0f)) v = 0.0f;
+            dz[o] = (__bf16)v;
         }
-}
-
-// dw[m][n] = sum_kc part[kc][m][n] (fixed order), db[m] = sum_p dzt[m][p].
-__global__ __launch_bounds__(256) void k_reduce_dw(const float *__restrict__ part, int nchunks,
-                                                   int N, int ncols, float *__restrict__ dw) {
-    const int idx = (int)(blockIdx.x * 256 + threadIdx.x);
-    if (idx >= 32 * ncols) return;
-    const int m = idx / ncols, n = idx % ncols;
-    float s = 0.0f;
-    for (int kc = 0; kc < nchunks; ++kc) s += part[(size_t)kc * 32 * N + (size_t)m * N + n];
-    dw[idx] = s;
-}
-
-__global__ __launch_bounds__(256) void k_row_sums(const __bf16 *__restrict__ dzt, long Ppad,
-                                                  float *__restrict__ db) {
-    __shared__ float sh[4];
-    const int m = (int)blockIdx.x;
-    float s = 0.0f;
-    for (long p = threadIdx.x; p < Ppad; p += 256) s += (float)dzt[(size_t)m * Ppad + p];
-#pragma unroll
-    for (int k = 32; k >= 1; k >>= 1) s += __shfl_xor(s, k, 64);
-    if ((threadIdx.x & 63u) == 0u) sh[threadIdx.x >> 6] = s;
+        tile[c][p] = (__bf16)v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) db[m] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    for (int e = (int)threadIdx.x; e < 32 * kTP; e += 256) {
+        const int c = e / kTP, p = e % kTP;
+        dzt[(size_t)c * Ppad + p0 + p] = tile[c][p];
+    }
+}
+
+// x [P][C] BF16 -> xt [C][Ppad] (columns p >= P zero), through an LDS tile.
+__global__ __launch_bounds__(256) void k_to_cmajor(const __bf16 *__restrict__ x, long P, int C,
+                                                   __bf16 *__restrict__ xt, long Ppad) {
+    __shared__ __bf16 tile[32][kTP + 2];
+    const long p0 = (long)blockIdx.x * kTP;
+    for (int e = (int)threadIdx.x; e < kTP * 32; e += 256) {
+        const int p = e >> 5, c = e & 31;
+        __bf16 v = (__bf16)0.0f;
+        if (c < C && p0 + p < P) v = x[(p0 + p) * C + c];
+        tile[c][p] = v;
+    }
+    __syncthreads();
+    for (int e = (int)threadIdx.x; e < C * kTP; e += 256) {
+        const int c = e / kTP, p = e % kTP;
+        xt[(size_t)c * Ppad + p0 + p] = tile[c][p];
+    }
+}
+
+// Weight and bias gradients of one layer.  One work-group per chunk of
+// `chunk` pixels (a multiple of 16); its waves split the N tiles, TPW tiles
+// each, and every wave walks all 16-pixel steps of the chunk.  For each step
+// a lane loads its A fragment (dZT row co = lane % 32, pixels p .. p + 7 with
+// p = step + 8 (lane / 32)) and one B fragment per tile of the wave (xT row
+// ci at the tap's shift, eight consecutive pixels: one 16-byte load when
+// they stay in one image row, masked element loads at the image edges), then
+// runs one MFMA per tile; the next step's loads are issued before this
+// step's MFMAs.  Each wave writes its tiles of the chunk's partial dW
+// [32][9 CIN], wave 0 also the partial db [32]; k_sum_rows sums the chunks
+// in order.
+template <int CIN, int TPW>
+__global__ __launch_bounds__(64 * (((9 * CIN + 31) / 32 + TPW - 1) / TPW)) void k_wgrad(
+    const __bf16 *__restrict__ dzt, const __bf16 *__restrict__ xt, int H, int W, int dil, long P,
+    long Ppad, int chunk, float *__restrict__ part, float *__restrict__ dbpart) {
+    constexpr int NN = 9 * CIN;
+    constexpr int NT = (NN + 31) / 32;     // N tiles of 32 (tap, channel) columns
+    const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+    const int r = lane & 31, h = lane >> 5;
+    const long HW = (long)H * W;
+    f32x16 acc[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; ++k)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[k][v] = 0.0f;
+    float bsum = 0.0f;
+    // this lane's (tap, channel) in each of the wave's tiles
+    int tdy[TPW], tdx[TPW], tci[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        const int n = 32 * (w * TPW + k) + r;
+        const int tap = n / CIN;
+        tci[k] = n % CIN;
+        const bool real = tap < 9 && w * TPW + k < NT;
+        tdy[k] = real ? (tap / 3 - 1) * dil : 1 << 28;   // huge: never inside
+        tdx[k] = real ? (tap % 3 - 1) * dil : 0;
+        if (!real) tci[k] = 0;
+    }
+    const int c0 = (int)((long)blockIdx.x * chunk);
+    const int c1 = (int)(c0 + chunk < Ppad ? c0 + chunk : Ppad);
+    const int Pi = (int)P, HWi = (int)HW;
+    // eight aligned pixels stay in one image row (and a 16-pixel step moves
+    // at most one row on)
+    const bool rows8 = (W & 7) == 0 && W >= 16;
+    // image, row and column of this lane's first pixel of the next step to
+    // load, advanced by 16 pixels per step (no division in the loop)
+    int pb = (c0 + 8 * h) / HWi, prem = (c0 + 8 * h) - pb * HWi;
+    int py = prem / W, px = prem - py * W;
+    // operands of the 16-pixel step at s (zero past the chunk)
+    auto load_step = [&](int s, bf16x8 &a, bf16x8 *bv) {
+        a = zero_bf16x8();
+#pragma unroll
+        for (int k = 0; k < TPW; ++k) bv[k] = zero_bf16x8();
+        const int p = s + 8 * h;
+        const int b = pb, y = py, x = px;
+        px += 16;
+        if (px >= W) {
+            px -= W;
+            if (++py == H) {
+                py = 0;
+                ++pb;
+            }
+        }
+        if (s >= c1) return;
+        a = *(const bf16x8 *)(dzt + (size_t)r * Ppad + p);
+#pragma unroll
+        for (int k = 0; k < TPW; ++k) {
+            const __bf16 *src = xt + (size_t)tci[k] * Ppad;
+            if (rows8 && p + 8 <= Pi) {
+                const int yy = y + tdy[k];
+                if (yy >= 0 && yy < H) {
+                    const int xs = x + tdx[k];
+                    const int q = (b * H + yy) * W + xs;
+                    if (xs >= 0 && xs + 8 <= W) {
+                        __builtin_memcpy(&bv[k], src + q, 16);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (xs + j >= 0 && xs + j < W) bv[k][j] = src[q + j];
+                    }
+                }
+            } else {
+                // general position: each pixel on its own (rows of any width,
+                // the last pixels of the batch)
+#pragma unroll 1
+                for (int j = 0; j < 8; ++j) {
+                    const int pj = p + j;
+                    if (pj >= Pi) break;
+                    const int bj = pj / HWi, rj = pj - bj * HWi;
+                    const int yj = rj / W + tdy[k], xj = rj % W + tdx[k];
+                    if (yj >= 0 && yj < H && xj >= 0 && xj < W)
+                        bv[k][j] = src[(bj * H + yj) * W + xj];
+                }
+            }
+        }
+    };
+    auto mma_step = [&](const bf16x8 &a, const bf16x8 *bv) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bsum += (float)a[j];
+#pragma unroll
+        for (int k = 0; k < TPW; ++k)
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv[k], acc[k], 0, 0, 0);
+    };
+    bf16x8 a0, a1, b0[TPW], b1[TPW];
+    int s = c0;
+    load_step(s, a0, b0);
+#pragma unroll 1
+    for (; s < c1; s += 32) {
+        load_step(s + 16, a1, b1);
+        mma_step(a0, b0);
+        if (s + 16 >= c1) break;
+        load_step(s + 32, a0, b0);
+        mma_step(a1, b1);
+    }
+    // this wave's tiles of the partial: D[co][n] with co = 8 i + 4 h + j in
+    // accumulator 4 i + j, n = 32 tile + lane % 32
+    float *out = part + (size_t)blockIdx.x * 32 * NN;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        const int n = 32 * (w * TPW + k) + r;
+        if (n >= NN) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[(size_t)(8 * i + 4 * h + j) * NN + n] = acc[k][4 * i + j];
+    }
+    bsum += __shfl_xor(bsum, 32, 64);   // lanes r and r + 32 hold the same channel
+    if (w == 0 && h == 0) dbpart[(size_t)blockIdx.x * 32 + r] = bsum;
+}
+
+// out[g][i] = sum of in[r][i] over rows r in [g rpg, (g + 1) rpg) of nrows,
+// in order: the split-K partials of the weight and bias gradients are summed
+// in two such passes (groups, then the groups), a fixed order.
+__global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ in, int nrows,
+                                                  int rpg, int ncols, float *__restrict__ out) {
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    const int g = (int)blockIdx.y;
+    if (i >= ncols) return;
+    const int r0 = g * rpg, r1 = min(nrows, r0 + rpg);
+    float acc = 0.0f;
+    for (int r = r0; r < r1; ++r) acc += in[(size_t)r * ncols + i];
+    out[(size_t)g * ncols + i] = acc;
 }
 
 // Adam step on FP32 master weights (bias-corrected moments); refreshes the
@@ -240,16 +382,30 @@ __global__ __launch_bounds__(256) void k_warm_loss(const float *__restrict__ pre
     const long p = (long)blockIdx.x * 256 + threadIdx.x;
     double l = 0.0;
     if (p < P) {
-        const float e = pred[p * 16] - mu_t[p];
-        grad[p * 16] = 2.0f * e * inv_np;
+        // the pixel's 16 prediction channels as four 16-byte rows
+        const float4 *pr = (const float4 *)(pred + p * 16);
+        float v[16], g[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t = pr[q];
+            v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        }
+        const float e = v[0] - mu_t[p];
+        g[0] = 2.0f * e * inv_np;
         l += (double)e * e * inv_np;
-        for (int d = 0; d < ndir; ++d) {
-            const float ok = valid[(size_t)d * P + p];
-            const float ed = ok > 0.0f ? pred[p * 16 + 1 + d] - lam_t[(size_t)d * P + p] : 0.0f;
-            grad[p * 16 + 1 + d] = 2.0f * ed * lam_w_inv_ne;
+#pragma unroll
+        for (int d = 0; d < 15; ++d) {
+            float ed = 0.0f;
+            if (d < ndir) {
+                const float ok = valid[(size_t)d * P + p];
+                ed = ok > 0.0f ? v[1 + d] - lam_t[(size_t)d * P + p] : 0.0f;
+            }
+            g[1 + d] = 2.0f * ed * lam_w_inv_ne;
             l += (double)ed * ed * lam_w_inv_ne;
         }
-        for (int c = 1 + ndir; c < 16; ++c) grad[p * 16 + c] = 0.0f;
+        float4 *gr = (float4 *)(grad + p * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gr[q] = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
     }
 #pragma unroll
     for (int k = 32; k >= 1; k >>= 1) l += __shfl_xor(l, k, 64);
@@ -416,25 +572,33 @@ bool chan_ok(int c) { return c == 16 || c == 32; }
             return nfail(GABP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+constexpr int kConvNP = 2;   // 32-pixel tiles per wave of the convolution
+
 hipError_t conv_dispatch(const void *x, int B, int H, int W, int cin, const void *w,
                          const float *bias, int cout, int dil, int relu, void *yb, float *yf,
                          hipStream_t s) {
-    const long waves = (long)B * H * ((W + 31) / 32);
+    const long tiles = (long)B * H * ((W + 31) / 32);
+    const long waves = (tiles + kConvNP - 1) / kConvNP;
     dim3 grid((unsigned)((waves + 3) / 4)), block(256);
     const __bf16 *xx = (const __bf16 *)x, *ww = (const __bf16 *)w;
     __bf16 *ybb = (__bf16 *)yb;
     if (cin == 16 && cout == 16)
-        hipLaunchKernelGGL((gabp::k_conv_fwd<16, 16>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
+        hipLaunchKernelGGL((gabp::k_conv_fwd<16, 16, kConvNP>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
     else if (cin == 16)
-        hipLaunchKernelGGL((gabp::k_conv_fwd<16, 32>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
+        hipLaunchKernelGGL((gabp::k_conv_fwd<16, 32, kConvNP>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
     else if (cout == 16)
-        hipLaunchKernelGGL((gabp::k_conv_fwd<32, 16>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
+        hipLaunchKernelGGL((gabp::k_conv_fwd<32, 16, kConvNP>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
     else
-        hipLaunchKernelGGL((gabp::k_conv_fwd<32, 32>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
+        hipLaunchKernelGGL((gabp::k_conv_fwd<32, 32, kConvNP>), grid, block, 0, s, xx, ww, bias, B, H, W, dil, relu, ybb, yf);
     return hipGetLastError();
 }
 
-long pad16(long p) { return (p + 15) / 16 * 16; }
+long pad64(long p) { return (p + 63) / 64 * 64; }
+// pixels per work-group of the weight gradient (split-K chunk), and the
+// groups of chunks its first summation pass forms
+constexpr long kWgradChunk = 1024;
+constexpr int kWgradTPW = 3;     // N tiles per wave
+constexpr int kSumGroups = 16;
 }  // namespace
 
 extern "C" {
@@ -452,16 +616,16 @@ gabp_status gabp_conv3x3_fwd(const void *x, int32_t B, int32_t H, int32_t W, int
 }
 
 size_t gabp_conv3x3_bwd_workspace(int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout) {
-    const long P = (long)B * H * W, Pp = pad16(P);
-    const int nrows = ((9 * cin + 31) / 32) * 32;
-    const long chunk = 8192;
-    const long nchunks = (Pp + chunk - 1) / chunk;
+    const long P = (long)B * H * W, Pp = pad64(P);
+    const long nchunks = (Pp + kWgradChunk - 1) / kWgradChunk;
     size_t bytes = 0;
     bytes += (size_t)32 * 9 * 32 * 2 + 256;                  // flipped weights
     bytes += (size_t)P * cout * 2 + 256;                     // dz (NHWC)
-    bytes += (size_t)32 * Pp * 2 + 256;                      // dz transposed
-    bytes += (size_t)nrows * Pp * 2 + 256;                   // im2col transposed
-    bytes += (size_t)nchunks * 32 * nrows * 4 + 256;         // split-K partials
+    bytes += (size_t)32 * Pp * 2 + 256;                      // dz channel-major
+    bytes += (size_t)cin * Pp * 2 + 256;                     // x channel-major
+    bytes += (size_t)nchunks * 32 * 9 * cin * 4 + 256;       // split-K partials of dw
+    bytes += (size_t)nchunks * 32 * 4 + 256;                 // and of db
+    bytes += (size_t)kSumGroups * 32 * (9 * cin + 1) * 4 + 512;   // group sums
     return bytes;
 }
 
@@ -476,13 +640,13 @@ gabp_status gabp_conv3x3_bwd(const void *x, const void *y, const float *dy, int3
     if (!x || !y || !dy || !w || !dw || !db || B < 1 || H < 1 || W < 1 || !chan_ok(cin) ||
         !chan_ok(cout) || dil < 1 || !workspace)
         return nfail(GABP_E_INVALID, "conv3x3_bwd: bad arguments");
+    if ((long)B * H * W >= (1L << 31) - 64)
+        return nfail(GABP_E_INVALID, "conv3x3_bwd: more than 2^31 - 64 pixels");
     if (workspace_bytes < gabp_conv3x3_bwd_workspace(B, H, W, cin, cout))
         return nfail(GABP_E_NOMEM, "conv3x3_bwd: workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    const long P = (long)B * H * W, Pp = pad16(P);
-    const int nrows = ((9 * cin + 31) / 32) * 32;
-    const long chunk = 8192;
-    const int nchunks = (int)((Pp + chunk - 1) / chunk);
+    const long P = (long)B * H * W, Pp = pad64(P);
+    const int nchunks = (int)((Pp + kWgradChunk - 1) / kWgradChunk);
     char *ws = (char *)workspace;
     auto take = [&](size_t bytes) {
         char *p = ws;
@@ -492,17 +656,38 @@ gabp_status gabp_conv3x3_bwd(const void *x, const void *y, const float *dy, int3
     __bf16 *wt = (__bf16 *)take((size_t)32 * 9 * 32 * 2);
     __bf16 *dz = (__bf16 *)take((size_t)P * cout * 2);
     __bf16 *dzt = (__bf16 *)take((size_t)32 * Pp * 2);
-    __bf16 *xt = (__bf16 *)take((size_t)nrows * Pp * 2);
-    float *part = (float *)take((size_t)nchunks * 32 * nrows * 4);
-    hipLaunchKernelGGL(gabp::k_relu_bwd, dim3((unsigned)((32 * Pp + 255) / 256)), dim3(256), 0, s,
-                       dy, (const __bf16 *)y, P, cout, relu, dz, dzt, Pp);
-    hipLaunchKernelGGL(gabp::k_im2col_t, dim3((unsigned)((nrows * Pp + 255) / 256)), dim3(256), 0, s,
-                       (const __bf16 *)x, B, H, W, cin, dil, nrows, Pp, xt);
-    hipLaunchKernelGGL(gabp::k_gemm_nt, dim3(nrows / 32, nchunks), dim3(64), 0, s,
-                       (const __bf16 *)dzt, (const __bf16 *)xt, Pp, nrows, (int)chunk, part);
-    hipLaunchKernelGGL(gabp::k_reduce_dw, dim3((32 * 9 * cin + 255) / 256), dim3(256), 0, s,
-                       (const float *)part, nchunks, nrows, 9 * cin, dw);
-    hipLaunchKernelGGL(gabp::k_row_sums, dim3(32), dim3(256), 0, s, (const __bf16 *)dzt, Pp, db);
+    __bf16 *xt = (__bf16 *)take((size_t)cin * Pp * 2);
+    float *part = (float *)take((size_t)nchunks * 32 * 9 * cin * 4);
+    float *dbpart = (float *)take((size_t)nchunks * 32 * 4);
+    float *gpart = (float *)take((size_t)kSumGroups * 32 * 9 * cin * 4);
+    float *gdb = (float *)take((size_t)kSumGroups * 32 * 4);
+    const unsigned tiles = (unsigned)(Pp / gabp::kTP);
+    hipLaunchKernelGGL(gabp::k_relu_bwd_t, dim3(tiles), dim3(256), 0, s, dy, (const __bf16 *)y, P,
+                       cout, relu, dz, dzt, Pp);
+    hipLaunchKernelGGL(gabp::k_to_cmajor, dim3(tiles), dim3(256), 0, s, (const __bf16 *)x, P, cin,
+                       xt, Pp);
+    // waves per work-group: the N tiles (5 for 16 input channels, 9 for 32)
+    // in groups of kWgradTPW
+    if (cin == 16)
+        hipLaunchKernelGGL((gabp::k_wgrad<16, kWgradTPW>), dim3(nchunks),
+                           dim3(64 * ((5 + kWgradTPW - 1) / kWgradTPW)), 0, s,
+                           (const __bf16 *)dzt, (const __bf16 *)xt, H, W, dil, P, Pp,
+                           (int)kWgradChunk, part, dbpart);
+    else
+        hipLaunchKernelGGL((gabp::k_wgrad<32, kWgradTPW>), dim3(nchunks),
+                           dim3(64 * ((9 + kWgradTPW - 1) / kWgradTPW)), 0, s,
+                           (const __bf16 *)dzt, (const __bf16 *)xt, H, W, dil, P, Pp,
+                           (int)kWgradChunk, part, dbpart);
+    const int nn = 32 * 9 * cin;
+    const int rpg = (nchunks + kSumGroups - 1) / kSumGroups;
+    hipLaunchKernelGGL(gabp::k_sum_rows, dim3((nn + 255) / 256, kSumGroups), dim3(256), 0, s,
+                       (const float *)part, nchunks, rpg, nn, gpart);
+    hipLaunchKernelGGL(gabp::k_sum_rows, dim3((nn + 255) / 256, 1), dim3(256), 0, s,
+                       (const float *)gpart, kSumGroups, kSumGroups, nn, dw);
+    hipLaunchKernelGGL(gabp::k_sum_rows, dim3(1, kSumGroups), dim3(256), 0, s,
+                       (const float *)dbpart, nchunks, rpg, 32, gdb);
+    hipLaunchKernelGGL(gabp::k_sum_rows, dim3(1, 1), dim3(256), 0, s, (const float *)gdb,
+                       kSumGroups, kSumGroups, 32, db);
     if (dx) {
         hipLaunchKernelGGL(gabp::k_flip_weights, dim3((32 * 9 * cout + 255) / 256), dim3(256), 0, s,
                            (const __bf16 *)w, cin, cout, wt);

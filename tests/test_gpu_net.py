@@ -52,10 +52,15 @@ def test_conv_forward_matches_reference(G, cin, cout, dil, relu):
     assert np.array_equal(yb.cpu().float().numpy(), yf.cpu().to(torch.bfloat16).float().numpy())
 
 
+@pytest.mark.parametrize("shape", [(2, 11, 45), (3, 9, 40), (1, 16, 64)],
+                         ids=["w45", "w40_ragged", "w64"])
 @pytest.mark.parametrize("cin,cout,dil,relu", CASES)
-def test_conv_backward_matches_reference(G, cin, cout, dil, relu):
+def test_conv_backward_matches_reference(G, cin, cout, dil, relu, shape):
+    """Rows of any width (the weight gradient's per-pixel path), widths that
+    are a multiple of 8 (its 16-byte loads, masked at the image edges) and
+    pixel counts that are not a multiple of the 64-pixel tiles."""
     rng = np.random.default_rng(cin * 7 + dil)
-    B, H, W = 2, 11, 45
+    B, H, W = shape
     x = bf16_round(rng.normal(size=(B, H, W, cin)))
     w = weights(rng, cin, cout)
     b = rng.normal(size=32).astype(np.float32) * 0.1
