@@ -86,20 +86,32 @@ def rel_err(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def fp64_reference(prob, tol=1e-10):
+def progress(msg):
+    """One progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
+def fp64_reference(prob, tol=None):
     """The posterior mean an FP32 result is compared with: the same problem
     solved with FP64 messages (the path pinned to the oracle at 1e-12) by
-    multigrid to a 1e-10 relative residual.  Returns (mean on the device,
-    description)."""
+    multigrid to the same stopping rule (the problem's relative residual, or
+    tol).  Tighter FP64 references are out of reach on these workloads: the
+    smoothest error modes of the 13-point prior decay so slowly that FP64
+    iterations from a 1e-6 solution of the 8192 x 4096 lattice stay above 4e-8
+    after 400 000 iterations.  Returns (mean on the device, description)."""
     import dataclasses
 
     from paper_2404_12968_amd import gabp as G
     from paper_2404_12968_amd import multigrid as MG
+    tol = prob.rel_tol if tol is None else tol
+    progress(f"FP64 reference of {prob.name} to {tol:g}")
     p64 = dataclasses.replace(prob, dtype="f64", rel_tol=tol)
-    r = MG.multigrid_solve(p64, keep_context=True, max_iters=2000000)
+    r = MG.multigrid_solve(p64, keep_context=True)
     mu = G.gabp_posterior(r["ctx"], want_var=False)[0]
     G.gabp_destroy(r["ctx"])
-    return mu, {"reference": "FP64 messages, multigrid to the residual below",
+    progress(f"FP64 reference done in {r['seconds']:.1f} s")
+    return mu, {"reference": "FP64 messages, multigrid to the residual below (the FP32 runs' "
+                             "stopping rule)",
                 "rel_residual": r["rel"], "status": G.gabp_status_string(r["status"]),
                 "fine_iterations": r["iterations"], "seconds": r["seconds"]}
 
@@ -134,7 +146,7 @@ def cpu_baseline(prob, seconds=10.0):
                       f"{its} iterations after 2 warm-up, {el:.1f} s"}
 
 
-def bench_warm(I, n, freeze=None, fp64_ref=True):
+def bench_warm(I, n, freeze=None, fp64_ref=True, tol=None):
     """Time to 1e-6 on held-out 1024^2 warm-start problems, cold vs the trained
     network's warm start (inference and the fallback probe included) vs
     multigrid; each FP32 mean's relative L2 error against the FP64 reference."""
@@ -157,7 +169,7 @@ def bench_warm(I, n, freeze=None, fp64_ref=True):
         if fp64_ref:
             mm = G.gabp_posterior(m["ctx"], want_var=False)[0]
             G.gabp_destroy(m["ctx"])
-            ref, info = fp64_reference(p)
+            ref, info = fp64_reference(p, tol)
             rows[-1]["error_vs_fp64"] = {"cold": rel_err(c["mean"], ref),
                                          "warm": rel_err(w["mean"], ref),
                                          "multigrid": rel_err(mm, ref),
@@ -171,7 +183,7 @@ def bench_warm(I, n, freeze=None, fp64_ref=True):
             "freeze_tolerance": {"max_slots": freeze[0], "max_rel": freeze[1]} if freeze
             else "bitwise",
             "error_vs_fp64_note": "relative L2 of each FP32 mean against the same problem solved "
-                                  "with FP64 messages by multigrid to a 1e-10 residual",
+                                  "with FP64 messages by multigrid to the same residual",
             "cold_seconds": cs, "warm_seconds": ws, "speedup": cs / ws if ws > 0 else None,
             "multigrid_seconds": ms, "multigrid_speedup": cs / ms if ms > 0 else None,
             "instances": rows}
@@ -429,6 +441,8 @@ def main(argv=None):
     ap.add_argument("--warm-freeze-slots", type=int, default=64,
                     help="warm-start leg: freeze tolerance (messages) of the cold, warm and "
                          "multigrid solves alike (0: bitwise freeze only)")
+    ap.add_argument("--fp64-ref-tol", type=float, default=None,
+                    help="residual of the FP64 reference solves (default: each problem's own)")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the FP64 reference solves that the FP32 results' errors are "
                          "measured against")
@@ -647,11 +661,13 @@ def main(argv=None):
                      "traffic": traffic},
     }
     del ctx
+    progress(f"timed steps done: {value:.3e} edge-message updates/s")
     ref = None
     if not args.no_fp64_ref and (not args.no_solve or not args.no_multigrid):
-        ref, info = fp64_reference(prob)
+        ref, info = fp64_reference(prob, args.fp64_ref_tol)
         out["fp64_reference"] = info
     if not args.no_solve:
+        progress("cold solve to the tolerance")
         ctx2 = G.gabp_create_problem(prob, device=dev)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -665,15 +681,19 @@ def main(argv=None):
                 G.gabp_posterior(ctx2, want_var=False)[0], ref)
         del ctx2
     if not args.no_multigrid:
+        progress("multigrid solve to the tolerance")
         out["multigrid"] = bench_multigrid(G, prob, ref)
         if "time_to_tol" in out:
             out["multigrid"]["speedup_vs_cold"] = (out["time_to_tol"]["seconds"] /
                                                    out["multigrid"]["seconds"])
     del ref
     if not args.no_warm:
+        progress("warm-start leg")
         wf = (args.warm_freeze_slots, args.freeze_rel) if args.warm_freeze_slots > 0 else None
-        out["warm_start"] = bench_warm(I, args.warm_instances, wf, not args.no_fp64_ref)
+        out["warm_start"] = bench_warm(I, args.warm_instances, wf, not args.no_fp64_ref,
+                                       args.fp64_ref_tol)
     if not args.no_table1:
+        progress("Table 1 leg")
         t1 = bench_table1(G, I, torch, args)
         out["table1"] = {"seconds": t1["value"], "paper_seconds_rtx3090": t1["value"] / t1["vs_baseline"],
                          "config": t1["config"]["workload"], "truths_per_config": args.table1_truths,
@@ -681,6 +701,7 @@ def main(argv=None):
                                                       "paper_mp_seconds_rtx3090", "paper_mp_rmse",
                                                       "paper_exact_rmse")} for r in t1["rows"]]}
     if not args.no_cpu_baseline:
+        progress("CPU baseline")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0

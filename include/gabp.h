@@ -274,6 +274,14 @@ gabp_status gabp_get_tile(const gabp_ctx *ctx, int32_t *rows_per_thread, int32_t
  * precision messages.  The iteration counter is kept.  Async. */
 gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precisions);
 
+/* Training targets of the learned warm start's precision outputs from the
+ * current messages: lam [12][ny][nx] (FP32, device) receives log(-Lam) of the
+ * message from each cell to its neighbour in direction d (-Lam floored at
+ * 1e-30), and valid [12][ny][nx] (FP32, device, may be NULL) 1 where that
+ * neighbour exists; both 0 elsewhere and for d >= deg.  These are the
+ * channels 1..12 gabp_warm_init reads.  Async. */
+gabp_status gabp_log_precisions(gabp_ctx *ctx, float *lam, float *valid);
+
 /* Multigrid transfer (Alg. 2, Upscale Messages, read as initialising the
  * finer grid's marginals to the coarser grid's): writes into channel 0 of a
  * prediction pred [nyf][nxf][16] (FP32, other channels 0) the bilinear
@@ -393,6 +401,11 @@ gabp_status gabp_batch_autotune(gabp_batch *b, int32_t trials, double damping, i
  * range or a NULL pred, DIVERGED for an instance that diverged. */
 gabp_status gabp_batch_warm_init(gabp_batch *b, int32_t i, const float *pred,
                                  int32_t keep_precisions);
+
+/* gabp_log_precisions for instance i of a batch (arrays of its own size).
+ * Asynchronous on the batch's stream; INVALID for an index out of range or a
+ * NULL lam. */
+gabp_status gabp_batch_log_precisions(gabp_batch *b, int32_t i, float *lam, float *valid);
 
 /* gabp_upscale_precisions from instance i of a batch (as the coarse
  * context) into a finer prediction pred[nyf][nxf][16].  Asynchronous on the

@@ -1126,6 +1126,18 @@ gabp_status gabp_batch_get_messages(gabp_batch *b, int32_t i, void *prec, void *
     return GABP_OK;
 }
 
+gabp_status gabp_batch_log_precisions(gabp_batch *b, int32_t i, float *lam, float *valid) {
+    if (!b) return GABP_E_INVALID;
+    if (i < 0 || i >= b->n || !lam) return bfail(b, GABP_E_INVALID, "need 0 <= i < n and lam");
+    StreamJoin join(b);
+    if (!join.ok) return bfail(b, GABP_E_DEVICE, "stream ordering failed");
+    const InstHost &H = b->h[i];
+    char *base = b->ws + H.base;
+    BHIP(b, gabp::launch_log_prec(b->dtype == GABP_F32 ? 0 : 1, H.L, base + H.lay.msg[state_buf(H)],
+                                  lam, valid, b->stream));
+    return GABP_OK;
+}
+
 gabp_status gabp_batch_warm_init(gabp_batch *b, int32_t i, const float *pred,
                                  int32_t keep_precisions) {
     if (!b) return GABP_E_INVALID;

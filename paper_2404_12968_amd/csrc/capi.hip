@@ -964,6 +964,15 @@ gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precis
     return GABP_OK;
 }
 
+gabp_status gabp_log_precisions(gabp_ctx *ctx, float *lam, float *valid) {
+    gabp_status st = ctx_ok(ctx);
+    if (st != GABP_OK) return st;
+    if (!lam) return fail(ctx, GABP_E_INVALID, "lam is NULL");
+    GABP_HIP(ctx, gabp::launch_log_prec(ctx->dtype == GABP_F32 ? 0 : 1, ctx->L, cur_msgs(ctx), lam,
+                                        valid, ctx->stream));
+    return GABP_OK;
+}
+
 gabp_status gabp_iteration_count(gabp_ctx *ctx, int64_t *iters) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;

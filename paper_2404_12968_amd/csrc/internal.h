@@ -72,6 +72,9 @@ hipError_t launch_upsample_mean(const double *coarse, int nxc, int nyc, int perx
 // Message initialisation from a network prediction (net.hip).
 hipError_t launch_warm_init(int dtype, const Lattice &L, const float *pred, int keep_prec,
                             void *m, hipStream_t s);
+// Targets log(-Lam) and edge masks of the precision outputs (net.hip).
+hipError_t launch_log_prec(int dtype, const Lattice &L, const void *m, float *lam, float *valid,
+                           hipStream_t s);
 hipError_t launch_msgs_get(int dtype, const Lattice &L, const void *m, void *prec, void *info,
                            hipStream_t s);
 hipError_t launch_msgs_set(int dtype, const Lattice &L, void *m, const void *prec,

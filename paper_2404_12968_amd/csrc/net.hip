@@ -484,9 +484,56 @@ __global__ __launch_bounds__(256) void k_warm_init(Lattice L, const float *__res
     }
 }
 
+// Training targets of the precision outputs from a solver state:
+// lam[d][y][x] = log(-Lam) of the message from (x, y) to its neighbour in
+// direction d (the sender-indexed plane d of the message buffer m) and
+// valid[d][y][x] = 1 where that neighbour exists; 0 in both elsewhere and
+// for d >= deg (12 planes are always written).  -Lam is floored at 1e-30.
+template <typename T, int ALPHA>
+__global__ __launch_bounds__(256) void k_log_prec(Lattice L, const T *__restrict__ m,
+                                                  float *__restrict__ lam,
+                                                  float *__restrict__ valid) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const int tile = (int)blockIdx.x;
+    const int x = (tile % L.tiles_x) * 64 + (int)(threadIdx.x & 63u);
+    const int y = (tile / L.tiles_x) * 4 + (int)(threadIdx.x >> 6);
+    if (x >= L.nx || y >= L.ny) return;
+    const uint32_t i = (uint32_t)(y * L.pitch + x);
+    const size_t np = (size_t)L.nx * L.ny, pi = (size_t)y * L.nx + x;
+#pragma unroll
+    for (int d = 0; d < 12; ++d) {
+        float l = 0.0f, v = 0.0f;
+        int xn, yn;
+        if (d < DEG && neighbour(L, x, y, d, xn, yn)) {
+            const float neg = -(float)(m + (size_t)d * L.plane)[i];
+            l = logf(neg > 1e-30f ? neg : 1e-30f);
+            v = 1.0f;
+        }
+        lam[(size_t)d * np + pi] = l;
+        if (valid) valid[(size_t)d * np + pi] = v;
+    }
+}
+
 // --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
+hipError_t launch_log_prec(int dtype, const Lattice &L, const void *m, float *lam, float *valid,
+                           hipStream_t s) {
+    dim3 grid(L.tiles_x * ((L.ny + 3) / 4)), block(256);
+    if (dtype == 0) {
+        if (L.alpha == 1)
+            hipLaunchKernelGGL((k_log_prec<float, 1>), grid, block, 0, s, L, (const float *)m, lam, valid);
+        else
+            hipLaunchKernelGGL((k_log_prec<float, 2>), grid, block, 0, s, L, (const float *)m, lam, valid);
+    } else {
+        if (L.alpha == 1)
+            hipLaunchKernelGGL((k_log_prec<double, 1>), grid, block, 0, s, L, (const double *)m, lam, valid);
+        else
+            hipLaunchKernelGGL((k_log_prec<double, 2>), grid, block, 0, s, L, (const double *)m, lam, valid);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_warm_init(int dtype, const Lattice &L, const float *pred, int keep_prec,
                             void *m, hipStream_t s) {
     dim3 grid(L.tiles_x * ((L.ny + 3) / 4)), block(256);

@@ -93,6 +93,8 @@ _SIGS = {
     "gabp_set_graph": ([_P, ctypes.c_int32], ctypes.c_int),
     "gabp_set_tile": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "gabp_launch_counts": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "gabp_log_precisions": ([_P, _P, _P], ctypes.c_int),
+    "gabp_batch_log_precisions": ([_P, ctypes.c_int32, _P, _P], ctypes.c_int),
     "gabp_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_batch_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_batch_warm_init": ([_P, ctypes.c_int32, _P, ctypes.c_int32], ctypes.c_int),
@@ -453,6 +455,15 @@ def gabp_batch_upscale_precisions(b: Batch, i: int, pred: torch.Tensor, scale: f
                                                float(scale)), b)
 
 
+def gabp_batch_log_precisions(b: Batch, i: int, want_valid: bool = True):
+    """gabp_log_precisions of instance i: (lam, valid or None) [12, ny, nx]."""
+    nx, ny, _ = b.shapes[i]
+    lam = torch.empty((12, ny, nx), dtype=torch.float32, device=b.device)
+    valid = torch.empty_like(lam) if want_valid else None
+    _bcheck(_lib.gabp_batch_log_precisions(b.handle, int(i), _ptr(lam), _ptr(valid)), b)
+    return lam, valid
+
+
 def gabp_batch_get_messages(b: Batch, i: int):
     nx, ny, deg = b.shapes[i]
     td = TORCH_DTYPES[b.dtype]
@@ -554,8 +565,12 @@ def gabp_warm_loss(pred, mu_t, lam_t, valid, ndir, lam_weight, stream=None):
 def gabp_warm_features(cells, y, nx, ny, kappa, device=None, stream=None):
     """[ny, nx, 16] bf16 input features of one problem."""
     device = torch.device(device or "cuda")
-    cells = torch.as_tensor(np.asarray(cells), dtype=torch.int64).to(device).contiguous()
-    y = torch.as_tensor(np.asarray(y), dtype=torch.float64).to(device).contiguous()
+    if not isinstance(cells, torch.Tensor):
+        cells = torch.as_tensor(np.asarray(cells), dtype=torch.int64)
+    if not isinstance(y, torch.Tensor):
+        y = torch.as_tensor(np.asarray(y), dtype=torch.float64)
+    cells = cells.to(device=device, dtype=torch.int64).contiguous()
+    y = y.to(device=device, dtype=torch.float64).contiguous()
     scratch = torch.empty(2 * nx * ny, dtype=torch.float32, device=device)
     x = torch.empty((ny, nx, 16), dtype=torch.bfloat16, device=device)
     _ncheck(_lib.gabp_warm_features(int(cells.numel()), _ptr(cells) if cells.numel() else None,
@@ -593,6 +608,14 @@ def gabp_set_freeze_tolerance(ctx: Context, max_slots: int, max_rel: float) -> N
 def gabp_batch_set_freeze_tolerance(b: Batch, max_slots: int, max_rel: float) -> None:
     """gabp_set_freeze_tolerance for every instance of a batch."""
     _bcheck(_lib.gabp_batch_set_freeze_tolerance(b.handle, int(max_slots), float(max_rel)), b)
+
+
+def gabp_log_precisions(ctx: Context, want_valid: bool = True):
+    """(lam [12, ny, nx], valid [12, ny, nx] or None) FP32 device tensors."""
+    lam = torch.empty((12, ctx.ny, ctx.nx), dtype=torch.float32, device=ctx.device)
+    valid = torch.empty_like(lam) if want_valid else None
+    _check(_lib.gabp_log_precisions(ctx.handle, _ptr(lam), _ptr(valid)), ctx)
+    return lam, valid
 
 
 def gabp_launch_counts(ctx: Context) -> dict:

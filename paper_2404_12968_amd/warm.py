@@ -118,66 +118,59 @@ class WarmNet:
 
 
 # --------------------------------------------------------------------------
-# targets from solver states
+# training data: the solver's own solutions
 # --------------------------------------------------------------------------
 
-def sender_log_precisions(prec_recv: torch.Tensor, bc_x: int, bc_y: int):
-    """log(-Lam) of sender-indexed messages from receiver-indexed precision
-    planes [deg, ny, nx] (gabp_get_messages layout): the message from i to
-    i + off_d is the receiver slot d^1 at i + off_d.  Returns (lam [12,ny,nx],
-    valid [12,ny,nx]) FP32 with valid = 1 where the edge exists."""
-    deg, ny, nx = prec_recv.shape
-    lam = torch.zeros((NDIR, ny, nx), dtype=torch.float32, device=prec_recv.device)
-    valid = torch.zeros_like(lam)
-    for d in range(deg):
-        dx, dy = DIRS[d]
-        src = prec_recv[d ^ 1].to(torch.float32)
-        # out[y, x] = src[y + dy, x + dx]
-        sh = torch.zeros_like(src)
-        ok = torch.zeros_like(src)
-        ys = slice(max(0, -dy), min(ny, ny - dy)); yt = slice(max(0, dy), min(ny, ny + dy))
-        xs = slice(max(0, -dx), min(nx, nx - dx)); xt = slice(max(0, dx), min(nx, nx + dx))
-        if bc_x == I.BC_PERIODIC or bc_y == I.BC_PERIODIC:
-            rolled = torch.roll(src, shifts=(-dy, -dx), dims=(0, 1))
-            okp = torch.ones_like(src)
-            if bc_y != I.BC_PERIODIC:
-                okp[:max(0, -dy)] = 0
-                if dy > 0:
-                    okp[ny - dy:] = 0
-            if bc_x != I.BC_PERIODIC:
-                okp[:, :max(0, -dx)] = 0
-                if dx > 0:
-                    okp[:, nx - dx:] = 0
-            sh, ok = rolled * okp, okp
-        else:
-            sh[ys, xs] = src[yt, xt]
-            ok[ys, xs] = 1.0
-        valid[d] = ok
-        lam[d] = torch.where(ok > 0, torch.log(torch.clamp(-sh, min=1e-30)), torch.zeros_like(sh))
-    return lam, valid
-
-
 class TrainingSet:
-    """Features and solver targets of many problems, resident on the GPU."""
+    """Solutions of many problems, resident on the GPU in compact form: each
+    problem's observations (cells, values, kappa: the network input is
+    rebuilt from them by gabp_warm_features when a batch is drawn) and its
+    FP32 posterior mean; for some problems also the log(-Lam) targets of the
+    precision outputs (gabp_log_precisions), whose edge masks are shared by
+    problems of one grid."""
 
     def __init__(self):
-        self.x: List[torch.Tensor] = []      # bf16 [ny, nx, 16]
-        self.mu: List[torch.Tensor] = []     # fp32 [ny, nx]
-        self.lam: List[torch.Tensor] = []    # fp32 [12, ny, nx]
-        self.valid: List[torch.Tensor] = []  # fp32 [12, ny, nx]
+        self.cells: List[torch.Tensor] = []    # int64 device
+        self.y: List[torch.Tensor] = []        # float64 device
+        self.kappa: List[float] = []
+        self.shape: List[tuple] = []           # (ny, nx)
+        self.mu: List[torch.Tensor] = []       # fp32 [ny, nx]
+        self.lam: List[Optional[torch.Tensor]] = []   # fp32 [12, ny, nx] or None
+        self.valid: Dict[tuple, torch.Tensor] = {}    # (ny, nx, bc_x, bc_y) -> [12, ny, nx]
+        self.key: List[tuple] = []
         self.iters: List[int] = []
 
     def __len__(self):
-        return len(self.x)
+        return len(self.mu)
+
+    def add(self, p: I.Problem, mu: torch.Tensor, lam: Optional[torch.Tensor],
+            valid: Optional[torch.Tensor], iters: int, device) -> None:
+        key = (p.ny, p.nx, p.bc_x, p.bc_y)
+        if valid is not None and key not in self.valid:
+            self.valid[key] = valid
+        self.cells.append(torch.as_tensor(np.asarray(p.cells), dtype=torch.int64).to(device))
+        self.y.append(torch.as_tensor(np.asarray(p.y), dtype=torch.float64).to(device))
+        self.kappa.append(float(p.kappa))
+        self.shape.append((p.ny, p.nx))
+        self.mu.append(mu.to(torch.float32).reshape(p.ny, p.nx))
+        self.lam.append(lam)
+        self.key.append(key)
+        self.iters.append(int(iters))
+
+    def features(self, k: int) -> torch.Tensor:
+        ny, nx = self.shape[k]
+        return G.gabp_warm_features(self.cells[k], self.y[k], nx, ny, self.kappa[k],
+                                    device=self.mu[k].device)
 
 
 def solve_training_set(problems: Sequence[I.Problem], max_iters: int = 300000,
                        rel_tol: float = 1e-6, device="cuda", log=print,
-                       multigrid: bool = False) -> TrainingSet:
+                       multigrid: bool = False, lam_targets: bool = True,
+                       ts: Optional[TrainingSet] = None) -> TrainingSet:
     """Solve the problems with the batched solver (multigrid: batched
     coarse-to-fine, the same fixed points at the same residual tolerance) and
-    keep features + targets."""
-    ts = TrainingSet()
+    keep the solutions."""
+    ts = TrainingSet() if ts is None else ts
     t0 = time.time()
     if multigrid:
         from . import multigrid as MG
@@ -197,14 +190,56 @@ def solve_training_set(problems: Sequence[I.Problem], max_iters: int = 300000,
         if sts[i] != G.GABP_OK:
             continue
         mean, _ = G.gabp_batch_posterior(b, i, want_var=False)
-        prec, _ = G.gabp_batch_get_messages(b, i)
-        lam, valid = sender_log_precisions(prec, p.bc_x, p.bc_y)
-        ts.x.append(G.gabp_warm_features(p.cells, p.y, p.nx, p.ny, p.kappa, device=device))
-        ts.mu.append(mean.to(torch.float32))
-        ts.lam.append(lam)
-        ts.valid.append(valid)
-        ts.iters.append(int(its[i]))
+        lam, valid = G.gabp_batch_log_precisions(b, i) if lam_targets else (None, None)
+        ts.add(p, mean, lam, valid, its[i], device)
     del b
+    torch.cuda.synchronize()
+    return ts
+
+
+def solve_training_set_warm(net: "WarmNet", problems: Sequence[I.Problem],
+                            max_iters: int = 300000, rel_tol: float = 1e-6, device="cuda",
+                            log=print, lam_targets: int = 0,
+                            freeze_tolerance: Optional[tuple] = (64, 1e-6),
+                            ts: Optional[TrainingSet] = None, deadline: Optional[float] = None,
+                            log_every: int = 256) -> TrainingSet:
+    """Solve each problem from the network's warm start (cold where that
+    start diverges) to the residual tolerance and keep the solutions: the
+    fixed point does not depend on the start, so a network can generate the
+    data its successor trains on.  The first `lam_targets` solutions keep
+    their precision targets.  Stops early at time.time() >= deadline."""
+    ts = TrainingSet() if ts is None else ts
+    t0 = time.time()
+    its_all = []
+    for k, p in enumerate(problems):
+        if deadline is not None and time.time() >= deadline:
+            log(f"[warm] generation deadline reached after {k} problems")
+            break
+        p.rel_tol = rel_tol
+        pred = predict(net, p, device)
+        ctx = G.gabp_create_problem(p, device=device)
+        G.gabp_warm_init(ctx, pred)
+        if freeze_tolerance is not None:
+            G.gabp_set_freeze_tolerance(ctx, *freeze_tolerance)
+        st, it, rel = G.gabp_solve(ctx, max_iters, p.damping, rel_tol, -10)
+        if st == G.GABP_E_DIVERGED:
+            G.gabp_destroy(ctx)
+            ctx = G.gabp_create_problem(p, device=device)
+            if freeze_tolerance is not None:
+                G.gabp_set_freeze_tolerance(ctx, *freeze_tolerance)
+            st, it, rel = G.gabp_solve(ctx, max_iters, p.damping, rel_tol, -10)
+        if st == G.GABP_OK:
+            mean, _ = G.gabp_posterior(ctx, want_var=False)
+            want = len(ts) < lam_targets
+            lam, valid = G.gabp_log_precisions(ctx) if want else (None, None)
+            if not want and (p.ny, p.nx, p.bc_x, p.bc_y) not in ts.valid:
+                _, valid = G.gabp_log_precisions(ctx)
+            ts.add(p, mean, lam, valid, it, device)
+            its_all.append(it)
+        G.gabp_destroy(ctx)
+        if (k + 1) % log_every == 0:
+            log(f"[warm] {k + 1} problems in {time.time() - t0:.1f}s, iterations median "
+                f"{int(np.median(its_all)) if its_all else -1}")
     torch.cuda.synchronize()
     return ts
 
@@ -212,22 +247,32 @@ def solve_training_set(problems: Sequence[I.Problem], max_iters: int = 300000,
 def train(net: WarmNet, ts: TrainingSet, steps: int, batch: int = 8, crop: int = 256,
           lr: float = 2e-3, lam_weight: float = 0.1, seed: int = 0, log=print,
           log_every: int = 100) -> List[float]:
-    """Adam on random crops of the training set; returns the loss history."""
+    """Adam on random crops of the training set; returns the loss history.
+    Crops of problems without precision targets carry no precision loss."""
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.time()
+    zeros = {}
     for s in range(steps):
         xs, mus, lams, vals = [], [], [], []
         for _ in range(batch):
             k = int(rng.integers(0, len(ts)))
-            ny, nx = ts.mu[k].shape
+            ny, nx = ts.shape[k]
             cy = int(rng.integers(0, ny - crop + 1)) if ny > crop else 0
             cx = int(rng.integers(0, nx - crop + 1)) if nx > crop else 0
             h, w = min(crop, ny), min(crop, nx)
-            xs.append(ts.x[k][cy:cy + h, cx:cx + w])
+            xs.append(ts.features(k)[cy:cy + h, cx:cx + w])
             mus.append(ts.mu[k][cy:cy + h, cx:cx + w])
-            lams.append(ts.lam[k][:, cy:cy + h, cx:cx + w])
-            vals.append(ts.valid[k][:, cy:cy + h, cx:cx + w])
+            if ts.lam[k] is not None:
+                lams.append(ts.lam[k][:, cy:cy + h, cx:cx + w])
+                vals.append(ts.valid[ts.key[k]][:, cy:cy + h, cx:cx + w])
+            else:
+                z = zeros.get((h, w))
+                if z is None:
+                    z = zeros[(h, w)] = torch.zeros((NDIR, h, w), dtype=torch.float32,
+                                                    device=ts.mu[k].device)
+                lams.append(z)
+                vals.append(z)
         x = torch.stack(xs).contiguous()
         mu = torch.stack(mus).contiguous()
         # direction-major targets [12, B*h*w] to match the kernel's layout

@@ -4,17 +4,21 @@
         --out paper_2404_12968_amd/weights/warm1024.npz --eval 6
 
 1. Draws `n-train` problems of the 1024 x 1024 warm-start workload (seeds
-   seed-base .. seed-base + n-1) and solves them to 1e-6 with the batched
-   solver.
+   seed-base .. seed-base + n-1) and solves them to 1e-6: with the batched
+   solver (cold, or --multigrid), or (--warm-gen) one by one from the warm
+   start of the network given by --init (the fixed points do not depend on
+   the start).  The solutions stay on the GPU in compact form (observations
+   and FP32 means; precision targets for the first --lam-targets).
 2. Trains the network (Adam, cosine schedule) on random 256 x 256 crops of
    those solutions.
 3. Solves `eval` held-out problems (seeds 100000 + k) cold and warm (network
-   inference included in the warm time, cold fallback active) and prints one
-   JSON summary line.
+   inference included in the warm time, cold fallback active, the same
+   freeze tolerance for both) and prints one JSON summary line.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -43,6 +47,12 @@ def main(argv=None):
                     help="continue from these weights (npz) instead of a fresh network")
     ap.add_argument("--multigrid", action="store_true",
                     help="solve the training problems by batched multigrid")
+    ap.add_argument("--warm-gen", action="store_true",
+                    help="solve the training problems from the --init network's warm start")
+    ap.add_argument("--lam-targets", type=int, default=1024,
+                    help="solutions that keep their precision targets")
+    ap.add_argument("--max-gen-seconds", type=float, default=None,
+                    help="stop generating training solutions after this long")
     ap.add_argument("--out", default=None)
     ap.add_argument("--summary", default=None)
     args = ap.parse_args(argv)
@@ -51,36 +61,62 @@ def main(argv=None):
         print(*a, flush=True)
 
     torch.cuda.set_device(0)
-    t0 = time.time()
-    probs = [I.warm1024(instance=args.seed_base + k, n=args.side) for k in range(args.n_train)]
-    log(f"[warm] generated {len(probs)} problems in {time.time() - t0:.1f}s")
-    chunk = 64
+    seeds = range(args.seed_base, args.seed_base + args.n_train)
+
+    def make(k):
+        p = I.warm1024(instance=k, n=args.side)
+        p.truth = None          # the solver's solution is the target
+        return p
+
     ts = Wm.TrainingSet()
-    for c0 in range(0, len(probs), chunk):
-        part = Wm.solve_training_set(probs[c0:c0 + chunk], log=log, multigrid=args.multigrid)
-        for f in ("x", "mu", "lam", "valid", "iters"):
-            getattr(ts, f).extend(getattr(part, f))
-    log(f"[warm] training set: {len(ts)} solutions, iterations median {int(np.median(ts.iters))}")
+    deadline = time.time() + args.max_gen_seconds if args.max_gen_seconds else None
+    t_gen = time.time()
+    if args.warm_gen:
+        if not args.init:
+            raise SystemExit("--warm-gen needs --init")
+        gen_net = Wm.WarmNet.load(args.init)
+        # problems are drawn on host threads while the GPU solves earlier ones
+        ex = cf.ThreadPoolExecutor(max_workers=4)
+        try:
+            Wm.solve_training_set_warm(gen_net, ex.map(make, seeds), log=log,
+                                       lam_targets=args.lam_targets, ts=ts, deadline=deadline)
+        finally:
+            ex.shutdown(wait=False, cancel_futures=True)
+        del gen_net
+    else:
+        chunk = 64
+        for c0 in range(0, len(seeds), chunk):
+            if deadline is not None and time.time() >= deadline:
+                log(f"[warm] generation deadline reached after {c0} problems")
+                break
+            Wm.solve_training_set([make(k) for k in seeds[c0:c0 + chunk]], log=log,
+                                  multigrid=args.multigrid,
+                                  lam_targets=len(ts) < args.lam_targets, ts=ts)
+    gen_s = time.time() - t_gen
+    log(f"[warm] training set: {len(ts)} solutions in {gen_s:.1f}s, iterations median "
+        f"{int(np.median(ts.iters))}, {sum(l is not None for l in ts.lam)} with precision targets")
     net = Wm.WarmNet.load(args.init) if args.init else Wm.WarmNet(seed=0)
     t1 = time.time()
     hist = Wm.train(net, ts, args.steps, batch=args.batch, crop=args.crop, lr=args.lr,
                     lam_weight=args.lam_weight, log=log, log_every=200)
     train_s = time.time() - t1
+    n_solutions = len(ts)
     del ts
     torch.cuda.empty_cache()
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-        net.save(args.out, meta={"n_train": args.n_train, "steps": args.steps,
+        net.save(args.out, meta={"n_train": n_solutions, "steps": args.steps,
                                  "batch": args.batch, "crop": args.crop, "lr": args.lr,
                                  "side": args.side, "seed_base": args.seed_base,
                                  "init": args.init or "", "final_loss": hist[-1]})
         log(f"[warm] saved {args.out}")
     evals = []
+    ft = (64, 1e-6)
     for k in range(args.eval):
         p = I.warm1024(instance=100000 + k, n=args.side)
-        c = Wm.cold_solve(p)
-        w = Wm.warm_solve(net, p)
-        wm = Wm.warm_solve(net, p, use_precisions=False)
+        c = Wm.cold_solve(p, freeze_tolerance=ft)
+        w = Wm.warm_solve(net, p, freeze_tolerance=ft)
+        wm = Wm.warm_solve(net, p, use_precisions=False, freeze_tolerance=ft)
         evals.append({"instance": 100000 + k, "kappa": p.kappa, "coverage": p.coverage,
                       "cold_iters": c["iterations"], "cold_s": c["seconds"],
                       "warm_iters": w["iterations"], "warm_s": w["seconds"],
@@ -92,7 +128,8 @@ def main(argv=None):
             f" | mean-only {wm['iterations']} it")
     cold_t = sum(e["cold_s"] for e in evals)
     warm_t = sum(e["warm_s"] for e in evals)
-    summary = {"n_train": args.n_train, "seed_base": args.seed_base, "init": args.init,
+    summary = {"n_train": n_solutions, "seed_base": args.seed_base, "init": args.init,
+               "warm_gen": args.warm_gen, "generation_seconds": gen_s,
                "steps": args.steps, "train_seconds": train_s,
                "loss_first": hist[0], "loss_last": hist[-1], "eval": evals,
                "cold_seconds_total": cold_t, "warm_seconds_total": warm_t,

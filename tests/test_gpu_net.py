@@ -149,8 +149,7 @@ def test_warm_init_from_the_fixed_point_is_converged(G, bcx):
     st, it, rel = G.gabp_solve(ref, 200000, 0.5, 1e-12, 50)
     assert st == G.GABP_OK
     mean, _ = G.gabp_posterior(ref, want_var=False)
-    prec, _ = G.gabp_get_messages(ref)
-    lam, valid = warm.sender_log_precisions(prec, prob.bc_x, prob.bc_y)
+    lam, valid = G.gabp_log_precisions(ref)
     pred = torch.zeros((prob.ny, prob.nx, 16), dtype=torch.float32, device="cuda")
     pred[:, :, 0] = mean.float()
     pred[:, :, 1:13] = lam.permute(1, 2, 0)
@@ -161,6 +160,47 @@ def test_warm_init_from_the_fixed_point_is_converged(G, bcx):
     G.gabp_iterate(ctx, 20, 0.5)
     m2, _ = G.gabp_posterior(ctx, want_var=False)
     assert float((m2 - mean).norm() / mean.norm()) < 1e-5
+
+
+DIRS = [(1, 0), (-1, 0), (0, 1), (0, -1), (2, 0), (-2, 0), (0, 2), (0, -2),
+        (1, 1), (-1, -1), (1, -1), (-1, 1)]
+
+
+@pytest.mark.parametrize("alpha,bcx,bcy", [(2, I.BC_NEUMANN, I.BC_NEUMANN),
+                                          (2, I.BC_PERIODIC, I.BC_NEUMANN),
+                                          (1, I.BC_DIRICHLET, I.BC_PERIODIC)])
+def test_log_precision_targets(G, alpha, bcx, bcy):
+    """gabp_log_precisions against the checkpoint layout: the message from
+    (x, y) to its neighbour in direction d is the receiver slot d ^ 1 at the
+    neighbour (include/gabp.h), so lam[d][y][x] = log(-prec[d ^ 1][y + dy][x +
+    dx]) where that neighbour exists (wrapped on periodic axes), 0 and invalid
+    elsewhere and for d >= deg."""
+    prob = I.small_lattice(70, 33, alpha, bc_x=bcx, bc_y=bcy, kappa=0.2, frac=0.1, sigma=0.1,
+                           seed=9, dtype="f32")
+    ctx = G.gabp_create_problem(prob)
+    G.gabp_iterate(ctx, 30, 0.5)
+    lam, valid = G.gabp_log_precisions(ctx)
+    prec, _ = G.gabp_get_messages(ctx)
+    lam, valid, prec = lam.cpu().numpy(), valid.cpu().numpy(), prec.cpu().double().numpy()
+    deg = prec.shape[0]
+    ny, nx = prob.ny, prob.nx
+    for d in range(12):
+        for y in range(ny):
+            for x in range(nx):
+                ok = d < deg
+                if ok:
+                    xn, yn = x + DIRS[d][0], y + DIRS[d][1]
+                    if bcx == I.BC_PERIODIC:
+                        xn %= nx
+                    if bcy == I.BC_PERIODIC:
+                        yn %= ny
+                    ok = 0 <= xn < nx and 0 <= yn < ny
+                if ok:
+                    want = np.log(max(-prec[d ^ 1, yn, xn], 1e-30))
+                    assert valid[d, y, x] == 1.0
+                    assert abs(lam[d, y, x] - want) <= 1e-6 * max(1.0, abs(want)), (d, y, x)
+                else:
+                    assert valid[d, y, x] == 0.0 and lam[d, y, x] == 0.0, (d, y, x)
 
 
 def test_training_reduces_loss(G):
