@@ -244,6 +244,45 @@ def solve_training_set_warm(net: "WarmNet", problems: Sequence[I.Problem],
     return ts
 
 
+def solve_training_set_multigrid(problems, rel_tol: float = 1e-6, device="cuda", log=print,
+                                 lam_targets: int = 0,
+                                 freeze_tolerance: Optional[tuple] = (64, 1e-6),
+                                 ts: Optional[TrainingSet] = None,
+                                 deadline: Optional[float] = None,
+                                 log_every: int = 128) -> TrainingSet:
+    """Solve each problem by multigrid (coarse levels carry the smooth modes
+    that single-grid iterations leave far from converged at a given
+    residual) and keep the solutions; problems may be an iterator.  The first
+    `lam_targets` solutions keep their precision targets.  Stops early at
+    time.time() >= deadline."""
+    from . import multigrid as MG
+    ts = TrainingSet() if ts is None else ts
+    t0 = time.time()
+    its_all = []
+    for k, p in enumerate(problems):
+        if deadline is not None and time.time() >= deadline:
+            log(f"[warm] generation deadline reached after {k} problems")
+            break
+        p.rel_tol = rel_tol
+        r = MG.multigrid_solve(p, keep_context=True, freeze_tolerance=freeze_tolerance,
+                               device=device)
+        ctx = r["ctx"]
+        if r["status"] == G.GABP_OK:
+            mean, _ = G.gabp_posterior(ctx, want_var=False)
+            want = len(ts) < lam_targets
+            lam, valid = G.gabp_log_precisions(ctx) if want else (None, None)
+            if not want and (p.ny, p.nx, p.bc_x, p.bc_y) not in ts.valid:
+                _, valid = G.gabp_log_precisions(ctx)
+            ts.add(p, mean, lam, valid, r["iterations"], device)
+            its_all.append(r["iterations"])
+        G.gabp_destroy(ctx)
+        if (k + 1) % log_every == 0:
+            log(f"[warm] {k + 1} problems in {time.time() - t0:.1f}s, fine iterations median "
+                f"{int(np.median(its_all)) if its_all else -1}")
+    torch.cuda.synchronize()
+    return ts
+
+
 def train(net: WarmNet, ts: TrainingSet, steps: int, batch: int = 8, crop: int = 256,
           lr: float = 2e-3, lam_weight: float = 0.1, seed: int = 0, log=print,
           log_every: int = 100) -> List[float]:

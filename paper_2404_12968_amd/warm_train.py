@@ -49,6 +49,9 @@ def main(argv=None):
                     help="solve the training problems by batched multigrid")
     ap.add_argument("--warm-gen", action="store_true",
                     help="solve the training problems from the --init network's warm start")
+    ap.add_argument("--stream-multigrid", action="store_true",
+                    help="solve the training problems one by one by multigrid while host "
+                         "threads draw the next ones")
     ap.add_argument("--lam-targets", type=int, default=1024,
                     help="solutions that keep their precision targets")
     ap.add_argument("--max-gen-seconds", type=float, default=None,
@@ -71,7 +74,15 @@ def main(argv=None):
     ts = Wm.TrainingSet()
     deadline = time.time() + args.max_gen_seconds if args.max_gen_seconds else None
     t_gen = time.time()
-    if args.warm_gen:
+    if args.stream_multigrid:
+        ex = cf.ThreadPoolExecutor(max_workers=4)
+        try:
+            Wm.solve_training_set_multigrid(ex.map(make, seeds), log=log,
+                                            lam_targets=args.lam_targets, ts=ts,
+                                            deadline=deadline)
+        finally:
+            ex.shutdown(wait=False, cancel_futures=True)
+    elif args.warm_gen:
         if not args.init:
             raise SystemExit("--warm-gen needs --init")
         gen_net = Wm.WarmNet.load(args.init)
@@ -129,7 +140,9 @@ def main(argv=None):
     cold_t = sum(e["cold_s"] for e in evals)
     warm_t = sum(e["warm_s"] for e in evals)
     summary = {"n_train": n_solutions, "seed_base": args.seed_base, "init": args.init,
-               "warm_gen": args.warm_gen, "generation_seconds": gen_s,
+               "generation": ("multigrid" if args.stream_multigrid or args.multigrid else
+                              "warm start" if args.warm_gen else "batched cold"),
+               "generation_seconds": gen_s,
                "steps": args.steps, "train_seconds": train_s,
                "loss_first": hist[0], "loss_last": hist[-1], "eval": evals,
                "cold_seconds_total": cold_t, "warm_seconds_total": warm_t,

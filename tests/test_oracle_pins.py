@@ -528,6 +528,34 @@ def test_table2_convergence_pattern(oracle_mod):
             assert got == want, (eta_s, c, got)
 
 
+def test_table2_ordering_of_c_on_the_table1_generator(oracle_mod):
+    """Table 2's grid search at learning rate 0.6 on the Table 1 generator's
+    128^2 problem (5 % observed): c = 1 and c = 5 diverge (cavity or residual
+    blow-up), the others converge, and the RMSE ratio to the exact posterior
+    after 4000 iterations orders the constants as the paper's row does
+    (c = 10 and 20 best, then -10, -2, -1)."""
+    p = I.table1(128, 0.05, 0)
+    A, b = oracle_mod.posterior_system(p)
+    exact = oracle_mod.direct_solve(A, b)
+    truth = p.truth.ravel()
+    r_exact = np.sqrt(np.mean((exact - truth) ** 2))
+    ratio = {}
+    for c in (-10, -2, -1, 1, 5, 10, 20):
+        og = oracle_mod.OracleGaBP(oracle_mod.FactorGraph(A, b), float(c))
+        og.iterate(50, 0.6)
+        r0 = og.residual()[0]
+        st = og.iterate(3950, 0.6)
+        mu, _ = og.posterior()
+        fin = np.all(np.isfinite(mu))
+        if st == oracle_mod.STATUS_DIVERGED or not fin or og.residual()[0] > 1e3 * r0:
+            ratio[c] = None
+        else:
+            ratio[c] = np.sqrt(np.mean((mu - truth) ** 2)) / r_exact
+    assert ratio[1] is None and ratio[5] is None
+    assert all(ratio[c] is not None for c in (-10, -2, -1, 10, 20))
+    assert max(ratio[10], ratio[20]) < ratio[-10] < ratio[-2] < ratio[-1]
+
+
 # --------------------------------------------------------------------------
 # determinism and the early-stop statistic
 # --------------------------------------------------------------------------
