@@ -363,3 +363,147 @@ def workload(name: str, instance: int = 0):
           "batch256": lambda instance=0: batch256(), "warm1024": warm1024,
           "table1": lambda instance=0: table1(instance=instance), "global32k": global32k}[name]
     return fn(instance)
+
+
+# --------------------------------------------------------------------------
+# space-time workloads (the paper's spatio-temporal extension, Appendix
+# "Extension to Spatiotemporal Systems")
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SpaceTimeProblem:
+    """One space-time assimilation instance: nt slices of an nx x ny grid.
+
+    Prior: the stochastic heat equation du/dt = nu Lap u + sigma_u W on a grid
+    of spacing h, Crank-Nicolson steps of length dt, initial condition with
+    precision (dt h^2 / sigma_u^2) (a0 (kappa^2 I - Lap_h))^2 and zero mean.
+    Cells are ``n * nx * ny + y * nx + x`` for slice n; ``sigma`` is the
+    observation noise standard deviation, ``var`` (optional) overrides it.
+    """
+
+    name: str
+    nx: int
+    ny: int
+    nt: int
+    bc_x: int
+    bc_y: int
+    dt: float
+    h: float
+    nu: float
+    kappa: float
+    a0: float
+    sigma_u: float
+    c: float
+    sigma: float
+    cells: np.ndarray
+    y: np.ndarray
+    var: Optional[np.ndarray] = None
+    truth: Optional[np.ndarray] = None
+    dtype: str = "f32"
+    damping: float = 0.5
+    rel_tol: float = 1e-6
+    max_iters: int = 100000
+    check_every: int = 10
+    seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nt
+
+    @property
+    def coverage(self) -> float:
+        return np.unique(self.cells).size / float(self.n)
+
+
+def heat_field_neumann(nx: int, ny: int, nt: int, dt: float, h: float, nu: float,
+                       kappa: float, a0: float, sigma_u: float,
+                       rng: np.random.Generator) -> np.ndarray:
+    """A sample of the discretised stochastic heat equation on a zero-flux
+    grid, shape (nt, ny, nx): u^0 solves a0 (kappa^2 I - Lap_h) u^0 = s z^0 and
+    (I/dt - nu/2 Lap_h) u^{n+1} = (I/dt + nu/2 Lap_h) u^n + s z^{n+1} with
+    s = sigma_u / sqrt(dt h^2) and z white noise.  The orthonormal DCT-II
+    diagonalises the zero-flux Laplacian (eigenvalues -(4/h^2)(sin^2(pi j /
+    (2 nx)) + sin^2(pi k / (2 ny)))) and maps white noise to white noise, so
+    every step is a division per mode.  Draws the truth only; neither solver
+    calls it."""
+    import scipy.fft as sf
+    ex = 4.0 / (h * h) * np.sin(np.pi * np.arange(nx) / (2.0 * nx)) ** 2
+    ey = 4.0 / (h * h) * np.sin(np.pi * np.arange(ny) / (2.0 * ny)) ** 2
+    g = ey[:, None] + ex[None, :]                      # eigenvalues of -Lap_h
+    s = sigma_u / np.sqrt(dt * h * h)
+    ua = s * rng.standard_normal((ny, nx)) / (a0 * (kappa * kappa + g))
+    a = 1.0 / dt + 0.5 * nu * g
+    b = 1.0 / dt - 0.5 * nu * g
+    out = np.empty((nt, ny, nx))
+    for k in range(nt):
+        if k > 0:
+            ua = (b * ua + s * rng.standard_normal((ny, nx))) / a
+        out[k] = sf.idctn(ua, type=2, norm="ortho")
+    return out
+
+
+def spacetime_track_cells(nx: int, ny: int, nt: int, n_tracks: int, run: int,
+                          drift: int, rng: np.random.Generator) -> np.ndarray:
+    """Ground tracks that move between slices: track j (slope +-1, offset x0_j)
+    sits at offset x0_j + drift_j * n in slice n, drift_j uniform on
+    {-drift..drift}; each slice's cells as in ``track_cells``.  Sorted,
+    distinct space-time cells."""
+    ys = np.arange(ny, dtype=np.int64)
+    out = []
+    for _ in range(n_tracks):
+        s = 1 if rng.integers(0, 2) == 1 else -1
+        x0 = int(rng.integers(0, nx))
+        v = int(rng.integers(-drift, drift + 1))
+        for k in range(nt):
+            start = x0 + v * k + s * ys - run // 2
+            xs = (start[:, None] + np.arange(run, dtype=np.int64)[None, :]) % nx
+            out.append(k * nx * ny + (ys[:, None] * nx + xs).ravel())
+    if not out:
+        return np.zeros(0, dtype=np.int64)
+    return np.unique(np.concatenate(out))
+
+
+# heat-equation prior of the space-time workloads: one grid unit, unit time
+# step, diffusion number nu dt / h^2 = 1/4, Matern-type initial field (kappa
+# 0.1), process noise 0.1; re-weighting and damping chosen by the oracle's
+# c x eta sweep on small grids.
+SPACETIME_PRIOR = dict(dt=1.0, h=1.0, nu=0.25, kappa=0.1, a0=1.0, sigma_u=0.1)
+SPACETIME_C = 3.0
+SPACETIME_ETA = 0.4
+
+
+def spacetime(instance: int = 0, nx: int = 512, ny: int = 512, nt: int = 64,
+              n_tracks: int = 4, run: int = 3, sigma: float = 0.05,
+              dtype: str = "f32", **prior) -> SpaceTimeProblem:
+    """nt slices of an nx x ny zero-flux grid under the heat-equation prior,
+    observed along ``n_tracks`` drifting ground tracks of ``run`` cells per
+    slice (about 2 % of the space-time cells at 512^2 x 64), noise sigma."""
+    pr = dict(SPACETIME_PRIOR)
+    pr.update(prior)
+    rng = np.random.default_rng([1000 * 8 + instance, nx, ny, nt])
+    truth = heat_field_neumann(nx, ny, nt, pr["dt"], pr["h"], pr["nu"], pr["kappa"], pr["a0"],
+                               pr["sigma_u"], rng)
+    cells = spacetime_track_cells(nx, ny, nt, n_tracks, run, 3, rng)
+    y = observe(truth, cells, sigma, rng)
+    return SpaceTimeProblem(f"spacetime{nx}x{ny}x{nt}[{instance}]", nx, ny, nt, BC_NEUMANN,
+                            BC_NEUMANN, c=SPACETIME_C, sigma=sigma, cells=cells, y=y,
+                            truth=truth, dtype=dtype, damping=SPACETIME_ETA,
+                            seed=8000 + instance, **pr)
+
+
+def small_spacetime(nx: int, ny: int, nt: int, *, bc_x: int = BC_NEUMANN,
+                    bc_y: int = BC_NEUMANN, frac: float = 0.05, sigma: float = 0.1,
+                    seed: int = 0, dtype: str = "f64", c: float = SPACETIME_C,
+                    damping: float = SPACETIME_ETA, **prior) -> SpaceTimeProblem:
+    """Generic small space-time problem for tests: a plane-wave truth per slice,
+    uniformly random observed space-time cells."""
+    pr = dict(SPACETIME_PRIOR)
+    pr.update(prior)
+    rng = np.random.default_rng([seed, nx, ny, nt])
+    truth = np.stack([fourier_modes_field(nx, ny, rng, n_modes=8, max_freq=3)
+                      for _ in range(nt)])
+    cells = uniform_cells(nx * ny * nt, frac, rng)
+    y = observe(truth, cells, sigma, rng)
+    return SpaceTimeProblem(f"small_st{nx}x{ny}x{nt}", nx, ny, nt, bc_x, bc_y, c=c,
+                            sigma=sigma, cells=cells, y=y, truth=truth, dtype=dtype,
+                            damping=damping, seed=seed, **pr)
