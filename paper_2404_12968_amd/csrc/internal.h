@@ -60,6 +60,13 @@ hipError_t launch_resid(const Lattice &L, const double *mu, const double *adiag6
                         hipStream_t s);
 hipError_t launch_abs_change(int dtype, const void *a, const void *b, int64_t n,
                              double *partials, int npart, double *out, hipStream_t s);
+// Deterministic fold of point observations into FP64 node terms (obs.hip):
+// p[i] += sum 1/s_k^2 and h[i] += sum y_k/s_k^2 over the observations of
+// cell c, i = (c / nx) * pitch + c % nx, summed in input order.  Synchronises
+// the stream (temporary sort buffers are freed before it returns).
+hipError_t launch_obs_fold(int64_t n, const int64_t *cell, const double *y, const double *var,
+                           double sigma2, int64_t ncells, int32_t nx, int32_t pitch,
+                           double *p_plane, double *h_plane, uint32_t *err_flag, hipStream_t s);
 hipError_t launch_setup(int dtype, const Lattice &L, int64_t nobs, const int64_t *cell,
                         const double *y, const double *var, double sigma2, double *adiag64,
                         double *b64, const double *prior_mean, void *adiag_w, void *b_w,

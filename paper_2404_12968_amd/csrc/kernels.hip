@@ -229,37 +229,11 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ parti
 }
 
 // --------------------------------------------------------------------------
-// Problem setup (Section "Including Observations"): fold every observation
-// into its cell's node terms, p_i += 1/s^2 and h_i += y/s^2, accumulated in
-// the (zeroed) FP64 diagonal and information planes.  Out-of-range cells and
-// non-finite or non-positive inputs set err_flag and are skipped.
-// --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_obs_scatter(Lattice L, int64_t n,
-                                                     const int64_t *__restrict__ cell,
-                                                     const double *__restrict__ yv,
-                                                     const double *__restrict__ var,
-                                                     double sigma2, double *__restrict__ adiag64,
-                                                     double *__restrict__ b64,
-                                                     uint32_t *__restrict__ err_flag) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    const int64_t c = cell[k];
-    const double s2 = var ? var[k] : sigma2;
-    const double y = yv[k];
-    const int64_t N = (int64_t)L.nx * L.ny;
-    if (c < 0 || c >= N || !(s2 > 0.0) || !isfinite(s2) || !isfinite(y)) {
-        *err_flag = 1u;
-        return;
-    }
-    const int64_t x = c % L.nx, row = c / L.nx;
-    const int64_t i = row * L.pitch + x;
-    const double w = 1.0 / s2;
-    atomicAdd(&adiag64[i], w);
-    atomicAdd(&b64[i], w * y);
-}
-
-// A_ii = Q_ii + p_i in FP64, b_i (+ (Q f_b)_i for a prior mean f_b), and the
-// copies in message precision that the iteration reads.
+// Problem setup (Section "Including Observations"): launch_obs_fold
+// (obs.hip, deterministic) folds the observations into adiag64 (p_i) and b64
+// (h_i); then k_node_init forms A_ii = Q_ii + p_i in FP64, b_i (+ (Q f_b)_i
+// for a prior mean f_b), and the copies in message precision that the
+// iteration reads.
 template <typename T>
 __global__ __launch_bounds__(256) void k_node_init(Lattice L, double *__restrict__ adiag64,
                                                    double *__restrict__ b64,
@@ -532,9 +506,11 @@ hipError_t launch_setup(int dtype, const Lattice &L, int64_t nobs, const int64_t
                         const double *y, const double *var, double sigma2, double *adiag64,
                         double *b64, const double *prior_mean, void *adiag_w, void *b_w,
                         uint32_t *err_flag, hipStream_t s) {
-    if (nobs > 0)
-        hipLaunchKernelGGL(k_obs_scatter, dim3((unsigned)((nobs + 255) / 256)), dim3(256), 0, s, L,
-                           nobs, cell, y, var, sigma2, adiag64, b64, err_flag);
+    if (nobs > 0) {
+        const hipError_t e = launch_obs_fold(nobs, cell, y, var, sigma2, (int64_t)L.nx * L.ny, L.nx,
+                                             L.pitch, adiag64, b64, err_flag, s);
+        if (e != hipSuccess) return e;
+    }
     dim3 grid(tiles_of(L)), block(256);
     if (dtype == 0)
         hipLaunchKernelGGL((k_node_init<float>), grid, block, 0, s, L, adiag64, b64, prior_mean,
