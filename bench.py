@@ -232,6 +232,116 @@ def copy_ceiling_gbps(torch, dev, reps=10):
     return 2 * 4 * n / (ms * 1e-3) / 1e9
 
 
+def st_edge_count(prob):
+    """Directed edges of the space-time graph (38 directions, include/gabp_st.h)."""
+    from paper_2404_12968_amd.inputs import BC_PERIODIC
+    lat = [(1, 0), (-1, 0), (0, 1), (0, -1), (2, 0), (-2, 0), (0, 2), (0, -2),
+           (1, 1), (-1, -1), (1, -1), (-1, 1)]
+    dirs = [(dx, dy, 0) for dx, dy in lat]
+    for ox, oy in [(0, 0)] + lat:
+        dirs += [(ox, oy, 1), (-ox, -oy, -1)]
+    total = 0
+    for dx, dy, dt in dirs:
+        cx = prob.nx if prob.bc_x == BC_PERIODIC else max(0, prob.nx - abs(dx))
+        cy = prob.ny if prob.bc_y == BC_PERIODIC else max(0, prob.ny - abs(dy))
+        total += cx * cy * max(0, prob.nt - abs(dt))
+    return total
+
+
+def bench_spacetime(G, I, torch, args):
+    """The space-time solver (heat-equation GMRF of the paper's
+    spatio-temporal extension) on 64 slices of a 512 x 512 zero-flux grid,
+    drifting satellite tracks (~2.3 % of the space-time cells), FP32
+    messages: steps of ITERS_PER_STEP iterations timed with HIP events on the
+    context's stream, then the FP64 residual.  Algorithmic bytes per
+    iteration: both components of every directed message read and written
+    once (16 B per edge) and the two node terms (8 B per node).  CPU
+    baseline: the FP64 oracle iterating on a 128 x 128 x 16 problem of the
+    same generator."""
+    prob = I.spacetime(nx=args.st_nx, ny=args.st_ny, nt=args.st_nt)
+    E = st_edge_count(prob)
+    N = prob.n
+    alg = 16 * E + 8 * N
+    progress(f"space-time {prob.nx}x{prob.ny}x{prob.nt}: {E} directed edges")
+    ctx = G.gabp_st_create_problem(prob)
+    stream = ctx.stream
+
+    def event_ms(fn, reps):
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in ev], time.perf_counter() - t0
+
+    step = lambda: G.gabp_st_iterate(ctx, ITERS_PER_STEP, prob.damping)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    ms, wall = event_ms(step, args.steps)
+    iter_ms = sum(ms) / (len(ms) * ITERS_PER_STEP)
+    rel, _ = G.gabp_st_residual(ctx)
+    its = G.gabp_st_iteration_count(ctx)[0]
+    value = E * args.steps * ITERS_PER_STEP / wall
+    achieved = alg / (iter_ms * 1e-3) / 1e9
+    out = {"metric": "edge-message updates/s (space-time GMRF)", "value": value,
+           "unit": "edge-message updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{prob.name}: heat-equation prior (Crank-Nicolson, "
+                                  f"nu dt/h^2 = {prob.nu * prob.dt / prob.h ** 2:g}), "
+                                  f"{prob.nx}x{prob.ny} zero-flux grid x {prob.nt} slices, "
+                                  f"38-neighbour stencil, {prob.coverage * 100:.2f}% observed, "
+                                  f"c={prob.c}, damping={prob.damping}, FP32 messages",
+                      "nodes": N, "directed_edges": E, "iters_per_step": ITERS_PER_STEP,
+                      "parallelism": "single GPU"},
+           "iterations_run": its, "rel_residual_after": rel,
+           "roofline": {"bound": "hbm", "kernel": "k_iter (space-time)", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "iter_ms": iter_ms, "algorithmic_bytes_per_launch": alg,
+                        "traffic": None}}
+    if args.st_solve_tol > 0:
+        progress(f"space-time solve to {args.st_solve_tol:g}")
+        ctx2 = G.gabp_st_create_problem(prob)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, it, r = G.gabp_st_solve(ctx2, args.solve_max_iters, prob.damping, args.st_solve_tol,
+                                    100)
+        torch.cuda.synchronize()
+        out["time_to_tol"] = {"tol": args.st_solve_tol, "status": G.gabp_status_string(st),
+                              "iterations": it, "seconds": time.perf_counter() - t1,
+                              "rel_residual": r}
+        del ctx2
+    del ctx
+    if not args.no_cpu_baseline:
+        progress("space-time CPU baseline")
+        from oracle import oracle as O
+        from oracle import spacetime as S
+        small = I.spacetime(nx=128, ny=128, nt=16, dtype="f64")
+        A, b = S.posterior_system(small)
+        og = O.OracleGaBP(O.FactorGraph(A, b), small.c)
+        og.iterate(2, small.damping)
+        n_it = 0
+        t0 = time.perf_counter()
+        while True:
+            og.iterate(2, small.damping)
+            n_it += 2
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds and n_it >= 6:
+                break
+        out["cpu_baseline"] = {"value": og.g.nnz * n_it / el, "unit": "edge-message updates/s",
+                               "cores": O.max_threads(), "kind": "oracle",
+                               "sample": f"FP64 oracle on 128x128x16 of the same generator "
+                                         f"({og.g.nnz} directed edges), {n_it} iterations "
+                                         f"after 2 warm-up, {el:.1f} s"}
+    progress(f"space-time done: {value:.3e} edge-message updates/s, {achieved:.0f} GB/s")
+    return out
+
+
 def bench_warm(I, n, freeze=None, fp64_ref=True, tol=None):
     """Time to 1e-6 on held-out 1024^2 warm-start problems, cold vs the trained
     network's warm start (inference and the fallback probe included) vs
@@ -579,7 +689,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="global8192",
                     choices=["global8192", "tracks2048", "batch256", "table1", "table2",
-                             "global32k", "warmnet"])
+                             "global32k", "warmnet", "spacetime"])
+    ap.add_argument("--st-nx", type=int, default=512)
+    ap.add_argument("--st-ny", type=int, default=512)
+    ap.add_argument("--st-nt", type=int, default=64)
+    ap.add_argument("--st-solve-tol", type=float, default=0.0,
+                    help="spacetime: also solve a fresh context to this relative residual")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-solve", action="store_true",
@@ -655,8 +770,10 @@ def main(argv=None):
         print(json.dumps(bench_table2(G, I, torch, args)), flush=True)
         return 0
     if args.workload == "warmnet":
-        import numpy as np  # noqa: F401
         print(json.dumps(bench_warmnet(G, I, torch, args)), flush=True)
+        return 0
+    if args.workload == "spacetime":
+        print(json.dumps(bench_spacetime(G, I, torch, args)), flush=True)
         return 0
 
     prob = I.workload(args.workload)

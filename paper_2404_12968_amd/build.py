@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgabp.so")
-SOURCES = ["iter.hip", "kernels.hip", "capi.hip", "batch.hip", "net.hip"]
+SOURCES = ["iter.hip", "kernels.hip", "capi.hip", "batch.hip", "net.hip", "obs.hip",
+           "spacetime.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,883 @@
+// Space-time Gaussian belief propagation (include/gabp_st.h): the GMRF of
+// the stochastic heat equation discretised by Crank-Nicolson steps (paper:
+// Appendix "Extension to Spatiotemporal Systems"), solved by the damped,
+// re-weighted flooding iteration on its 38-neighbour graph.
+//
+// Precision closed form.  With G the graph Laplacian of the grid (unit
+// spacing; G_ii = g_i, the number of in-grid axis neighbours of i, G_ij = -1
+// for grid neighbours), Lap_h = -G/h^2 and every block of M is a polynomial
+// in G: A = a1 I + a2 G, B = a1 I - a2 G, L = l1 I + l2 G with a1 = 1/dt,
+// a2 = nu/(2 h^2), l1 = a0 kappa^2, l2 = a0/h^2.  The blocks of
+// Q = S M^T M (S = dt h^2 / sigma_u^2) are then polynomials p I + q G + r G^2:
+//     slice 0:        S (L^2 + B^2)      (S L^2 when there is one slice)
+//     slices 1..N-2:  S (A^2 + B^2)
+//     slice N-1:      S A^2
+//     between n, n+1: -S A B = -S (a1^2 I - a2^2 G^2)
+// and the entries of p I + q G + r G^2 follow from those of G and G^2 (the
+// grid graph is bipartite, so grid neighbours share no neighbour):
+//     (i, i):               p + q g_i + r (g_i^2 + g_i)
+//     one step:             -q - r (g_i + g_j)
+//     two steps on an axis: r
+//     diagonal:             2 r
+// The host folds the three products of each block into one (p, q, r) in
+// FP64; kernels evaluate the entries from it, the position and the slice.
+//
+// Storage.  Sender-indexed SoA planes as in the lattice kernels: plane d at
+// node i holds the message from i to i + off_d (d = 0..37, opposite d ^ 1),
+// precisions in planes 0..37 and information in planes 38..75.  A node's
+// plane index is n * slice + y * pitch + x with slice = pitch * ny.
+//
+// Launch shape.  A workgroup of 64 x 4 threads owns one 64 x 4 tile of a
+// band of kChunk consecutive slices and walks them in order, so the
+// messages a slice reads from its successor (and writes for it) are touched
+// again by the same workgroup one step later, while they sit in L2.
+// Workgroups are ordered tile-row-major within a band and band by band, and
+// remapped so that each XCD runs a contiguous range: vertically adjacent
+// tiles, which share their two-row halos, run side by side on one L2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gabp_st.h"
+#include "internal.h"
+#include "lattice.h"
+#include "numerics.h"
+
+#pragma clang fp contract(off)
+
+namespace gabp {
+namespace st {
+
+constexpr int kDeg = 38;
+constexpr int kChunk = 8;           // slices per workgroup in the iteration kernel
+constexpr int kPartials = 2048;     // workgroups of the residual reduction
+
+// Direction tables: d < 12 lie in the slice (the lattice directions of
+// lattice.h); d = 12 + 2k is (o_k, +1), d = 13 + 2k is (-o_k, -1), with
+// o_0 = (0, 0) and o_k the lattice direction k - 1.
+__host__ __device__ constexpr int cross_k(int d) { return (d - 12) >> 1; }
+__host__ __device__ constexpr int sdx(int d) {
+    return d < 12 ? dir_dx(d)
+                  : cross_k(d) == 0 ? 0 : ((d & 1) ? -dir_dx(cross_k(d) - 1) : dir_dx(cross_k(d) - 1));
+}
+__host__ __device__ constexpr int sdy(int d) {
+    return d < 12 ? dir_dy(d)
+                  : cross_k(d) == 0 ? 0 : ((d & 1) ? -dir_dy(cross_k(d) - 1) : dir_dy(cross_k(d) - 1));
+}
+__host__ __device__ constexpr int sdt(int d) { return d < 12 ? 0 : ((d & 1) ? -1 : 1); }
+// spatial relation of direction d: 0 same position, 1 one step, 2 two steps
+// along an axis, 3 diagonal
+__host__ __device__ constexpr int scls(int d) {
+    return d < 12 ? (d < 4 ? 1 : d < 8 ? 2 : 3)
+                  : cross_k(d) == 0 ? 0 : (cross_k(d) - 1 < 4 ? 1 : cross_k(d) - 1 < 8 ? 2 : 3);
+}
+
+struct Grid {
+    int32_t nx, ny, nt, pitch;
+    int32_t bcx, bcy, tiles_x, tiles_y;
+    int32_t chunks;             // bands of kChunk slices
+    int64_t slice;              // elements between slices (pitch * ny)
+    int64_t plane;              // elements between planes
+    double blk[4][3];           // (p, q, r) of blocks: slice 0, middle, last, coupling
+    double lsq[3];              // (p, q, r) of S L^2, the initial condition's precision
+    double c, inv_c;
+};
+
+__device__ __forceinline__ int axis_g(int v, int n, int bc) {
+    return bc == BC_PERIODIC ? 2 : (int)(v > 0) + (int)(v < n - 1);
+}
+
+__device__ __forceinline__ int slice_kind(const Grid &G, int t) {
+    return t == 0 ? 0 : (t == G.nt - 1 ? 2 : 1);
+}
+
+// Entry of p I + q G + r G^2 for a relation class (g_j only for one step).
+template <typename T>
+__device__ __forceinline__ T coef(const double *pqr, int cls, T gi, T gj) {
+    const T p = (T)pqr[0], q = (T)pqr[1], r = (T)pqr[2];
+    if (cls == 0) return p + q * gi + r * (gi * gi + gi);
+    if (cls == 1) return -q - r * (gi + gj);
+    if (cls == 2) return r;
+    return r + r;
+}
+
+// Neighbour of (x, y, t) in direction d: wraps periodic axes; false when it
+// lies outside the grid.
+__device__ __forceinline__ bool nbr(const Grid &G, int x, int y, int t, int d, int &xn, int &yn,
+                                    int &tn) {
+    xn = x + sdx(d);
+    yn = y + sdy(d);
+    tn = t + sdt(d);
+    if ((unsigned)tn >= (unsigned)G.nt) return false;
+    if (G.bcx == BC_PERIODIC) {
+        xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+    } else if ((unsigned)xn >= (unsigned)G.nx) {
+        return false;
+    }
+    if (G.bcy == BC_PERIODIC) {
+        yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
+    } else if ((unsigned)yn >= (unsigned)G.ny) {
+        return false;
+    }
+    return true;
+}
+
+// Q_ij / c for direction d of node (x, y, t) whose neighbour (xn, yn) exists.
+template <typename T>
+__device__ __forceinline__ T q_over_c(const Grid &G, int d, int kind, T gi, int xn, int yn) {
+    const double *pqr = d < 12 ? G.blk[kind] : G.blk[3];
+    const int cls = scls(d);
+    T gj = (T)0;
+    if (cls == 1) gj = (T)(axis_g(xn, G.nx, G.bcx) + axis_g(yn, G.ny, G.bcy));
+    return coef<T>(pqr, cls, gi, gj) * (T)G.inv_c;
+}
+
+// --------------------------------------------------------------------------
+// One flooding iteration of node (x, y, t) (as the lattice kernels):
+//   Lam_i = A_ii + c sum_k Lam_{k->i},  th_i = b_i + c sum_k th_{k->i}
+//   for each neighbour j: Lam_c = Lam_i - Lam_{j->i}, th_c = th_i - th_{j->i},
+//   g = -(Q_ij/c)/Lam_c, new (g Q_ij/c, g th_c), damped with the previous
+//   outgoing message (Appendix "Re-weighted message updates"; Section
+//   "Update Damping").  INTERIOR: every neighbour exists (radius-2 spatial
+//   halo inside the grid, a slice on either side).
+// --------------------------------------------------------------------------
+template <typename T, bool INTERIOR>
+__device__ __forceinline__ void iter_node(const Grid &G, const T *__restrict__ m_in,
+                                          T *__restrict__ m_out, const T *__restrict__ aw,
+                                          const T *__restrict__ bw, T eta, bool &bad, int x,
+                                          int y, int t) {
+    const uint32_t i = (uint32_t)((int64_t)t * G.slice + (int64_t)y * G.pitch + x);
+    T lin[kDeg], tin[kDeg];
+    bool ok[kDeg];
+#pragma unroll
+    for (int d = 0; d < kDeg; ++d) {
+        int xn, yn, tn;
+        if (INTERIOR) {
+            xn = x + sdx(d);
+            yn = y + sdy(d);
+            tn = t + sdt(d);
+            ok[d] = true;
+        } else {
+            ok[d] = nbr(G, x, y, t, d, xn, yn, tn);
+            if (!ok[d]) {
+                xn = x;
+                yn = y;
+                tn = t;
+            }
+        }
+        const uint32_t j = (uint32_t)((int64_t)tn * G.slice + (int64_t)yn * G.pitch + xn);
+        lin[d] = (m_in + (size_t)(d ^ 1) * G.plane)[j];
+        tin[d] = (m_in + (size_t)(kDeg + (d ^ 1)) * G.plane)[j];
+    }
+    const T a = aw[i], b = bw[i];
+    if (!INTERIOR) {
+#pragma unroll
+        for (int d = 0; d < kDeg; ++d) {
+            lin[d] = ok[d] ? lin[d] : (T)0;
+            tin[d] = ok[d] ? tin[d] : (T)0;
+        }
+    }
+    T sl = 0, st = 0;
+#pragma unroll
+    for (int d = 0; d < kDeg; ++d) {
+        sl += lin[d];
+        st += tin[d];
+    }
+    const T c = (T)G.c, keep = (T)1 - eta;
+    const T bl = fmadd(c, sl, a);
+    const T bt = fmadd(c, st, b);
+    const int kind = INTERIOR ? 1 : slice_kind(G, t);
+    const T gi = (T)(axis_g(x, G.nx, G.bcx) + axis_g(y, G.ny, G.bcy));
+#pragma unroll
+    for (int d = 0; d < kDeg; ++d) {
+        if (!INTERIOR && !ok[d]) continue;
+        int xn = x + sdx(d), yn = y + sdy(d);
+        if (!INTERIOR) {
+            if (G.bcx == BC_PERIODIC) xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+            if (G.bcy == BC_PERIODIC) yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
+        }
+        const T q = q_over_c<T>(G, d, kind, gi, xn, yn);
+        const T lc = bl - lin[d];
+        const T tc = bt - tin[d];
+        const T g = edge_gain(q, lc);
+        const T ol = (m_in + (size_t)d * G.plane)[i];
+        const T ot = (m_in + (size_t)(kDeg + d) * G.plane)[i];
+        const T dl = fmadd(eta, g * q, keep * ol);
+        const T dt = fmadd(eta, g * tc, keep * ot);
+        bad |= !(lc > (T)0) || !isfinite(dl) || !isfinite(dt);
+        (m_out + (size_t)d * G.plane)[i] = dl;
+        (m_out + (size_t)(kDeg + d) * G.plane)[i] = dt;
+    }
+}
+
+// Workgroup -> (tile x, tile y, band of slices).
+__device__ __forceinline__ void wg_tile(const Grid &G, int &tx, int &ty, int &band) {
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int per_band = G.tiles_x * G.tiles_y;
+    band = b / per_band;
+    const int r = b - band * per_band;
+    ty = r / G.tiles_x;
+    tx = r - ty * G.tiles_x;
+}
+
+// The iteration.  diverged_at[0] records the first iteration whose launch
+// met an invalid value; launches of later iterations return at once (the
+// launch that met it completes, so its output buffer holds that iteration).
+template <typename T>
+__global__ __launch_bounds__(256) void k_iter(Grid G, const T *__restrict__ m_in,
+                                              T *__restrict__ m_out, const T *__restrict__ aw,
+                                              const T *__restrict__ bw, T eta,
+                                              uint32_t *__restrict__ diverged_at, uint32_t it) {
+    const uint32_t seen = *diverged_at;
+    if (seen != 0u && seen < it) return;
+    int tx, ty, band;
+    wg_tile(G, tx, ty, band);
+    const int x = tx * 64 + (int)(threadIdx.x & 63u);
+    const int y = ty * 4 + (int)(threadIdx.x >> 6);
+    const bool inner_xy = tx * 64 >= 2 && tx * 64 + 66 <= G.nx && ty * 4 >= 2 &&
+                          ty * 4 + 6 <= G.ny;
+    const int t0 = band * kChunk, t1 = min(G.nt, t0 + kChunk);
+    bool bad = false;
+#pragma unroll 1
+    for (int t = t0; t < t1; ++t) {
+        if (inner_xy && t > 0 && t < G.nt - 1)
+            iter_node<T, true>(G, m_in, m_out, aw, bw, eta, bad, x, y, t);
+        else if (x < G.nx && y < G.ny)
+            iter_node<T, false>(G, m_in, m_out, aw, bw, eta, bad, x, y, t);
+    }
+    if (bad) atomicCAS(diverged_at, 0u, it);
+}
+
+// --------------------------------------------------------------------------
+// Set-up: A_ii = Q_ii + p_i (p_i already folded into adiag64 by the
+// observation fold), b_i = h_i + (P m)_i on slice 0 with P = S L^2, the
+// message-precision copies of both.  Thread per node.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double q_diag(const Grid &G, int x, int y, int t) {
+    const double gi = (double)(axis_g(x, G.nx, G.bcx) + axis_g(y, G.ny, G.bcy));
+    return coef<double>(G.blk[slice_kind(G, t)], 0, gi, 0.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_node_init(Grid G, double *__restrict__ adiag64,
+                                                   double *__restrict__ b64,
+                                                   const double *__restrict__ pm,
+                                                   T *__restrict__ aw, T *__restrict__ bw,
+                                                   uint32_t *__restrict__ err_flag) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nodes = (int64_t)G.nx * G.ny * G.nt;
+    if (k >= nodes) return;
+    const int x = (int)(k % G.nx);
+    const int y = (int)((k / G.nx) % G.ny);
+    const int t = (int)(k / ((int64_t)G.nx * G.ny));
+    const int64_t i = (int64_t)t * G.slice + (int64_t)y * G.pitch + x;
+    const double a = q_diag(G, x, y, t) + adiag64[i];
+    double b = b64[i];
+    if (pm && t == 0) {
+        // (S L^2 m)_i over the 13-point stencil of S L^2
+        const double *lsq = G.lsq;
+        const double gi = (double)(axis_g(x, G.nx, G.bcx) + axis_g(y, G.ny, G.bcy));
+        double s = coef<double>(lsq, 0, gi, 0.0) * pm[(int64_t)y * G.nx + x];
+        for (int d = 0; d < 12; ++d) {
+            int xn, yn, tn;
+            if (!nbr(G, x, y, 0, d, xn, yn, tn)) continue;
+            const double gj = (double)(axis_g(xn, G.nx, G.bcx) + axis_g(yn, G.ny, G.bcy));
+            s += coef<double>(lsq, scls(d), gi, gj) * pm[(int64_t)yn * G.nx + xn];
+        }
+        if (!isfinite(s)) *err_flag = 1u;
+        b += s;
+    }
+    adiag64[i] = a;
+    b64[i] = b;
+    aw[i] = (T)a;
+    bw[i] = (T)b;
+}
+
+// --------------------------------------------------------------------------
+// Marginals (Compute Marginal) in FP64: Lam = A_ii + c sum Lam_{k->i},
+// th = b_i + c sum th_{k->i}, mu = th / Lam, var = 1 / Lam.  Writes the
+// pitched mean plane read by the residual and, when given, dense outputs.
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_post(Grid G, const T *__restrict__ m,
+                                              const double *__restrict__ adiag64,
+                                              const double *__restrict__ b64,
+                                              double *__restrict__ mu_plane,
+                                              double *__restrict__ mean,
+                                              double *__restrict__ var) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nodes = (int64_t)G.nx * G.ny * G.nt;
+    if (k >= nodes) return;
+    const int x = (int)(k % G.nx);
+    const int y = (int)((k / G.nx) % G.ny);
+    const int t = (int)(k / ((int64_t)G.nx * G.ny));
+    const int64_t i = (int64_t)t * G.slice + (int64_t)y * G.pitch + x;
+    double sl = 0.0, st = 0.0;
+    for (int d = 0; d < kDeg; ++d) {
+        int xn, yn, tn;
+        if (!nbr(G, x, y, t, d, xn, yn, tn)) continue;
+        const int64_t j = (int64_t)tn * G.slice + (int64_t)yn * G.pitch + xn;
+        sl += (double)(m + (size_t)(d ^ 1) * G.plane)[j];
+        st += (double)(m + (size_t)(kDeg + (d ^ 1)) * G.plane)[j];
+    }
+    const double bl = adiag64[i] + G.c * sl;
+    const double bt = b64[i] + G.c * st;
+    const double mu = bt / bl;
+    mu_plane[i] = mu;
+    if (mean) mean[k] = mu;
+    if (var) var[k] = 1.0 / bl;
+}
+
+// FP64 residual partials: workgroup g sums (A mu - b)_i^2 and b_i^2 over the
+// nodes g*256 + l + k*256*gridDim (fixed order), wave64 butterfly then LDS.
+__global__ __launch_bounds__(256) void k_resid(Grid G, const double *__restrict__ mu,
+                                               const double *__restrict__ adiag64,
+                                               const double *__restrict__ b64,
+                                               double *__restrict__ partials) {
+    __shared__ double sh[2][4];
+    const int64_t nodes = (int64_t)G.nx * G.ny * G.nt;
+    double rr = 0.0, bb = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nodes;
+         k += (int64_t)gridDim.x * 256) {
+        const int x = (int)(k % G.nx);
+        const int y = (int)((k / G.nx) % G.ny);
+        const int t = (int)(k / ((int64_t)G.nx * G.ny));
+        const int64_t i = (int64_t)t * G.slice + (int64_t)y * G.pitch + x;
+        const int kind = slice_kind(G, t);
+        const double gi = (double)(axis_g(x, G.nx, G.bcx) + axis_g(y, G.ny, G.bcy));
+        double r = adiag64[i] * mu[i];
+        for (int d = 0; d < kDeg; ++d) {
+            int xn, yn, tn;
+            if (!nbr(G, x, y, t, d, xn, yn, tn)) continue;
+            const int64_t j = (int64_t)tn * G.slice + (int64_t)yn * G.pitch + xn;
+            const double gj = (double)(axis_g(xn, G.nx, G.bcx) + axis_g(yn, G.ny, G.bcy));
+            r += coef<double>(d < 12 ? G.blk[kind] : G.blk[3], scls(d), gi, gj) * mu[j];
+        }
+        r -= b64[i];
+        rr += r * r;
+        bb += b64[i] * b64[i];
+    }
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    const int w = (int)(threadIdx.x >> 6);
+    if ((threadIdx.x & 63u) == 0u) {
+        sh[0][w] = rr;
+        sh[1][w] = bb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        partials[2 * blockIdx.x + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partials, int npart,
+                                                double *__restrict__ out) {
+    __shared__ double sh[2][4];
+    double a = 0.0, b = 0.0;
+    for (int k = (int)threadIdx.x; k < npart; k += 256) {
+        a += partials[2 * k];
+        b += partials[2 * k + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = (int)(threadIdx.x >> 6);
+    if ((threadIdx.x & 63u) == 0u) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        out[1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    }
+}
+
+// Receiver-indexed copy: out[d][node] = message into node from node + off_d
+// (sender plane d ^ 1 at the sender), 0 where the sender does not exist.
+template <typename T>
+__global__ __launch_bounds__(256) void k_msgs_get(Grid G, const T *__restrict__ m,
+                                                  T *__restrict__ prec, T *__restrict__ info) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nodes = (int64_t)G.nx * G.ny * G.nt;
+    if (k >= nodes) return;
+    const int x = (int)(k % G.nx);
+    const int y = (int)((k / G.nx) % G.ny);
+    const int t = (int)(k / ((int64_t)G.nx * G.ny));
+    for (int d = 0; d < kDeg; ++d) {
+        int xn, yn, tn;
+        T l = (T)0, th = (T)0;
+        if (nbr(G, x, y, t, d, xn, yn, tn)) {
+            const int64_t j = (int64_t)tn * G.slice + (int64_t)yn * G.pitch + xn;
+            l = (m + (size_t)(d ^ 1) * G.plane)[j];
+            th = (m + (size_t)(kDeg + (d ^ 1)) * G.plane)[j];
+        }
+        prec[(size_t)d * nodes + k] = l;
+        info[(size_t)d * nodes + k] = th;
+    }
+}
+
+}  // namespace st
+}  // namespace gabp
+
+// ==========================================================================
+// Host side
+// ==========================================================================
+using gabp::st::Grid;
+
+namespace {
+
+thread_local std::string g_st_create_error;
+
+struct Layout {
+    int32_t pitch = 0;
+    int64_t slice = 0, plane = 0, node_elems = 0;
+    size_t msg[2] = {0, 0};
+    size_t adiag64 = 0, b64 = 0, mu64 = 0, aw = 0, bw = 0;
+    size_t partials = 0, red = 0, flags = 0, total = 0;
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+Layout make_layout(const gabp_st_model &m, size_t esize) {
+    Layout l;
+    const size_t row = 256 / esize;
+    l.pitch = (int32_t)round_up((size_t)m.nx, row);
+    l.slice = (int64_t)l.pitch * m.ny;
+    l.node_elems = l.slice * m.nt;
+    l.plane = (int64_t)(round_up((size_t)l.node_elems, row) + row);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = round_up(off + bytes, 256);
+        return o;
+    };
+    const size_t buf = (size_t)(2 * gabp::st::kDeg) * (size_t)l.plane * esize;
+    l.msg[0] = take(buf);
+    l.msg[1] = take(buf);
+    const size_t n8 = (size_t)l.node_elems * 8;
+    l.adiag64 = take(n8);
+    l.b64 = take(n8);
+    l.mu64 = take(n8);
+    if (esize == 4) {
+        l.aw = take((size_t)l.node_elems * 4);
+        l.bw = take((size_t)l.node_elems * 4);
+    }
+    l.partials = take((size_t)gabp::st::kPartials * 2 * sizeof(double));
+    l.red = take(8 * sizeof(double));
+    l.flags = take(8 * sizeof(uint32_t));
+    l.total = off;
+    return l;
+}
+
+std::string check_model(const gabp_st_model *m, int32_t dtype) {
+    if (!m) return "model is NULL";
+    if (dtype != GABP_F32 && dtype != GABP_F64) return "dtype must be GABP_F32 or GABP_F64";
+    if (m->nx < 1 || m->ny < 1 || m->nt < 1) return "nx, ny and nt must be >= 1";
+    for (int32_t bc : {m->bc_x, m->bc_y})
+        if (bc != GABP_BC_NEUMANN && bc != GABP_BC_PERIODIC)
+            return "boundary must be GABP_BC_NEUMANN or GABP_BC_PERIODIC";
+    if ((m->bc_x == GABP_BC_PERIODIC && m->nx < 5) || (m->bc_y == GABP_BC_PERIODIC && m->ny < 5))
+        return "a periodic axis needs at least 5 cells";
+    const int64_t pitch = (m->nx + 63) / 64 * 64;
+    if (pitch * (int64_t)m->ny * (int64_t)m->nt >= ((int64_t)1 << 31))
+        return "grid too large (nx*ny*nt, rows padded to 64, must stay below 2^31)";
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(m->dt) || !pos(m->h) || !pos(m->sigma_u) || !pos(m->a0) || !pos(m->kappa))
+        return "dt, h, sigma_u, a0 and kappa must be finite and > 0";
+    if (!std::isfinite(m->nu) || m->nu < 0.0) return "nu must be finite and >= 0";
+    if (!std::isfinite(m->c) || m->c == 0.0) return "c must be finite and non-zero";
+    return "";
+}
+
+// (p, q, r) of the four blocks and of L^2, times S (see the file comment).
+void block_coefficients(const gabp_st_model &m, double blk[4][3], double lsq[3]) {
+    const double S = m.dt * m.h * m.h / (m.sigma_u * m.sigma_u);
+    const double a1 = 1.0 / m.dt, a2 = m.nu / (2.0 * m.h * m.h);
+    const double l1 = m.a0 * m.kappa * m.kappa, l2 = m.a0 / (m.h * m.h);
+    const double AA[3] = {a1 * a1, 2.0 * a1 * a2, a2 * a2};
+    const double BB[3] = {a1 * a1, -2.0 * a1 * a2, a2 * a2};
+    const double LL[3] = {l1 * l1, 2.0 * l1 * l2, l2 * l2};
+    const double AB[3] = {a1 * a1, 0.0, -a2 * a2};
+    for (int k = 0; k < 3; ++k) {
+        blk[0][k] = S * (m.nt > 1 ? LL[k] + BB[k] : LL[k]);
+        blk[1][k] = S * (AA[k] + BB[k]);
+        blk[2][k] = S * AA[k];
+        blk[3][k] = -S * AB[k];
+        lsq[k] = S * LL[k];
+    }
+}
+
+}  // namespace
+
+struct gabp_st_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Grid G{};
+    int dtype = 0;
+    char *ws = nullptr;
+    Layout lay;
+    void *msg[2] = {nullptr, nullptr};
+    double *adiag64 = nullptr, *b64 = nullptr, *mu64 = nullptr;
+    void *aw = nullptr, *bw = nullptr;
+    double *partials = nullptr, *red = nullptr;
+    uint32_t *flags = nullptr;    // [0] diverged-at iteration, [1] input error
+    uint32_t *host_flags = nullptr;   // pinned mirrors
+    double *host_red = nullptr;
+    int cur = 0;
+    int64_t iter = 0;
+    int64_t diverged_at = 0;
+    std::string err;
+};
+
+namespace {
+
+gabp_status st_fail(gabp_st_ctx *ctx, gabp_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    else g_st_create_error = msg;
+    return s;
+}
+
+#define ST_HIP(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return st_fail((ctx), GABP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+gabp_status st_ok(gabp_st_ctx *ctx) {
+    if (!ctx) return GABP_E_INVALID;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return st_fail(ctx, GABP_E_DEVICE, "hipSetDevice failed");
+    return GABP_OK;
+}
+
+// Read the device flags back and fold a recorded divergence into the host state.
+gabp_status st_sync(gabp_st_ctx *ctx) {
+    ST_HIP(ctx, hipMemcpyAsync(ctx->host_flags, ctx->flags, 8 * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    ST_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->host_flags[0] != 0u && ctx->diverged_at == 0) {
+        ctx->diverged_at = ctx->host_flags[0];
+        // the launch of that iteration completed; later ones wrote nothing
+        ctx->cur = (int)(ctx->diverged_at & 1);
+        ctx->iter = ctx->diverged_at;
+    }
+    if (ctx->diverged_at != 0)
+        return st_fail(ctx, GABP_E_DIVERGED,
+                       "non-positive cavity precision or non-finite message at iteration " +
+                           std::to_string(ctx->diverged_at));
+    return GABP_OK;
+}
+
+unsigned node_blocks(const Grid &G) {
+    return (unsigned)(((int64_t)G.nx * G.ny * G.nt + 255) / 256);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gabp_st_create_error(void) { return g_st_create_error.c_str(); }
+
+gabp_status gabp_st_workspace_size(const gabp_st_model *model, int32_t dtype, size_t *bytes) {
+    const std::string e = check_model(model, dtype);
+    if (!e.empty()) return st_fail(nullptr, GABP_E_INVALID, e);
+    if (!bytes) return st_fail(nullptr, GABP_E_INVALID, "bytes is NULL");
+    *bytes = make_layout(*model, dtype == GABP_F32 ? 4 : 8).total;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_create(const gabp_st_model *model, const gabp_obs *obs,
+                           const gabp_noise *noise, const double *prior_mean, int32_t dtype,
+                           void *stream, gabp_st_ctx **out) {
+    g_st_create_error.clear();
+    if (!out) return st_fail(nullptr, GABP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const std::string me = check_model(model, dtype);
+    if (!me.empty()) return st_fail(nullptr, GABP_E_INVALID, me);
+    if (!obs || !noise) return st_fail(nullptr, GABP_E_INVALID, "obs and noise are required");
+    if (obs->n < 0 || (obs->n > 0 && (!obs->cell || !obs->y)))
+        return st_fail(nullptr, GABP_E_INVALID, "observation arrays missing");
+    if (!noise->var && !(std::isfinite(noise->sigma) && noise->sigma > 0.0))
+        return st_fail(nullptr, GABP_E_INVALID, "sigma must be finite and > 0");
+    if (obs->n > 0 && !obs->on_device) {
+        // host observations are checked before any device call
+        const int64_t ncells = (int64_t)model->nx * model->ny * model->nt;
+        for (int64_t k = 0; k < obs->n; ++k) {
+            const double v = noise->var ? noise->var[k] : noise->sigma * noise->sigma;
+            if (obs->cell[k] < 0 || obs->cell[k] >= ncells)
+                return st_fail(nullptr, GABP_E_INVALID, "observation cell out of range");
+            if (!std::isfinite(obs->y[k]) || !std::isfinite(v) || !(v > 0.0))
+                return st_fail(nullptr, GABP_E_INVALID,
+                               "non-finite observation or non-positive variance");
+        }
+    }
+    gabp_st_ctx *ctx = new (std::nothrow) gabp_st_ctx();
+    if (!ctx) return st_fail(nullptr, GABP_E_NOMEM, "host allocation failed");
+    auto bail = [&](gabp_status s) {
+        g_st_create_error = ctx->err;
+        gabp_st_destroy(ctx);
+        return s;
+    };
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        ctx->err = "hipGetDevice failed";
+        return bail(GABP_E_DEVICE);
+    }
+    ctx->stream = (hipStream_t)stream;
+    ctx->dtype = dtype;
+    const size_t esize = dtype == GABP_F32 ? 4 : 8;
+    ctx->lay = make_layout(*model, esize);
+    const Layout &l = ctx->lay;
+    Grid &G = ctx->G;
+    G.nx = model->nx;
+    G.ny = model->ny;
+    G.nt = model->nt;
+    G.pitch = l.pitch;
+    G.bcx = model->bc_x;
+    G.bcy = model->bc_y;
+    G.tiles_x = (model->nx + 63) / 64;
+    G.tiles_y = (model->ny + 3) / 4;
+    G.chunks = (model->nt + gabp::st::kChunk - 1) / gabp::st::kChunk;
+    G.slice = l.slice;
+    G.plane = l.plane;
+    block_coefficients(*model, G.blk, G.lsq);
+    G.c = model->c;
+    G.inv_c = 1.0 / model->c;
+    if ((int64_t)G.tiles_x * G.tiles_y * G.chunks >= INT32_MAX) {
+        ctx->err = "grid too large for one launch";
+        return bail(GABP_E_INVALID);
+    }
+    if (hipMalloc((void **)&ctx->ws, l.total) != hipSuccess) {
+        ctx->err = "device allocation of " + std::to_string(l.total) + " bytes failed";
+        return bail(GABP_E_NOMEM);
+    }
+    if (hipHostMalloc((void **)&ctx->host_flags, 8 * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->host_red, 8 * sizeof(double)) != hipSuccess) {
+        ctx->err = "pinned host allocation failed";
+        return bail(GABP_E_NOMEM);
+    }
+    ctx->msg[0] = ctx->ws + l.msg[0];
+    ctx->msg[1] = ctx->ws + l.msg[1];
+    ctx->adiag64 = (double *)(ctx->ws + l.adiag64);
+    ctx->b64 = (double *)(ctx->ws + l.b64);
+    ctx->mu64 = (double *)(ctx->ws + l.mu64);
+    ctx->aw = esize == 4 ? (void *)(ctx->ws + l.aw) : (void *)ctx->adiag64;
+    ctx->bw = esize == 4 ? (void *)(ctx->ws + l.bw) : (void *)ctx->b64;
+    ctx->partials = (double *)(ctx->ws + l.partials);
+    ctx->red = (double *)(ctx->ws + l.red);
+    ctx->flags = (uint32_t *)(ctx->ws + l.flags);
+    if (hipMemsetAsync(ctx->ws, 0, l.total, ctx->stream) != hipSuccess) {
+        ctx->err = "hipMemsetAsync failed";
+        return bail(GABP_E_DEVICE);
+    }
+    // observations on the device (staged when given on the host)
+    const int64_t nobs = obs->n;
+    int64_t *tc = nullptr;
+    double *ty = nullptr, *tv = nullptr;
+    const int64_t *dc = obs->cell;
+    const double *dy = obs->y, *dv = noise->var;
+    if (nobs > 0 && !obs->on_device) {
+        bool ok = hipMalloc((void **)&tc, nobs * sizeof(int64_t)) == hipSuccess &&
+                  hipMalloc((void **)&ty, nobs * sizeof(double)) == hipSuccess &&
+                  (!noise->var || hipMalloc((void **)&tv, nobs * sizeof(double)) == hipSuccess) &&
+                  hipMemcpyAsync(tc, obs->cell, nobs * sizeof(int64_t), hipMemcpyHostToDevice,
+                                 ctx->stream) == hipSuccess &&
+                  hipMemcpyAsync(ty, obs->y, nobs * sizeof(double), hipMemcpyHostToDevice,
+                                 ctx->stream) == hipSuccess &&
+                  (!noise->var || hipMemcpyAsync(tv, noise->var, nobs * sizeof(double),
+                                                 hipMemcpyHostToDevice, ctx->stream) == hipSuccess);
+        if (!ok) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(tc);
+            (void)hipFree(ty);
+            (void)hipFree(tv);
+            ctx->err = "staging observations on the device failed";
+            return bail(GABP_E_NOMEM);
+        }
+        dc = tc;
+        dy = ty;
+        dv = tv;
+    }
+    const double s2 = noise->var ? 0.0 : noise->sigma * noise->sigma;
+    hipError_t e = gabp::launch_obs_fold(nobs, dc, dy, dv, s2,
+                                         (int64_t)G.nx * G.ny * G.nt, G.nx, G.pitch, ctx->adiag64,
+                                         ctx->b64, ctx->flags + 1, ctx->stream);
+    (void)hipFree(tc);
+    (void)hipFree(ty);
+    (void)hipFree(tv);
+    if (e == hipSuccess) {
+        if (esize == 4)
+            hipLaunchKernelGGL((gabp::st::k_node_init<float>), dim3(node_blocks(G)), dim3(256), 0,
+                               ctx->stream, G, ctx->adiag64, ctx->b64, prior_mean, (float *)ctx->aw, (float *)ctx->bw,
+                               ctx->flags + 1);
+        else
+            hipLaunchKernelGGL((gabp::st::k_node_init<double>), dim3(node_blocks(G)), dim3(256), 0,
+                               ctx->stream, G, ctx->adiag64, ctx->b64, prior_mean, (double *)ctx->aw, (double *)ctx->bw,
+                               ctx->flags + 1);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->host_flags, ctx->flags, 8 * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, ctx->stream);
+    const hipError_t es = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) {
+        ctx->err = std::string("set-up failed: ") + hipGetErrorString(e);
+        return bail(GABP_E_DEVICE);
+    }
+    if (ctx->host_flags[1] != 0u) {
+        ctx->err = "invalid observation (cell out of range, non-finite value or non-positive "
+                   "variance) or non-finite prior mean";
+        return bail(GABP_E_INVALID);
+    }
+    *out = ctx;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_iterate(gabp_st_ctx *ctx, int32_t n_iters, double damping) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (n_iters < 0) return st_fail(ctx, GABP_E_INVALID, "n_iters must be >= 0");
+    if (!(damping > 0.0 && damping <= 1.0))
+        return st_fail(ctx, GABP_E_INVALID, "damping must lie in (0, 1]");
+    if (ctx->diverged_at != 0) return st_sync(ctx);
+    if (ctx->iter + n_iters >= (int64_t)UINT32_MAX)
+        return st_fail(ctx, GABP_E_INVALID, "iteration count would exceed 2^32 - 1");
+    const Grid &G = ctx->G;
+    const dim3 grid((unsigned)(G.tiles_x * G.tiles_y * G.chunks)), block(256);
+    for (int32_t k = 0; k < n_iters; ++k) {
+        const uint32_t it = (uint32_t)(ctx->iter + 1);
+        void *in = ctx->msg[ctx->cur], *out = ctx->msg[ctx->cur ^ 1];
+        if (ctx->dtype == GABP_F32)
+            hipLaunchKernelGGL((gabp::st::k_iter<float>), grid, block, 0, ctx->stream, G,
+                               (const float *)in, (float *)out, (const float *)ctx->aw,
+                               (const float *)ctx->bw, (float)damping, ctx->flags, it);
+        else
+            hipLaunchKernelGGL((gabp::st::k_iter<double>), grid, block, 0, ctx->stream, G,
+                               (const double *)in, (double *)out, (const double *)ctx->aw,
+                               (const double *)ctx->bw, damping, ctx->flags, it);
+        ST_HIP(ctx, hipGetLastError());
+        ctx->cur ^= 1;
+        ctx->iter += 1;
+    }
+    return GABP_OK;
+}
+
+gabp_status gabp_st_posterior(gabp_st_ctx *ctx, double *mean, double *var) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    const Grid &G = ctx->G;
+    if (ctx->dtype == GABP_F32)
+        hipLaunchKernelGGL((gabp::st::k_post<float>), dim3(node_blocks(G)), dim3(256), 0,
+                           ctx->stream, G, (const float *)ctx->msg[ctx->cur], ctx->adiag64,
+                           ctx->b64, ctx->mu64, mean, var);
+    else
+        hipLaunchKernelGGL((gabp::st::k_post<double>), dim3(node_blocks(G)), dim3(256), 0,
+                           ctx->stream, G, (const double *)ctx->msg[ctx->cur], ctx->adiag64,
+                           ctx->b64, ctx->mu64, mean, var);
+    ST_HIP(ctx, hipGetLastError());
+    return GABP_OK;
+}
+
+gabp_status gabp_st_residual(gabp_st_ctx *ctx, double *rel_residual, double *abs_residual) {
+    gabp_status s = st_sync(ctx);
+    if (s != GABP_OK) return s;
+    s = gabp_st_posterior(ctx, nullptr, nullptr);
+    if (s != GABP_OK) return s;
+    const Grid &G = ctx->G;
+    const int64_t want = ((int64_t)G.nx * G.ny * G.nt + 255) / 256;
+    const int nb = (int)std::min<int64_t>(want, gabp::st::kPartials);
+    hipLaunchKernelGGL(gabp::st::k_resid, dim3(nb), dim3(256), 0, ctx->stream, G,
+                       (const double *)ctx->mu64, (const double *)ctx->adiag64,
+                       (const double *)ctx->b64, ctx->partials);
+    hipLaunchKernelGGL(gabp::st::k_reduce, dim3(1), dim3(256), 0, ctx->stream,
+                       (const double *)ctx->partials, nb, ctx->red);
+    ST_HIP(ctx, hipGetLastError());
+    ST_HIP(ctx, hipMemcpyAsync(ctx->host_red, ctx->red, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    ST_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const double a = std::sqrt(ctx->host_red[0]), nb2 = std::sqrt(ctx->host_red[1]);
+    if (!std::isfinite(a))
+        return st_fail(ctx, GABP_E_DIVERGED, "non-finite residual");
+    if (abs_residual) *abs_residual = a;
+    if (rel_residual) *rel_residual = nb2 > 0.0 ? a / nb2 : a;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_solve(gabp_st_ctx *ctx, int64_t max_iters, double damping, double rel_tol,
+                          int32_t check_every, int64_t *iters_done, double *rel_residual) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (max_iters < 0 || check_every <= 0 || !(rel_tol >= 0.0))
+        return st_fail(ctx, GABP_E_INVALID,
+                       "max_iters must be >= 0, check_every > 0 and rel_tol >= 0");
+    int64_t done = 0;
+    double rel = INFINITY, first = -1.0;
+    s = gabp_st_residual(ctx, &rel, nullptr);
+    while (s == GABP_OK && rel > rel_tol && done < max_iters) {
+        const int32_t k = (int32_t)std::min<int64_t>(check_every, max_iters - done);
+        s = gabp_st_iterate(ctx, k, damping);
+        if (s != GABP_OK) break;
+        done += k;
+        s = gabp_st_residual(ctx, &rel, nullptr);
+        if (s != GABP_OK) break;
+        if (first < 0.0) first = rel;
+        else if (rel > 1e3 * first) {
+            s = st_fail(ctx, GABP_E_DIVERGED, "residual grew more than 1e3 times");
+            break;
+        }
+    }
+    if (iters_done) *iters_done = ctx->iter;
+    if (rel_residual) *rel_residual = rel;
+    if (s != GABP_OK) return s;
+    return rel <= rel_tol ? GABP_OK : GABP_E_NOT_CONVERGED;
+}
+
+gabp_status gabp_st_get_messages(gabp_st_ctx *ctx, void *prec, void *info) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (!prec || !info) return st_fail(ctx, GABP_E_INVALID, "prec and info are required");
+    const Grid &G = ctx->G;
+    if (ctx->dtype == GABP_F32)
+        hipLaunchKernelGGL((gabp::st::k_msgs_get<float>), dim3(node_blocks(G)), dim3(256), 0,
+                           ctx->stream, G, (const float *)ctx->msg[ctx->cur], (float *)prec,
+                           (float *)info);
+    else
+        hipLaunchKernelGGL((gabp::st::k_msgs_get<double>), dim3(node_blocks(G)), dim3(256), 0,
+                           ctx->stream, G, (const double *)ctx->msg[ctx->cur], (double *)prec,
+                           (double *)info);
+    ST_HIP(ctx, hipGetLastError());
+    return GABP_OK;
+}
+
+gabp_status gabp_st_iteration_count(gabp_st_ctx *ctx, int64_t *iters, int64_t *diverged_at) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    s = st_sync(ctx);
+    if (iters) *iters = ctx->iter;
+    if (diverged_at) *diverged_at = ctx->diverged_at;
+    return s == GABP_E_DIVERGED ? GABP_OK : s;
+}
+
+const char *gabp_st_last_error(gabp_st_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+void gabp_st_destroy(gabp_st_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ws);
+    (void)hipHostFree(ctx->host_flags);
+    (void)hipHostFree(ctx->host_red);
+    delete ctx;
+}
+
+}  // extern "C"

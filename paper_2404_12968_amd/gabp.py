@@ -51,6 +51,13 @@ class gabp_opts(ctypes.Structure):
                 ("prior_mean", ctypes.c_void_p)]
 
 
+class gabp_st_model(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("h", ctypes.c_double), ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("a0", ctypes.c_double), ("sigma_u", ctypes.c_double), ("c", ctypes.c_double)]
+
+
 class gabp_instance(ctypes.Structure):
     _fields_ = [("grid", gabp_grid), ("stencil", gabp_stencil), ("obs", gabp_obs),
                 ("noise", gabp_noise)]
@@ -121,6 +128,19 @@ _SIGS = {
     "gabp_warm_features": ([ctypes.c_int64, _P, _P, ctypes.c_int64, ctypes.c_int64,
                             ctypes.c_double, _P, _P, _P], ctypes.c_int),
     "gabp_net_last_error": ([], ctypes.c_char_p),
+    # space-time solver, include/gabp_st.h
+    "gabp_st_workspace_size": ([_P, ctypes.c_int32, _P], ctypes.c_int),
+    "gabp_st_create": ([_P, _P, _P, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "gabp_st_create_error": ([], ctypes.c_char_p),
+    "gabp_st_iterate": ([_P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+    "gabp_st_residual": ([_P, _P, _P], ctypes.c_int),
+    "gabp_st_solve": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                       _P, _P], ctypes.c_int),
+    "gabp_st_posterior": ([_P, _P, _P], ctypes.c_int),
+    "gabp_st_get_messages": ([_P, _P, _P], ctypes.c_int),
+    "gabp_st_iteration_count": ([_P, _P, _P], ctypes.c_int),
+    "gabp_st_last_error": ([_P], ctypes.c_char_p),
+    "gabp_st_destroy": ([_P], None),
 }
 
 if not os.path.exists(_LIB_PATH):
@@ -655,3 +675,140 @@ def gabp_upsample_mean(coarse: torch.Tensor, bc_x: int, bc_y: int, nxf: int, nyf
     _check(_lib.gabp_upsample_mean(_ptr(coarse), int(nxc), int(nyc), int(bc_x), int(bc_y),
                                    _ptr(pred), int(nxf), int(nyf), _stream_handle(stream)))
     return pred
+
+
+# --------------------------------------------------------------------------
+# space-time solver (include/gabp_st.h)
+# --------------------------------------------------------------------------
+
+ST_DIRECTIONS = 38
+
+
+class STContext:
+    """A live gabp_st_ctx (the library owns its device memory)."""
+
+    def __init__(self, handle, stream, nx, ny, nt, dtype, device):
+        self.handle = handle
+        self.stream = stream
+        self.nx, self.ny, self.nt = nx, ny, nt
+        self.dtype = dtype
+        self.device = device
+
+    def __del__(self):
+        try:
+            gabp_st_destroy(self)
+        except Exception:
+            pass
+
+
+def _st_check(st: int, ctx: Optional[STContext] = None):
+    if st != GABP_OK:
+        raise GabpError(st, gabp_st_last_error(ctx) if ctx is not None else gabp_st_create_error())
+
+
+def gabp_st_create_error() -> str:
+    return _lib.gabp_st_create_error().decode()
+
+
+def gabp_st_last_error(ctx: Optional[STContext]) -> str:
+    return _lib.gabp_st_last_error(ctx.handle if ctx is not None else None).decode()
+
+
+def st_model(prob) -> gabp_st_model:
+    """gabp_st_model of an ``inputs.SpaceTimeProblem``."""
+    return gabp_st_model(int(prob.nx), int(prob.ny), int(prob.nt), int(prob.bc_x),
+                         int(prob.bc_y), float(prob.dt), float(prob.h), float(prob.nu),
+                         float(prob.kappa), float(prob.a0), float(prob.sigma_u), float(prob.c))
+
+
+def gabp_st_workspace_size(model: gabp_st_model, dtype: int) -> int:
+    n = ctypes.c_size_t(0)
+    _st_check(_lib.gabp_st_workspace_size(ctypes.byref(model), int(dtype), ctypes.byref(n)))
+    return int(n.value)
+
+
+def gabp_st_create(model: gabp_st_model, cells, y, sigma: float, var=None, prior_mean=None,
+                   dtype: int = GABP_F32, stream=None, device=None) -> STContext:
+    """Create a space-time context; cells (int64) and y (float64) go to the
+    device first (torch tensors or numpy arrays)."""
+    device = torch.device(device or "cuda")
+    cells = torch.as_tensor(np.asarray(cells) if not torch.is_tensor(cells) else cells,
+                            dtype=torch.int64).to(device).contiguous()
+    y = torch.as_tensor(np.asarray(y) if not torch.is_tensor(y) else y,
+                        dtype=torch.float64).to(device).contiguous()
+    if var is not None:
+        var = torch.as_tensor(var, dtype=torch.float64).to(device).contiguous()
+    if prior_mean is not None:
+        prior_mean = torch.as_tensor(prior_mean, dtype=torch.float64).to(device).contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    obs = gabp_obs(int(cells.numel()), cells.data_ptr() if cells.numel() else None,
+                   y.data_ptr() if y.numel() else None, 1)
+    noise = gabp_noise(float(sigma), None if var is None else var.data_ptr())
+    h = ctypes.c_void_p()
+    _st_check(_lib.gabp_st_create(ctypes.byref(model), ctypes.byref(obs), ctypes.byref(noise),
+                                  _ptr(prior_mean), int(dtype), stream.cuda_stream,
+                                  ctypes.byref(h)))
+    return STContext(h, stream, model.nx, model.ny, model.nt, int(dtype), device)
+
+
+def gabp_st_create_problem(prob, dtype: Optional[str] = None, prior_mean=None, stream=None,
+                           device=None) -> STContext:
+    """gabp_st_create with the arguments of an ``inputs.SpaceTimeProblem``."""
+    return gabp_st_create(st_model(prob), prob.cells, prob.y, prob.sigma, var=prob.var,
+                          prior_mean=prior_mean, dtype=DTYPES[dtype or prob.dtype],
+                          stream=stream, device=device)
+
+
+def gabp_st_iterate(ctx: STContext, n_iters: int, damping: float) -> None:
+    _st_check(_lib.gabp_st_iterate(ctx.handle, int(n_iters), float(damping)), ctx)
+
+
+def gabp_st_residual(ctx: STContext) -> Tuple[float, float]:
+    rel = ctypes.c_double(0.0)
+    ab = ctypes.c_double(0.0)
+    _st_check(_lib.gabp_st_residual(ctx.handle, ctypes.byref(rel), ctypes.byref(ab)), ctx)
+    return float(rel.value), float(ab.value)
+
+
+def gabp_st_solve(ctx: STContext, max_iters: int, damping: float, rel_tol: float,
+                  check_every: int = 50) -> Tuple[int, int, float]:
+    """Returns (status, total iterations, last relative residual)."""
+    it = ctypes.c_int64(0)
+    rel = ctypes.c_double(0.0)
+    st = _lib.gabp_st_solve(ctx.handle, int(max_iters), float(damping), float(rel_tol),
+                            int(check_every), ctypes.byref(it), ctypes.byref(rel))
+    if st not in (GABP_OK, GABP_E_DIVERGED, GABP_E_NOT_CONVERGED):
+        _st_check(st, ctx)
+    return int(st), int(it.value), float(rel.value)
+
+
+def gabp_st_posterior(ctx: STContext, want_var: bool = True):
+    """Posterior mean and variance as (nt, ny, nx) float64 device tensors."""
+    shape = (ctx.nt, ctx.ny, ctx.nx)
+    mean = torch.empty(shape, dtype=torch.float64, device=ctx.device)
+    var = torch.empty(shape, dtype=torch.float64, device=ctx.device) if want_var else None
+    _st_check(_lib.gabp_st_posterior(ctx.handle, _ptr(mean), _ptr(var)), ctx)
+    return mean, var
+
+
+def gabp_st_get_messages(ctx: STContext):
+    """Receiver-indexed (prec, info) of shape (38, nt, ny, nx), message dtype."""
+    shape = (ST_DIRECTIONS, ctx.nt, ctx.ny, ctx.nx)
+    prec = torch.empty(shape, dtype=TORCH_DTYPES[ctx.dtype], device=ctx.device)
+    info = torch.empty(shape, dtype=TORCH_DTYPES[ctx.dtype], device=ctx.device)
+    _st_check(_lib.gabp_st_get_messages(ctx.handle, _ptr(prec), _ptr(info)), ctx)
+    return prec, info
+
+
+def gabp_st_iteration_count(ctx: STContext) -> Tuple[int, int]:
+    it = ctypes.c_int64(0)
+    dv = ctypes.c_int64(0)
+    _st_check(_lib.gabp_st_iteration_count(ctx.handle, ctypes.byref(it), ctypes.byref(dv)), ctx)
+    return int(it.value), int(dv.value)
+
+
+def gabp_st_destroy(ctx: STContext) -> None:
+    if getattr(ctx, "handle", None) is not None and ctx.handle.value:
+        _lib.gabp_st_destroy(ctx.handle)
+        ctx.handle = ctypes.c_void_p()
