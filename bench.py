@@ -252,18 +252,26 @@ def bench_spacetime(G, I, torch, args):
     """The space-time solver (heat-equation GMRF of the paper's
     spatio-temporal extension) on 64 slices of a 512 x 512 zero-flux grid,
     drifting satellite tracks (~2.3 % of the space-time cells), FP32
-    messages: steps of ITERS_PER_STEP iterations timed with HIP events on the
-    context's stream, then the FP64 residual.  Algorithmic bytes per
-    iteration: both components of every directed message read and written
-    once (16 B per edge) and the two node terms (8 B per node).  CPU
-    baseline: the FP64 oracle iterating on a 128 x 128 x 16 problem of the
-    same generator."""
+    messages.  The full iteration is timed first; the solver then runs with
+    residual checks until the precision messages freeze (freeze tolerance
+    --st-freeze-slots messages of at most 1e-6 relative change), and the
+    timed steps are check intervals of the information-only iteration:
+    ITERS_PER_STEP iterations (HIP events on the context's stream) plus the
+    FP64 residual.  Algorithmic bytes per iteration: full kernel, both
+    components of every directed message read and written once (16 B per
+    edge) and the two node terms (8 B per node); information-only kernel,
+    the information message read and written and the gain read (12 B per
+    edge) and b (4 B per node).  CPU baseline: the FP64 oracle iterating on a
+    128 x 128 x 16 problem of the same generator."""
     prob = I.spacetime(nx=args.st_nx, ny=args.st_ny, nt=args.st_nt)
     E = st_edge_count(prob)
     N = prob.n
-    alg = 16 * E + 8 * N
+    alg_full = 16 * E + 8 * N
+    alg_theta = 12 * E + 4 * N
     progress(f"space-time {prob.nx}x{prob.ny}x{prob.nt}: {E} directed edges")
     ctx = G.gabp_st_create_problem(prob)
+    if args.st_freeze_slots > 0:
+        G.gabp_st_set_freeze_tolerance(ctx, args.st_freeze_slots, 1e-6)
     stream = ctx.stream
 
     def event_ms(fn, reps):
@@ -278,14 +286,41 @@ def bench_spacetime(G, I, torch, args):
         torch.cuda.synchronize()
         return [a.elapsed_time(b) for a, b in ev], time.perf_counter() - t0
 
-    step = lambda: G.gabp_st_iterate(ctx, ITERS_PER_STEP, prob.damping)  # noqa: E731
+    iterate = lambda: G.gabp_st_iterate(ctx, ITERS_PER_STEP, prob.damping)  # noqa: E731
+    iterate()
+    ms, _ = event_ms(iterate, 3)
+    full_ms = sum(ms) / (3 * ITERS_PER_STEP)
+    kernels = {"full": {"iter_ms": full_ms, "algorithmic_bytes": alg_full,
+                        "gbps": alg_full / (full_ms * 1e-3) / 1e9}}
+    # run on with checks until the precision messages freeze (bounded)
+    while G.gabp_st_precision_frozen(ctx) < 0 and G.gabp_st_iteration_count(ctx)[0] < 3000:
+        iterate()
+        G.gabp_st_residual(ctx)
+    frozen_at = G.gabp_st_precision_frozen(ctx)
+    progress(f"space-time precision messages frozen at iteration {frozen_at}")
     for _ in range(args.warmup):
-        step()
-    ms, wall = event_ms(step, args.steps)
-    iter_ms = sum(ms) / (len(ms) * ITERS_PER_STEP)
-    rel, _ = G.gabp_st_residual(ctx)
+        iterate()
+        G.gabp_st_residual(ctx)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    rel = None
+    for a, b in ev:
+        a.record(stream)
+        iterate()
+        b.record(stream)
+        rel, _ = G.gabp_st_residual(ctx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iter_ms = sum(a.elapsed_time(b) for a, b in ev) / (args.steps * ITERS_PER_STEP)
     its = G.gabp_st_iteration_count(ctx)[0]
     value = E * args.steps * ITERS_PER_STEP / wall
+    phase = "theta" if frozen_at >= 0 else "full"
+    alg = alg_theta if phase == "theta" else alg_full
+    kname = "k_iter information-only (space-time)" if phase == "theta" else "k_iter full (space-time)"
+    kernels[phase + "_timed"] = {"iter_ms": iter_ms, "algorithmic_bytes": alg,
+                                 "gbps": alg / (iter_ms * 1e-3) / 1e9}
     achieved = alg / (iter_ms * 1e-3) / 1e9
     out = {"metric": "edge-message updates/s (space-time GMRF)", "value": value,
            "unit": "edge-message updates/s", "n_gpus": 1, "steps": args.steps,
@@ -296,17 +331,23 @@ def bench_spacetime(G, I, torch, args):
                                   f"nu dt/h^2 = {prob.nu * prob.dt / prob.h ** 2:g}), "
                                   f"{prob.nx}x{prob.ny} zero-flux grid x {prob.nt} slices, "
                                   f"38-neighbour stencil, {prob.coverage * 100:.2f}% observed, "
-                                  f"c={prob.c}, damping={prob.damping}, FP32 messages",
+                                  f"c={prob.c}, damping={prob.damping}, FP32 messages, "
+                                  f"FP64 residual",
                       "nodes": N, "directed_edges": E, "iters_per_step": ITERS_PER_STEP,
                       "parallelism": "single GPU"},
            "iterations_run": its, "rel_residual_after": rel,
-           "roofline": {"bound": "hbm", "kernel": "k_iter (space-time)", "achieved": achieved,
+           "timed_phase": {"kernel": kname, "precision_frozen_at_iteration": frozen_at,
+                           "freeze_tolerance_slots": args.st_freeze_slots},
+           "kernels": kernels,
+           "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                         "iter_ms": iter_ms, "algorithmic_bytes_per_launch": alg,
                         "traffic": None}}
     if args.st_solve_tol > 0:
         progress(f"space-time solve to {args.st_solve_tol:g}")
         ctx2 = G.gabp_st_create_problem(prob)
+        if args.st_freeze_slots > 0:
+            G.gabp_st_set_freeze_tolerance(ctx2, args.st_freeze_slots, 1e-6)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         st, it, r = G.gabp_st_solve(ctx2, args.solve_max_iters, prob.damping, args.st_solve_tol,
@@ -314,7 +355,8 @@ def bench_spacetime(G, I, torch, args):
         torch.cuda.synchronize()
         out["time_to_tol"] = {"tol": args.st_solve_tol, "status": G.gabp_status_string(st),
                               "iterations": it, "seconds": time.perf_counter() - t1,
-                              "rel_residual": r}
+                              "rel_residual": r,
+                              "precision_frozen_at": G.gabp_st_precision_frozen(ctx2)}
         del ctx2
     del ctx
     if not args.no_cpu_baseline:
@@ -409,18 +451,50 @@ def bench_batch(G, I, torch, dev, args):
     probs = I.batch256()
     Es = np.array([edge_count(p.nx, p.ny, p.alpha, p.bc_x, p.bc_y) for p in probs], dtype=np.int64)
     Ns = np.array([p.n for p in probs], dtype=np.int64)
-    b = G.gabp_batch_create(probs, device=dev)
-    if args.freeze_slots > 0:
-        G.gabp_batch_set_freeze_tolerance(b, args.freeze_slots, args.freeze_rel)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, its, rels, sts = G.gabp_batch_solve(b, max(args.solve_max_iters, 300000), 0.5, 1e-6, -10)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    updates = float((Es * its).sum())
-    frozen = [G.gabp_batch_info(b, i)[1] for i in range(len(probs))]
     a2 = np.array([p.alpha == 2 for p in probs])
-    del b
+
+    def run(slots):
+        b = G.gabp_batch_create(probs, device=dev)
+        if slots > 0:
+            G.gabp_batch_set_freeze_tolerance(b, slots, args.freeze_rel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, its, rels, sts = G.gabp_batch_solve(b, max(args.solve_max_iters, 300000), 0.5, 1e-6,
+                                                -10)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        frozen = [G.gabp_batch_info(b, i)[1] for i in range(len(probs))]
+        del b
+        return wall, st, its, rels, sts, frozen
+
+    def summary(wall, st, its, rels, sts, frozen):
+        return {"seconds_to_all_converged": wall, "status": G.gabp_status_string(st),
+                "edge_updates_per_s": float((Es * its).sum()) / wall,
+                "converged": int((sts == G.GABP_OK).sum()),
+                "diverged": int((sts == G.GABP_E_DIVERGED).sum()),
+                "iterations_alpha1": [int(its[~a2].min()), int(np.median(its[~a2])), int(its[~a2].max())],
+                "iterations_alpha2": [int(its[a2].min()), int(np.median(its[a2])), int(its[a2].max())],
+                "frozen_at_median": float(np.median([f for f in frozen if f >= 0])) if any(f >= 0 for f in frozen) else None,
+                "frozen_instances": int(sum(f >= 0 for f in frozen)),
+                "max_rel_residual": float(rels.max()),
+                "not_converged": [{"instance": int(i), "side": probs[i].nx, "alpha": probs[i].alpha,
+                                   "kappa": probs[i].kappa, "sigma": probs[i].sigma,
+                                   "coverage": probs[i].coverage, "rel": float(rels[i]),
+                                   "iterations": int(its[i])}
+                                  for i in np.nonzero(sts != G.GABP_OK)[0]]}
+
+    # headline: precision messages frozen only when bitwise stationary (every
+    # result bitwise that of the unfrozen iteration); beside it the run with
+    # the freeze tolerance
+    progress("batch256, bitwise freeze")
+    r0 = run(0)
+    wall, st, its, rels, sts, frozen = r0
+    updates = float((Es * its).sum())
+    tol_run = None
+    if args.freeze_slots > 0:
+        progress(f"batch256, freeze tolerance {args.freeze_slots} messages / {args.freeze_rel:g}")
+        tol_run = summary(*run(args.freeze_slots))
+        tol_run["freeze_tolerance"] = {"max_slots": args.freeze_slots, "max_rel": args.freeze_rel}
     mg = None
     if not args.no_multigrid:
         from paper_2404_12968_amd import multigrid as MG
@@ -430,7 +504,9 @@ def bench_batch(G, I, torch, dev, args):
         fi = np.asarray(r["iterations"])
         mg = {"seconds": r["seconds"], "status": G.gabp_status_string(r["status"]),
               "converged": int((np.asarray(r["statuses"]) == G.GABP_OK).sum()),
-              "speedup": wall / r["seconds"],
+              "speedup_vs_bitwise_run": wall / r["seconds"],
+              "speedup_vs_freeze_tolerance_run": (tol_run["seconds_to_all_converged"] / r["seconds"]
+                                                  if tol_run else None),
               "fine_iterations_alpha1": [int(fi[~a2].min()), int(np.median(fi[~a2])), int(fi[~a2].max())],
               "fine_iterations_alpha2": [int(fi[a2].min()), int(np.median(fi[a2])), int(fi[a2].max())],
               "max_rel_residual": float(np.max(r["rel"])),
@@ -447,23 +523,12 @@ def bench_batch(G, I, torch, dev, args):
                                "kappa ~ U[0.02,0.3], 1-20% observed, sigma ~ U[0.02,0.2], "
                                "each to 1e-6, checks adaptive (every 10 until all running instances "
                                "froze, then growing with the slowest one's residual decay)",
-                   "freeze_tolerance": {"max_slots": args.freeze_slots,
-                                        "max_rel": args.freeze_rel if args.freeze_slots > 0 else 0.0},
+                   "freeze_tolerance": {"max_slots": 0, "max_rel": 0.0,
+                                        "note": "headline run: bitwise freeze only"},
                    "nodes": int(Ns.sum()), "directed_edges": int(Es.sum()),
                    "parallelism": "single GPU"},
-        "batch": {"seconds_to_all_converged": wall, "status": G.gabp_status_string(st),
-                  "converged": int((sts == G.GABP_OK).sum()),
-                  "diverged": int((sts == G.GABP_E_DIVERGED).sum()),
-                  "iterations_alpha1": [int(its[~a2].min()), int(np.median(its[~a2])), int(its[~a2].max())],
-                  "iterations_alpha2": [int(its[a2].min()), int(np.median(its[a2])), int(its[a2].max())],
-                  "frozen_at_median": float(np.median([f for f in frozen if f >= 0])) if any(f >= 0 for f in frozen) else None,
-                  "frozen_instances": int(sum(f >= 0 for f in frozen)),
-                  "max_rel_residual": float(rels.max()),
-                  "not_converged": [{"instance": int(i), "side": probs[i].nx, "alpha": probs[i].alpha,
-                                     "kappa": probs[i].kappa, "sigma": probs[i].sigma,
-                                     "coverage": probs[i].coverage, "rel": float(rels[i]),
-                                     "iterations": int(its[i])}
-                                    for i in np.nonzero(sts != G.GABP_OK)[0]]},
+        "batch": summary(*r0),
+        "batch_freeze_tolerance": tol_run,
         "multigrid": mg,
     }
 
@@ -483,9 +548,9 @@ def bench_table1(G, I, torch, args):
 
     ft = (args.freeze_slots, args.freeze_rel) if args.freeze_slots > 0 else None
 
-    def run(p):
-        r = MG.multigrid_solve(p, coarse_stop="message_change", final_stop="message_change",
-                               max_iters=10000, keep_context=True, freeze_tolerance=ft)
+    def run(p, transfer="messages", stop="message_change", max_iters=10000):
+        r = MG.multigrid_solve(p, coarse_stop=stop, final_stop=stop, max_iters=max_iters,
+                               keep_context=True, freeze_tolerance=ft, transfer=transfer)
         mu = G.gabp_posterior(r["ctx"], want_var=False)[0].cpu().numpy().ravel()
         G.gabp_destroy(r["ctx"])
         return r, float(np.sqrt(np.mean((mu - p.truth.ravel()) ** 2)))
@@ -517,6 +582,32 @@ def bench_table1(G, I, torch, args):
             print(f"[table1] {n}^2 {frac:.0%}: {secs:.3f} s rmse {rm:.4f} "
                   f"(paper MP {row['paper_mp_rmse']}, exact {row['paper_exact_rmse']}) "
                   f"{[x[3] for x in v]}", file=sys.stderr, flush=True)
+    diagnosis = None
+    if args.table1_diagnose:
+        # the 1 % rows, where every level runs into the T cap: the paper's
+        # Upscale Messages read literally (edge values copied unchanged), and
+        # the same runs with no cap, each level solved to a 1e-6 residual
+        diagnosis = []
+        for n in I.TABLE1_SIZES:
+            k = I.TABLE1_FRACS.index(0.01)
+            rec = {"grid": n, "observed": 0.01,
+                   "paper_mp_rmse": gold["rmse_mp"][str(n)][k],
+                   "paper_exact_rmse": gold["rmse_exact"][str(n)][k]}
+            for name, kw in (("messages_T10000", {}),
+                             ("literal_T10000", {"transfer": "literal"}),
+                             ("messages_to_1e-6", {"stop": "residual", "max_iters": 300000})):
+                out_v = []
+                for inst in range(args.table1_truths):
+                    r, e = run(I.table1(n, 0.01, inst), **kw)
+                    out_v.append((e, r["seconds"], [lv["iterations"] for lv in r["levels"]],
+                                  G.gabp_status_string(r["status"])))
+                rec[name] = {"rmse": float(np.mean([x[0] for x in out_v])),
+                             "seconds": float(np.mean([x[1] for x in out_v])),
+                             "level_iterations": [x[2] for x in out_v],
+                             "status": [x[3] for x in out_v]}
+                print(f"[table1 1%] {n}^2 {name}: rmse {rec[name]['rmse']:.4f} "
+                      f"{rec[name]['seconds']:.2f} s", file=sys.stderr, flush=True)
+            diagnosis.append(rec)
     paper_total = sum(sum(v) for v in gold["seconds_mp_rtx3090"].values())
     return {"metric": "wall time of the paper's synthetic experiments (Table 1: 9 grids x "
                       "densities, mean over truths), message passing as the paper runs it",
@@ -532,7 +623,7 @@ def bench_table1(G, I, torch, args):
                        "freeze_tolerance": {"max_slots": ft[0] if ft else 0,
                                             "max_rel": ft[1] if ft else 0.0}},
             "baseline_note": f"paper: {paper_total:.1f} s on one RTX 3090 (Table 1 MP column)",
-            "rows": rows}
+            "rows": rows, "one_percent_diagnosis": diagnosis}
 
 
 def net_flops_per_pixel():
@@ -693,6 +784,8 @@ def main(argv=None):
     ap.add_argument("--st-nx", type=int, default=512)
     ap.add_argument("--st-ny", type=int, default=512)
     ap.add_argument("--st-nt", type=int, default=64)
+    ap.add_argument("--st-freeze-slots", type=int, default=64,
+                    help="spacetime: freeze tolerance (messages changed by at most 1e-6)")
     ap.add_argument("--st-solve-tol", type=float, default=0.0,
                     help="spacetime: also solve a fresh context to this relative residual")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -702,7 +795,7 @@ def main(argv=None):
     ap.add_argument("--solve-max-iters", type=int, default=200000)
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the warm-vs-cold time-to-1e-6 leg (1024^2 workload)")
-    ap.add_argument("--warm-instances", type=int, default=3)
+    ap.add_argument("--warm-instances", type=int, default=8)
     ap.add_argument("--warm-freeze-slots", type=int, default=64,
                     help="warm-start leg: freeze tolerance (messages) of the cold, warm and "
                          "multigrid solves alike (0: bitwise freeze only)")
@@ -718,6 +811,9 @@ def main(argv=None):
                     help="batch256 and table1: ... each by at most this relative change")
     ap.add_argument("--table1-truths", type=int, default=3,
                     help="ground truths per Table 1 configuration")
+    ap.add_argument("--table1-diagnose", action="store_true",
+                    help="table1: rerun the 1 %% rows with the literal message copy between "
+                         "levels and with every level solved to a 1e-6 residual")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the paper's Table 1 leg (nine grid/density configurations)")
     ap.add_argument("--no-multigrid", action="store_true",

@@ -311,6 +311,18 @@ gabp_status gabp_upsample_mean(const double *coarse, int64_t nxc, int64_t nyc, i
 gabp_status gabp_upscale_precisions(gabp_ctx *coarse, float *pred, int64_t nxf, int64_t nyf,
                                     double scale);
 
+/* Multigrid transfer, the paper's Upscale Messages taken literally (Alg. 2):
+ * every message of the fine context (both components), for each fine node
+ * (x, y) and direction d whose fine neighbour exists, is set to the coarse
+ * context's current message from node (x/2, y/2) in direction d (the
+ * opposite direction where the coarse node has none in d, zero where it has
+ * neither), unscaled; the fine context's other slots stay zero.  The
+ * contexts must share device, dtype, alpha and boundary types, with
+ * ceil(nx_fine/2) = nx_coarse and ceil(ny_fine/2) = ny_coarse (INVALID
+ * otherwise).  Synchronises the coarse stream, then runs on the fine
+ * context's stream; the fine context starts its freeze test afresh. */
+gabp_status gabp_copy_coarse_messages(gabp_ctx *coarse, gabp_ctx *fine);
+
 /* Iteration kernels launched by this context so far (graph replays
  * included): one-iteration launches of the full update (full) and of the
  * information-only update once the precision messages froze (theta), and

@@ -66,8 +66,8 @@ typedef struct {
  * or NULL for zero) and the prior diagonal into FP64 node terms, and set
  * every message to zero.  dtype: message precision (GABP_F32 / GABP_F64).
  * stream: the hipStream_t of every call (NULL = default stream).  The library
- * allocates its device memory (two message buffers of 76 planes, node terms,
- * reduction scratch: gabp_st_workspace_size bytes).  INVALID on the first
+ * allocates its device memory (two message buffers of 76 planes, 38 gain
+ * planes, node terms, reduction scratch: gabp_st_workspace_size bytes).  INVALID on the first
  * bad argument (text in gabp_st_create_error). */
 gabp_status gabp_st_create(const gabp_st_model *model, const gabp_obs *obs,
                            const gabp_noise *noise, const double *prior_mean,
@@ -86,7 +86,8 @@ const char *gabp_st_create_error(void);
 gabp_status gabp_st_iterate(gabp_st_ctx *ctx, int32_t n_iters, double damping);
 
 /* FP64 residual ||A mu - b||_2 of the posterior mean (rel: divided by
- * ||b||_2).  Either pointer may be NULL.  Synchronises. */
+ * ||b||_2).  Either pointer may be NULL.  Synchronises.  Also runs the freeze
+ * test of the precision messages (gabp_st_set_freeze_tolerance). */
 gabp_status gabp_st_residual(gabp_st_ctx *ctx, double *rel_residual, double *abs_residual);
 
 /* Iterate until the relative residual is <= rel_tol (OK), max_iters
@@ -106,6 +107,21 @@ gabp_status gabp_st_posterior(gabp_st_ctx *ctx, double *mean, double *var);
  * sender are zero.  Device arrays of 38*nx*ny*nt values of the message
  * dtype.  Asynchronous. */
 gabp_status gabp_st_get_messages(gabp_st_ctx *ctx, void *prec, void *info);
+
+/* Freeze tolerance of the precision messages (as gabp_set_freeze_tolerance):
+ * the precision recursion involves neither the information messages nor the
+ * data, so once an iteration leaves every precision message unchanged (tested
+ * at each gabp_st_residual after the first iteration), later iterations store
+ * the edge gains once and update only the information messages -- bitwise
+ * the same results, 12 instead of 16 bytes per FP32 edge.  With max_slots > 0
+ * the precisions also freeze when at most max_slots of them changed, each by
+ * at most max_rel relative to the larger value (both buffers then keep the
+ * current precisions).  INVALID for max_slots < 0 or a negative or
+ * non-finite max_rel. */
+gabp_status gabp_st_set_freeze_tolerance(gabp_st_ctx *ctx, int64_t max_slots, double max_rel);
+
+/* Iteration at which the precision messages froze, or -1. */
+gabp_status gabp_st_precision_frozen(gabp_st_ctx *ctx, int64_t *frozen_at);
 
 /* Iterations run so far and the first invalid iteration (0: none).
  * Synchronises. */

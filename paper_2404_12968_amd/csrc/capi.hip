@@ -950,6 +950,31 @@ gabp_status gabp_upscale_precisions(gabp_ctx *coarse, float *pred, int64_t nxf, 
     return GABP_OK;
 }
 
+gabp_status gabp_copy_coarse_messages(gabp_ctx *coarse, gabp_ctx *fine) {
+    gabp_status st = ctx_ok(coarse);
+    if (st != GABP_OK) return st;
+    if (!fine) return fail(coarse, GABP_E_INVALID, "fine is NULL");
+    if (fine->device != coarse->device || fine->dtype != coarse->dtype ||
+        fine->L.alpha != coarse->L.alpha || fine->L.bcx != coarse->L.bcx ||
+        fine->L.bcy != coarse->L.bcy)
+        return fail(coarse, GABP_E_INVALID,
+                    "copy_coarse_messages: contexts differ in device, dtype, alpha or boundary");
+    if ((fine->L.nx + 1) / 2 != coarse->L.nx || (fine->L.ny + 1) / 2 != coarse->L.ny)
+        return fail(coarse, GABP_E_INVALID,
+                    "copy_coarse_messages: need ceil(nx_fine / 2) = nx and ceil(ny_fine / 2) = ny "
+                    "of the coarse context");
+    if (fine->diverged) return fail(coarse, GABP_E_DIVERGED, "the fine run has diverged");
+    // the fine context's stream waits for the coarse messages
+    GABP_HIP(coarse, hipStreamSynchronize(coarse->stream));
+    GABP_HIP(coarse, gabp::launch_copy_coarse(coarse->dtype == GABP_F32 ? 0 : 1, coarse->L,
+                                              cur_msgs(coarse), fine->L, fine->msg[fine->cur],
+                                              fine->stream));
+    fine->prev_valid = false;
+    fine->frozen = false;
+    fine->frozen_at = -1;
+    return GABP_OK;
+}
+
 gabp_status gabp_warm_init(gabp_ctx *ctx, const float *pred, int32_t keep_precisions) {
     gabp_status st = ctx_ok(ctx);
     if (st != GABP_OK) return st;

@@ -74,6 +74,9 @@ hipError_t launch_setup(int dtype, const Lattice &L, int64_t nobs, const int64_t
 // Multigrid: bilinear upsampling of a coarse mean into a prediction.
 hipError_t launch_upscale_prec(int dtype, const Lattice &Lc, const void *m, float scale,
                                float *pred, int nxf, int nyf, hipStream_t s);
+// Multigrid: the coarse messages copied unchanged onto the fine grid.
+hipError_t launch_copy_coarse(int dtype, const Lattice &Lc, const void *mc, const Lattice &Lf,
+                              void *mf, hipStream_t s);
 hipError_t launch_upsample_mean(const double *coarse, int nxc, int nyc, int perx, int pery,
                                 float *pred, int nxf, int nyf, hipStream_t s);
 // Message initialisation from a network prediction (net.hip).

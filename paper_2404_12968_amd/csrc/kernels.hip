@@ -395,6 +395,40 @@ __global__ __launch_bounds__(256) void k_upscale_prec(Lattice Lc, const T *__res
     }
 }
 
+// The paper's Upscale Messages taken literally: every message of the fine
+// grid (both components, sender-indexed plane d at fine node (x, y)) starts
+// as the coarse grid's message from the covering node (x/2, y/2) in the same
+// direction (the opposite one where the coarse node has none in that
+// direction, zero where it has neither), unscaled.  Slots whose fine
+// neighbour does not exist stay zero.
+template <typename T, int ALPHA>
+__global__ __launch_bounds__(256) void k_copy_coarse(Lattice Lc, const T *__restrict__ mc,
+                                                     Lattice Lf, T *__restrict__ mf) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long)Lf.nx * Lf.ny) return;
+    const int x = (int)(p % Lf.nx), y = (int)(p / Lf.nx);
+    const int xc = min(x >> 1, Lc.nx - 1), yc = min(y >> 1, Lc.ny - 1);
+    const size_t ic = (size_t)yc * Lc.pitch + xc;
+    const size_t i = (size_t)y * Lf.pitch + x;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        int xn, yn;
+        T l = (T)0, th = (T)0;
+        if (neighbour(Lf, x, y, d, xn, yn)) {
+            int src = -1;
+            if (neighbour(Lc, xc, yc, d, xn, yn)) src = d;
+            else if (neighbour(Lc, xc, yc, d ^ 1, xn, yn)) src = d ^ 1;
+            if (src >= 0) {
+                l = (mc + (size_t)src * Lc.plane)[ic];
+                th = (mc + (size_t)(DEG + src) * Lc.plane)[ic];
+            }
+        }
+        (mf + (size_t)d * Lf.plane)[i] = l;
+        (mf + (size_t)(DEG + d) * Lf.plane)[i] = th;
+    }
+}
+
 __global__ void k_set_u32(uint32_t *p, uint32_t v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -553,6 +587,24 @@ hipError_t launch_upscale_prec(int dtype, const Lattice &Lc, const void *m, floa
             hipLaunchKernelGGL((k_upscale_prec<double, 1>), grid, block, 0, s, Lc, (const double *)m, scale, pred, nxf, nyf);
         else
             hipLaunchKernelGGL((k_upscale_prec<double, 2>), grid, block, 0, s, Lc, (const double *)m, scale, pred, nxf, nyf);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_coarse(int dtype, const Lattice &Lc, const void *mc, const Lattice &Lf,
+                              void *mf, hipStream_t s) {
+    const long n = (long)Lf.nx * Lf.ny;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (dtype == 0) {
+        if (Lc.alpha == 1)
+            hipLaunchKernelGGL((k_copy_coarse<float, 1>), grid, block, 0, s, Lc, (const float *)mc, Lf, (float *)mf);
+        else
+            hipLaunchKernelGGL((k_copy_coarse<float, 2>), grid, block, 0, s, Lc, (const float *)mc, Lf, (float *)mf);
+    } else {
+        if (Lc.alpha == 1)
+            hipLaunchKernelGGL((k_copy_coarse<double, 1>), grid, block, 0, s, Lc, (const double *)mc, Lf, (double *)mf);
+        else
+            hipLaunchKernelGGL((k_copy_coarse<double, 2>), grid, block, 0, s, Lc, (const double *)mc, Lf, (double *)mf);
     }
     return hipGetLastError();
 }

@@ -27,13 +27,9 @@
 // precisions in planes 0..37 and information in planes 38..75.  A node's
 // plane index is n * slice + y * pitch + x with slice = pitch * ny.
 //
-// Launch shape.  A workgroup of 64 x 4 threads owns one 64 x 4 tile of a
-// band of kChunk consecutive slices and walks them in order, so the
-// messages a slice reads from its successor (and writes for it) are touched
-// again by the same workgroup one step later, while they sit in L2.
-// Workgroups are ordered tile-row-major within a band and band by band, and
-// remapped so that each XCD runs a contiguous range: vertically adjacent
-// tiles, which share their two-row halos, run side by side on one L2.
+// Launch shape.  A workgroup of 64 x 4 threads owns one 64 x 4 tile of one
+// slice; the workgroup order (wg_tile) keeps the tiles that share halo rows
+// and slices on one XCD at nearly the same time.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -44,8 +40,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "gabp_st.h"
+#include "host_common.h"
 #include "internal.h"
 #include "lattice.h"
 #include "numerics.h"
@@ -56,7 +54,6 @@ namespace gabp {
 namespace st {
 
 constexpr int kDeg = 38;
-constexpr int kChunk = 8;           // slices per workgroup in the iteration kernel
 constexpr int kPartials = 2048;     // workgroups of the residual reduction
 
 // Direction tables: d < 12 lie in the slice (the lattice directions of
@@ -82,7 +79,6 @@ __host__ __device__ constexpr int scls(int d) {
 struct Grid {
     int32_t nx, ny, nt, pitch;
     int32_t bcx, bcy, tiles_x, tiles_y;
-    int32_t chunks;             // bands of kChunk slices
     int64_t slice;              // elements between slices (pitch * ny)
     int64_t plane;              // elements between planes
     double blk[4][3];           // (p, q, r) of blocks: slice 0, middle, last, coupling
@@ -145,114 +141,279 @@ __device__ __forceinline__ T q_over_c(const Grid &G, int d, int kind, T gi, int 
 //   for each neighbour j: Lam_c = Lam_i - Lam_{j->i}, th_c = th_i - th_{j->i},
 //   g = -(Q_ij/c)/Lam_c, new (g Q_ij/c, g th_c), damped with the previous
 //   outgoing message (Appendix "Re-weighted message updates"; Section
-//   "Update Damping").  INTERIOR: every neighbour exists (radius-2 spatial
-//   halo inside the grid, a slice on either side).
+//   "Update Damping").
+// INTERIOR: every neighbour exists (radius-2 spatial halo inside the grid, a
+// slice on either side) and needs no test.  Otherwise the code stays
+// branch-free: a missing neighbour's address is clamped to the node itself,
+// its message is read as zero, and its outgoing slot is written as zero.
 // --------------------------------------------------------------------------
-template <typename T, bool INTERIOR>
-__device__ __forceinline__ void iter_node(const Grid &G, const T *__restrict__ m_in,
-                                          T *__restrict__ m_out, const T *__restrict__ aw,
-                                          const T *__restrict__ bw, T eta, bool &bad, int x,
-                                          int y, int t) {
-    const uint32_t i = (uint32_t)((int64_t)t * G.slice + (int64_t)y * G.pitch + x);
-    T lin[kDeg], tin[kDeg];
-    bool ok[kDeg];
+// v in [-2, n + 1] wrapped onto [0, n) without branches
+__device__ __forceinline__ int wrap(int v, int n) {
+    return v + n * ((int)(v < 0) - (int)(v >= n));
+}
+
+// Boundary handling is compile-time: PX / PY say whether an axis is periodic.
+template <bool PX, bool PY>
+__device__ __forceinline__ bool nbr_at(const Grid &G, int d, int x, int y, int t, int &xn,
+                                       int &yn, int &tn) {
+    xn = x + sdx(d);
+    yn = y + sdy(d);
+    tn = t + sdt(d);
+    if (PX && sdx(d) != 0) xn = wrap(xn, G.nx);
+    if (PY && sdy(d) != 0) yn = wrap(yn, G.ny);
+    bool ok = (unsigned)tn < (unsigned)G.nt;
+    if (!PX) ok = ok && (unsigned)xn < (unsigned)G.nx;
+    if (!PY) ok = ok && (unsigned)yn < (unsigned)G.ny;
+    return ok;
+}
+
+template <bool PX, bool PY>
+__device__ __forceinline__ int g_at(const Grid &G, int x, int y) {
+    return (PX ? 2 : (int)(x > 0) + (int)(x < G.nx - 1)) + (PY ? 2 : (int)(y > 0) + (int)(y < G.ny - 1));
+}
+
+// Plane index of neighbour d of (x, y, t) and whether it exists (a missing
+// neighbour's index is the node's own, so every load stays in bounds).
+template <bool INTERIOR, bool PX, bool PY>
+__device__ __forceinline__ uint32_t nbr_index(const Grid &G, int d, int x, int y, int t,
+                                              bool &ok) {
+    int xn, yn, tn;
+    if (INTERIOR) {
+        xn = x + sdx(d);
+        yn = y + sdy(d);
+        tn = t + sdt(d);
+        ok = true;
+    } else {
+        ok = nbr_at<PX, PY>(G, d, x, y, t, xn, yn, tn);
+        xn = ok ? xn : x;
+        yn = ok ? yn : y;
+        tn = ok ? tn : t;
+    }
+    return (uint32_t)tn * (uint32_t)G.slice + (uint32_t)(yn * G.pitch + xn);
+}
+
+// Incoming messages of one component (0: precisions, 1: information), zero
+// where the sender does not exist; bit d of okm says whether it does.
+template <typename T, bool INTERIOR, bool PX, bool PY>
+__device__ __forceinline__ void gather_in(const Grid &G, const T *__restrict__ m, int comp, int x,
+                                          int y, int t, T *v, uint64_t &okm) {
+    okm = 0;
 #pragma unroll
     for (int d = 0; d < kDeg; ++d) {
-        int xn, yn, tn;
-        if (INTERIOR) {
-            xn = x + sdx(d);
-            yn = y + sdy(d);
-            tn = t + sdt(d);
-            ok[d] = true;
-        } else {
-            ok[d] = nbr(G, x, y, t, d, xn, yn, tn);
-            if (!ok[d]) {
-                xn = x;
-                yn = y;
-                tn = t;
-            }
-        }
-        const uint32_t j = (uint32_t)((int64_t)tn * G.slice + (int64_t)yn * G.pitch + xn);
-        lin[d] = (m_in + (size_t)(d ^ 1) * G.plane)[j];
-        tin[d] = (m_in + (size_t)(kDeg + (d ^ 1)) * G.plane)[j];
+        bool ok;
+        const uint32_t j = nbr_index<INTERIOR, PX, PY>(G, d, x, y, t, ok);
+        const T val = (m + (size_t)(comp * kDeg + (d ^ 1)) * G.plane)[j];
+        v[d] = ok ? val : (T)0;
+        okm |= (uint64_t)ok << d;
     }
-    const T a = aw[i], b = bw[i];
-    if (!INTERIOR) {
+}
+
+// Both components at once (the full iteration): same values as two
+// gather_in calls.
+template <typename T, bool INTERIOR, bool PX, bool PY>
+__device__ __forceinline__ void gather_both(const Grid &G, const T *__restrict__ m, int x, int y,
+                                            int t, T *lv, T *tv, uint64_t &okm) {
+    okm = 0;
+#pragma unroll
+    for (int d = 0; d < kDeg; ++d) {
+        bool ok;
+        const uint32_t j = nbr_index<INTERIOR, PX, PY>(G, d, x, y, t, ok);
+        const T l = (m + (size_t)(d ^ 1) * G.plane)[j];
+        const T th = (m + (size_t)(kDeg + (d ^ 1)) * G.plane)[j];
+        lv[d] = ok ? l : (T)0;
+        tv[d] = ok ? th : (T)0;
+        okm |= (uint64_t)ok << d;
+    }
+}
+
+// Belief parameter: a + c * sum_d v[d], summed in direction order.
+template <typename T>
+__device__ __forceinline__ T belief(T a, const T *v, T c) {
+    T s = 0;
+#pragma unroll
+    for (int d = 0; d < kDeg; ++d) s += v[d];
+    return fmadd(c, s, a);
+}
+
+// Q_ij / c for direction d (closed forms at the top of this file); gi is
+// the node's neighbour count, pq_same / pq_cross the slice's blocks.
+template <typename T, bool INTERIOR, bool PX, bool PY>
+__device__ __forceinline__ T q_dir(const Grid &G, int d, int x, int y, int t, T gi,
+                                   const T *pq_same, const T *pq_cross) {
+    T gj = (T)4;
+    if (!INTERIOR && scls(d) == 1) {
+        int xn, yn, tn;
+        (void)nbr_at<PX, PY>(G, d, x, y, t, xn, yn, tn);
+        gj = (T)g_at<PX, PY>(G, xn, yn);
+    }
+    const T *pqr = d < 12 ? pq_same : pq_cross;
+    T q;
+    if (scls(d) == 0) q = pqr[0] + pqr[1] * gi + pqr[2] * (gi * gi + gi);
+    else if (scls(d) == 1) q = -pqr[1] - pqr[2] * (gi + gj);
+    else if (scls(d) == 2) q = pqr[2];
+    else q = pqr[2] + pqr[2];
+    return q * (T)G.inv_c;
+}
+
+// --------------------------------------------------------------------------
+// Frozen precision messages.  The precision recursion involves neither the
+// information messages nor the data, so once one iteration leaves every
+// precision message unchanged, all later ones do too.  The edge gains
+// g = -(Q_ij/c)/Lam_c are then stored once (MODE_GAIN) and the iteration
+// updates only the information messages (MODE_THETA):
+//   th_i = b_i + c sum_d th_{k->i},  out_d = (1 - eta) out_d + eta g_d (th_i - th_{j->i}).
+// All three modes share gather_in, belief and q_dir, so the information-only
+// iteration is bitwise the full one's.
+// --------------------------------------------------------------------------
+enum { MODE_FULL = 0, MODE_GAIN = 1, MODE_THETA = 2 };
+
+template <typename T, int MODE, bool INTERIOR, bool PX, bool PY>
+__device__ __forceinline__ void st_node(const Grid &G, const T *__restrict__ m_in,
+                                        T *__restrict__ m_out, T *__restrict__ gain,
+                                        const T *__restrict__ aw, const T *__restrict__ bw,
+                                        T eta, const T *pq_same, const T *pq_cross, bool &bad,
+                                        int x, int y, int t) {
+    const uint32_t i = (uint32_t)t * (uint32_t)G.slice + (uint32_t)(y * G.pitch + x);
+    const T c = (T)G.c, keep = (T)1 - eta;
+    const T gi = INTERIOR ? (T)4 : (T)g_at<PX, PY>(G, x, y);
+    uint64_t okm;
+    if constexpr (MODE == MODE_FULL) {
+        T lin[kDeg], tin[kDeg];
+        gather_both<T, INTERIOR, PX, PY>(G, m_in, x, y, t, lin, tin, okm);
+        const T bl = belief(aw[i], lin, c);
+        const T bt = belief(bw[i], tin, c);
 #pragma unroll
         for (int d = 0; d < kDeg; ++d) {
-            lin[d] = ok[d] ? lin[d] : (T)0;
-            tin[d] = ok[d] ? tin[d] : (T)0;
+            const T q = q_dir<T, INTERIOR, PX, PY>(G, d, x, y, t, gi, pq_same, pq_cross);
+            const T lc = bl - lin[d];
+            const T tc = bt - tin[d];
+            const T g = edge_gain(q, lc);
+            const T ol = (m_in + (size_t)d * G.plane)[i];
+            const T ot = (m_in + (size_t)(kDeg + d) * G.plane)[i];
+            T dl = fmadd(eta, g * q, keep * ol);
+            T dt = fmadd(eta, g * tc, keep * ot);
+            const bool ok = INTERIOR || ((okm >> d) & 1u);
+            bad |= ok && (!(lc > (T)0) || !isfinite(dl) || !isfinite(dt));
+            dl = ok ? dl : (T)0;
+            dt = ok ? dt : (T)0;
+            (m_out + (size_t)d * G.plane)[i] = dl;
+            (m_out + (size_t)(kDeg + d) * G.plane)[i] = dt;
         }
-    }
-    T sl = 0, st = 0;
+    } else if constexpr (MODE == MODE_GAIN) {
+        T lin[kDeg];
+        gather_in<T, INTERIOR, PX, PY>(G, m_in, 0, x, y, t, lin, okm);
+        const T bl = belief(aw[i], lin, c);
 #pragma unroll
-    for (int d = 0; d < kDeg; ++d) {
-        sl += lin[d];
-        st += tin[d];
-    }
-    const T c = (T)G.c, keep = (T)1 - eta;
-    const T bl = fmadd(c, sl, a);
-    const T bt = fmadd(c, st, b);
-    const int kind = INTERIOR ? 1 : slice_kind(G, t);
-    const T gi = (T)(axis_g(x, G.nx, G.bcx) + axis_g(y, G.ny, G.bcy));
-#pragma unroll
-    for (int d = 0; d < kDeg; ++d) {
-        if (!INTERIOR && !ok[d]) continue;
-        int xn = x + sdx(d), yn = y + sdy(d);
-        if (!INTERIOR) {
-            if (G.bcx == BC_PERIODIC) xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
-            if (G.bcy == BC_PERIODIC) yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
+        for (int d = 0; d < kDeg; ++d) {
+            const T q = q_dir<T, INTERIOR, PX, PY>(G, d, x, y, t, gi, pq_same, pq_cross);
+            const T g = edge_gain(q, bl - lin[d]);
+            const bool ok = INTERIOR || ((okm >> d) & 1u);
+            (gain + (size_t)d * G.plane)[i] = ok ? g : (T)0;
         }
-        const T q = q_over_c<T>(G, d, kind, gi, xn, yn);
-        const T lc = bl - lin[d];
-        const T tc = bt - tin[d];
-        const T g = edge_gain(q, lc);
-        const T ol = (m_in + (size_t)d * G.plane)[i];
-        const T ot = (m_in + (size_t)(kDeg + d) * G.plane)[i];
-        const T dl = fmadd(eta, g * q, keep * ol);
-        const T dt = fmadd(eta, g * tc, keep * ot);
-        bad |= !(lc > (T)0) || !isfinite(dl) || !isfinite(dt);
-        (m_out + (size_t)d * G.plane)[i] = dl;
-        (m_out + (size_t)(kDeg + d) * G.plane)[i] = dt;
+    } else {
+        T tin[kDeg];
+        gather_in<T, INTERIOR, PX, PY>(G, m_in, 1, x, y, t, tin, okm);
+        const T bt = belief(bw[i], tin, c);
+#pragma unroll
+        for (int d = 0; d < kDeg; ++d) {
+            const T g = (gain + (size_t)d * G.plane)[i];
+            const T ot = (m_in + (size_t)(kDeg + d) * G.plane)[i];
+            T dt = fmadd(eta, g * (bt - tin[d]), keep * ot);
+            const bool ok = INTERIOR || ((okm >> d) & 1u);
+            bad |= ok && !isfinite(dt);
+            dt = ok ? dt : (T)0;
+            (m_out + (size_t)(kDeg + d) * G.plane)[i] = dt;
+        }
     }
 }
 
-// Workgroup -> (tile x, tile y, band of slices).
-__device__ __forceinline__ void wg_tile(const Grid &G, int &tx, int &ty, int &band) {
+// Workgroup -> (tile x, tile y, slice).  One slice per workgroup.  Tiles are
+// grouped in bands of kGroupRows tile rows; within a band the order is slice
+// by slice, each slice row by row.  With the XCD remap each XCD runs a
+// contiguous range of this order, so a tile's vertical neighbours (same
+// slice) are at most a few tile rows away and its slice neighbours one
+// band-slice (tiles_x * kGroupRows workgroups) away: both halos are read
+// while still in L2.
+constexpr int kGroupRows = 4;
+
+__device__ __forceinline__ void wg_tile(const Grid &G, int &tx, int &ty, int &t) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int per_band = G.tiles_x * G.tiles_y;
-    band = b / per_band;
-    const int r = b - band * per_band;
-    ty = r / G.tiles_x;
-    tx = r - ty * G.tiles_x;
+    const int full = kGroupRows * G.tiles_x * G.nt;         // workgroups of a full band
+    const int g = b / full;
+    const int r = b - g * full;
+    const int hg = min(kGroupRows, G.tiles_y - g * kGroupRows);   // tile rows of this band
+    const int per_slice = hg * G.tiles_x;
+    t = r / per_slice;
+    const int r2 = r - t * per_slice;
+    const int tyi = r2 / G.tiles_x;
+    tx = r2 - tyi * G.tiles_x;
+    ty = g * kGroupRows + tyi;
 }
 
-// The iteration.  diverged_at[0] records the first iteration whose launch
-// met an invalid value; launches of later iterations return at once (the
-// launch that met it completes, so its output buffer holds that iteration).
-template <typename T>
+// One launch of a mode over the whole grid.  diverged_at[0] records the
+// first iteration whose launch met an invalid value; launches of later
+// iterations return at once (the launch that met it completes, so its output
+// buffer holds that iteration).  MODE_GAIN passes it = 0.
+template <typename T, int MODE, bool PX, bool PY>
 __global__ __launch_bounds__(256) void k_iter(Grid G, const T *__restrict__ m_in,
-                                              T *__restrict__ m_out, const T *__restrict__ aw,
-                                              const T *__restrict__ bw, T eta,
-                                              uint32_t *__restrict__ diverged_at, uint32_t it) {
+                                              T *__restrict__ m_out, T *__restrict__ gain,
+                                              const T *__restrict__ aw, const T *__restrict__ bw,
+                                              T eta, uint32_t *__restrict__ diverged_at,
+                                              uint32_t it) {
     const uint32_t seen = *diverged_at;
-    if (seen != 0u && seen < it) return;
-    int tx, ty, band;
-    wg_tile(G, tx, ty, band);
+    if (MODE != MODE_GAIN && seen != 0u && seen < it) return;
+    int tx, ty, t;
+    wg_tile(G, tx, ty, t);
     const int x = tx * 64 + (int)(threadIdx.x & 63u);
     const int y = ty * 4 + (int)(threadIdx.x >> 6);
-    const bool inner_xy = tx * 64 >= 2 && tx * 64 + 66 <= G.nx && ty * 4 >= 2 &&
-                          ty * 4 + 6 <= G.ny;
-    const int t0 = band * kChunk, t1 = min(G.nt, t0 + kChunk);
+    // the slice's blocks (uniform over the workgroup) in message precision
+    const int kind = slice_kind(G, t);
+    const T pq_same[3] = {(T)G.blk[kind][0], (T)G.blk[kind][1], (T)G.blk[kind][2]};
+    const T pq_cross[3] = {(T)G.blk[3][0], (T)G.blk[3][1], (T)G.blk[3][2]};
+    const bool inner = tx * 64 >= 2 && tx * 64 + 66 <= G.nx && ty * 4 >= 2 &&
+                       ty * 4 + 6 <= G.ny && t > 0 && t < G.nt - 1;
     bool bad = false;
-#pragma unroll 1
-    for (int t = t0; t < t1; ++t) {
-        if (inner_xy && t > 0 && t < G.nt - 1)
-            iter_node<T, true>(G, m_in, m_out, aw, bw, eta, bad, x, y, t);
-        else if (x < G.nx && y < G.ny)
-            iter_node<T, false>(G, m_in, m_out, aw, bw, eta, bad, x, y, t);
+    if (inner)
+        st_node<T, MODE, true, PX, PY>(G, m_in, m_out, gain, aw, bw, eta, pq_same, pq_cross, bad,
+                                       x, y, t);
+    else if (x < G.nx && y < G.ny)
+        st_node<T, MODE, false, PX, PY>(G, m_in, m_out, gain, aw, bw, eta, pq_same, pq_cross,
+                                        bad, x, y, t);
+    if (MODE != MODE_GAIN && bad) atomicCAS(diverged_at, 0u, it);
+}
+
+// Precision messages changed between two buffers: count of bitwise
+// differences (64-bit) and the largest relative change |a - b| / max(|a|,
+// |b|) as float bits (non-negative floats order like their bit patterns).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prec_change(const T *__restrict__ a,
+                                                     const T *__restrict__ b, int64_t n,
+                                                     unsigned long long *__restrict__ count,
+                                                     uint32_t *__restrict__ maxrel_bits) {
+    uint32_t cnt = 0;
+    float mx = 0.0f;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * 256) {
+        const T u = a[k], v = b[k];
+        using U = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+        U ub, vb;
+        __builtin_memcpy(&ub, &u, sizeof(T));
+        __builtin_memcpy(&vb, &v, sizeof(T));
+        if (ub != vb) {
+            ++cnt;
+            const double den = fmax(fabs((double)u), fabs((double)v));
+            const float r = den > 0.0 ? (float)(fabs((double)u - (double)v) / den) : INFINITY;
+            mx = fmaxf(mx, isnan(r) ? INFINITY : r);
+        }
     }
-    if (bad) atomicCAS(diverged_at, 0u, it);
+    for (int o = 32; o >= 1; o >>= 1) {
+        cnt += __shfl_xor(cnt, o, 64);
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    if ((threadIdx.x & 63u) == 0u && cnt != 0u) {
+        atomicAdd(count, (unsigned long long)cnt);
+        atomicMax(maxrel_bits, __float_as_uint(mx));
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -424,6 +585,10 @@ __global__ __launch_bounds__(256) void k_msgs_get(Grid G, const T *__restrict__ 
     }
 }
 
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
 }  // namespace st
 }  // namespace gabp
 
@@ -440,7 +605,7 @@ struct Layout {
     int32_t pitch = 0;
     int64_t slice = 0, plane = 0, node_elems = 0;
     size_t msg[2] = {0, 0};
-    size_t adiag64 = 0, b64 = 0, mu64 = 0, aw = 0, bw = 0;
+    size_t gain = 0, adiag64 = 0, b64 = 0, mu64 = 0, aw = 0, bw = 0;
     size_t partials = 0, red = 0, flags = 0, total = 0;
 };
 
@@ -462,6 +627,7 @@ Layout make_layout(const gabp_st_model &m, size_t esize) {
     const size_t buf = (size_t)(2 * gabp::st::kDeg) * (size_t)l.plane * esize;
     l.msg[0] = take(buf);
     l.msg[1] = take(buf);
+    l.gain = take(buf / 2);
     const size_t n8 = (size_t)l.node_elems * 8;
     l.adiag64 = take(n8);
     l.b64 = take(n8);
@@ -527,13 +693,20 @@ struct gabp_st_ctx {
     void *msg[2] = {nullptr, nullptr};
     double *adiag64 = nullptr, *b64 = nullptr, *mu64 = nullptr;
     void *aw = nullptr, *bw = nullptr;
+    void *gain = nullptr;         // edge gains once the precision messages froze
     double *partials = nullptr, *red = nullptr;
-    uint32_t *flags = nullptr;    // [0] diverged-at iteration, [1] input error
+    uint32_t *flags = nullptr;    // [0] diverged-at iteration, [1] input error,
+                                  // [4, 5] precision messages changed by the last
+                                  // iteration (64-bit), [6] their largest relative change
     uint32_t *host_flags = nullptr;   // pinned mirrors
     double *host_red = nullptr;
     int cur = 0;
     int64_t iter = 0;
     int64_t diverged_at = 0;
+    bool frozen = false;
+    int64_t frozen_at = -1;
+    int64_t freeze_slots = 0;     // freeze tolerance (0: bitwise only)
+    double freeze_rel = 0.0;
     std::string err;
 };
 
@@ -575,6 +748,30 @@ gabp_status st_sync(gabp_st_ctx *ctx) {
                        "non-positive cavity precision or non-finite message at iteration " +
                            std::to_string(ctx->diverged_at));
     return GABP_OK;
+}
+
+template <typename T, int MODE>
+void launch_mode(const Grid &G, const void *in, void *out, void *gain, const void *aw,
+                 const void *bw, T eta, uint32_t *flags, uint32_t it, hipStream_t s) {
+    const dim3 grid((unsigned)(G.tiles_x * G.tiles_y * G.nt)), block(256);
+    const bool px = G.bcx == GABP_BC_PERIODIC, py = G.bcy == GABP_BC_PERIODIC;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, s, G, (const T *)in, (T *)out, (T *)gain,
+                           (const T *)aw, (const T *)bw, eta, flags, it);
+    };
+    if (px && py) go(gabp::st::k_iter<T, MODE, true, true>);
+    else if (px) go(gabp::st::k_iter<T, MODE, true, false>);
+    else if (py) go(gabp::st::k_iter<T, MODE, false, true>);
+    else go(gabp::st::k_iter<T, MODE, false, false>);
+}
+
+template <typename T>
+void launch_any(int mode, const Grid &G, const void *in, void *out, void *gain, const void *aw,
+                const void *bw, T eta, uint32_t *flags, uint32_t it, hipStream_t s) {
+    using namespace gabp::st;
+    if (mode == MODE_FULL) launch_mode<T, MODE_FULL>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else if (mode == MODE_GAIN) launch_mode<T, MODE_GAIN>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else launch_mode<T, MODE_THETA>(G, in, out, gain, aw, bw, eta, flags, it, s);
 }
 
 unsigned node_blocks(const Grid &G) {
@@ -645,13 +842,12 @@ gabp_status gabp_st_create(const gabp_st_model *model, const gabp_obs *obs,
     G.bcy = model->bc_y;
     G.tiles_x = (model->nx + 63) / 64;
     G.tiles_y = (model->ny + 3) / 4;
-    G.chunks = (model->nt + gabp::st::kChunk - 1) / gabp::st::kChunk;
     G.slice = l.slice;
     G.plane = l.plane;
     block_coefficients(*model, G.blk, G.lsq);
     G.c = model->c;
     G.inv_c = 1.0 / model->c;
-    if ((int64_t)G.tiles_x * G.tiles_y * G.chunks >= INT32_MAX) {
+    if ((int64_t)G.tiles_x * G.tiles_y * G.nt >= INT32_MAX) {
         ctx->err = "grid too large for one launch";
         return bail(GABP_E_INVALID);
     }
@@ -671,6 +867,7 @@ gabp_status gabp_st_create(const gabp_st_model *model, const gabp_obs *obs,
     ctx->mu64 = (double *)(ctx->ws + l.mu64);
     ctx->aw = esize == 4 ? (void *)(ctx->ws + l.aw) : (void *)ctx->adiag64;
     ctx->bw = esize == 4 ? (void *)(ctx->ws + l.bw) : (void *)ctx->b64;
+    ctx->gain = ctx->ws + l.gain;
     ctx->partials = (double *)(ctx->ws + l.partials);
     ctx->red = (double *)(ctx->ws + l.red);
     ctx->flags = (uint32_t *)(ctx->ws + l.flags);
@@ -752,18 +949,16 @@ gabp_status gabp_st_iterate(gabp_st_ctx *ctx, int32_t n_iters, double damping) {
     if (ctx->iter + n_iters >= (int64_t)UINT32_MAX)
         return st_fail(ctx, GABP_E_INVALID, "iteration count would exceed 2^32 - 1");
     const Grid &G = ctx->G;
-    const dim3 grid((unsigned)(G.tiles_x * G.tiles_y * G.chunks)), block(256);
+    const int mode = ctx->frozen ? gabp::st::MODE_THETA : gabp::st::MODE_FULL;
     for (int32_t k = 0; k < n_iters; ++k) {
         const uint32_t it = (uint32_t)(ctx->iter + 1);
         void *in = ctx->msg[ctx->cur], *out = ctx->msg[ctx->cur ^ 1];
         if (ctx->dtype == GABP_F32)
-            hipLaunchKernelGGL((gabp::st::k_iter<float>), grid, block, 0, ctx->stream, G,
-                               (const float *)in, (float *)out, (const float *)ctx->aw,
-                               (const float *)ctx->bw, (float)damping, ctx->flags, it);
+            launch_any<float>(mode, G, in, out, ctx->gain, ctx->aw, ctx->bw, (float)damping,
+                              ctx->flags, it, ctx->stream);
         else
-            hipLaunchKernelGGL((gabp::st::k_iter<double>), grid, block, 0, ctx->stream, G,
-                               (const double *)in, (double *)out, (const double *)ctx->aw,
-                               (const double *)ctx->bw, damping, ctx->flags, it);
+            launch_any<double>(mode, G, in, out, ctx->gain, ctx->aw, ctx->bw, damping, ctx->flags,
+                               it, ctx->stream);
         ST_HIP(ctx, hipGetLastError());
         ctx->cur ^= 1;
         ctx->iter += 1;
@@ -800,6 +995,27 @@ gabp_status gabp_st_residual(gabp_st_ctx *ctx, double *rel_residual, double *abs
                        (const double *)ctx->b64, ctx->partials);
     hipLaunchKernelGGL(gabp::st::k_reduce, dim3(1), dim3(256), 0, ctx->stream,
                        (const double *)ctx->partials, nb, ctx->red);
+    // freeze probe: did the last iteration change any precision message?
+    // (the other buffer holds the previous iteration once one has run)
+    const bool probe = !ctx->frozen && ctx->iter >= 1;
+    if (probe) {
+        const int64_t n = (int64_t)gabp::st::kDeg * G.plane;
+        hipLaunchKernelGGL(gabp::st::k_zero_u32, dim3(1), dim3(64), 0, ctx->stream,
+                           ctx->flags + 4, 3);
+        const int pb = (int)std::min<int64_t>((n + 255) / 256, 4096);
+        if (ctx->dtype == GABP_F32)
+            hipLaunchKernelGGL(gabp::st::k_prec_change<float>, dim3(pb), dim3(256), 0,
+                               ctx->stream, (const float *)ctx->msg[ctx->cur],
+                               (const float *)ctx->msg[ctx->cur ^ 1], n,
+                               (unsigned long long *)(ctx->flags + 4), ctx->flags + 6);
+        else
+            hipLaunchKernelGGL(gabp::st::k_prec_change<double>, dim3(pb), dim3(256), 0,
+                               ctx->stream, (const double *)ctx->msg[ctx->cur],
+                               (const double *)ctx->msg[ctx->cur ^ 1], n,
+                               (unsigned long long *)(ctx->flags + 4), ctx->flags + 6);
+        ST_HIP(ctx, hipMemcpyAsync(ctx->host_flags, ctx->flags, 8 * sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+    }
     ST_HIP(ctx, hipGetLastError());
     ST_HIP(ctx, hipMemcpyAsync(ctx->host_red, ctx->red, 2 * sizeof(double),
                                hipMemcpyDeviceToHost, ctx->stream));
@@ -807,8 +1023,47 @@ gabp_status gabp_st_residual(gabp_st_ctx *ctx, double *rel_residual, double *abs
     const double a = std::sqrt(ctx->host_red[0]), nb2 = std::sqrt(ctx->host_red[1]);
     if (!std::isfinite(a))
         return st_fail(ctx, GABP_E_DIVERGED, "non-finite residual");
+    if (probe) {
+        uint64_t changed;
+        std::memcpy(&changed, ctx->host_flags + 4, sizeof changed);
+        if (gabp::host::freeze_now(changed, ctx->host_flags[6], ctx->freeze_slots,
+                                   ctx->freeze_rel)) {
+            // gains from the current precisions; both buffers keep them
+            if (ctx->dtype == GABP_F32)
+                launch_any<float>(gabp::st::MODE_GAIN, G, ctx->msg[ctx->cur], nullptr, ctx->gain,
+                                  ctx->aw, ctx->bw, 0.0f, ctx->flags, 0u, ctx->stream);
+            else
+                launch_any<double>(gabp::st::MODE_GAIN, G, ctx->msg[ctx->cur], nullptr,
+                                   ctx->gain, ctx->aw, ctx->bw, 0.0, ctx->flags, 0u, ctx->stream);
+            ST_HIP(ctx, hipGetLastError());
+            const size_t esize = ctx->dtype == GABP_F32 ? 4 : 8;
+            ST_HIP(ctx, hipMemcpyAsync(ctx->msg[ctx->cur ^ 1], ctx->msg[ctx->cur],
+                                       (size_t)gabp::st::kDeg * (size_t)G.plane * esize,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            ctx->frozen = true;
+            ctx->frozen_at = ctx->iter;
+        }
+    }
     if (abs_residual) *abs_residual = a;
     if (rel_residual) *rel_residual = nb2 > 0.0 ? a / nb2 : a;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_set_freeze_tolerance(gabp_st_ctx *ctx, int64_t max_slots, double max_rel) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (max_slots < 0 || !std::isfinite(max_rel) || max_rel < 0.0)
+        return st_fail(ctx, GABP_E_INVALID, "max_slots must be >= 0 and max_rel finite, >= 0");
+    ctx->freeze_slots = max_slots;
+    ctx->freeze_rel = max_rel;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_precision_frozen(gabp_st_ctx *ctx, int64_t *frozen_at) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (!frozen_at) return st_fail(ctx, GABP_E_INVALID, "frozen_at is NULL");
+    *frozen_at = ctx->frozen_at;
     return GABP_OK;
 }
 

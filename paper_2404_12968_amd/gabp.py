@@ -108,6 +108,7 @@ _SIGS = {
     "gabp_batch_upscale_precisions": ([_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_double], ctypes.c_int),
     "gabp_get_tile": ([_P, _P, _P], ctypes.c_int),
+    "gabp_copy_coarse_messages": ([_P, _P], ctypes.c_int),
     "gabp_upscale_precisions": ([_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double],
                                 ctypes.c_int),
     "gabp_upsample_mean": ([_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -139,6 +140,8 @@ _SIGS = {
     "gabp_st_posterior": ([_P, _P, _P], ctypes.c_int),
     "gabp_st_get_messages": ([_P, _P, _P], ctypes.c_int),
     "gabp_st_iteration_count": ([_P, _P, _P], ctypes.c_int),
+    "gabp_st_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
+    "gabp_st_precision_frozen": ([_P, _P], ctypes.c_int),
     "gabp_st_last_error": ([_P], ctypes.c_char_p),
     "gabp_st_destroy": ([_P], None),
 }
@@ -354,6 +357,11 @@ def gabp_precision_frozen(ctx: Context) -> int:
 
 def gabp_num_directions(ctx: Context) -> int:
     return ctx.deg
+
+
+def gabp_copy_coarse_messages(coarse: Context, fine: Context) -> None:
+    """The paper's Upscale Messages literally: fine messages = coarse ones."""
+    _check(_lib.gabp_copy_coarse_messages(coarse.handle, fine.handle), coarse)
 
 
 def gabp_destroy(ctx: Context) -> None:
@@ -806,6 +814,17 @@ def gabp_st_iteration_count(ctx: STContext) -> Tuple[int, int]:
     dv = ctypes.c_int64(0)
     _st_check(_lib.gabp_st_iteration_count(ctx.handle, ctypes.byref(it), ctypes.byref(dv)), ctx)
     return int(it.value), int(dv.value)
+
+
+def gabp_st_set_freeze_tolerance(ctx: STContext, max_slots: int, max_rel: float) -> None:
+    _st_check(_lib.gabp_st_set_freeze_tolerance(ctx.handle, int(max_slots), float(max_rel)), ctx)
+
+
+def gabp_st_precision_frozen(ctx: STContext) -> int:
+    """Iteration at which the precision messages froze, or -1."""
+    v = ctypes.c_int64(0)
+    _st_check(_lib.gabp_st_precision_frozen(ctx.handle, ctypes.byref(v)), ctx)
+    return int(v.value)
 
 
 def gabp_st_destroy(ctx: STContext) -> None:

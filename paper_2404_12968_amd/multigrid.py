@@ -14,7 +14,9 @@ coarser grid's, which it states the message copy is equivalent to.  With
 too, from the covering coarse node in the same direction, scaled by
 4^(alpha-1) (`gabp_upscale_precisions`: the prior's off-diagonal entries
 shrink by that factor per level); with `transfer="mean"` they start cold on
-every level.  A coarse level stops either at an FP64 relative residual
+every level; with `transfer="literal"` every edge value (both components)
+is copied unchanged from the covering coarse node, the paper's description
+read word for word (`gabp_copy_coarse_messages`).  A coarse level stops either at an FP64 relative residual
 (`coarse_stop="residual"`) or by the paper's early-stop rule of Appendix A
 (`"message_change"`: mean |m^t - m^(t-1)| below `coarse_tol` times the
 level's mean |m^2 - m^1|; the paper takes 1e-3).  The last level is solved to
@@ -84,8 +86,8 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
     if coarse_stop not in ("residual", "message_change") or \
             final_stop not in ("residual", "message_change"):
         raise ValueError("coarse_stop and final_stop are 'residual' or 'message_change'")
-    if transfer not in ("messages", "mean"):
-        raise ValueError("transfer is 'messages' or 'mean'")
+    if transfer not in ("messages", "mean", "literal"):
+        raise ValueError("transfer is 'messages', 'mean' or 'literal'")
     if levels is None:
         levels = max_levels(prob, coarsest=32)
     if coarse_tol is None:
@@ -95,6 +97,7 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
     pred: Optional[torch.Tensor] = None
     per_level: List[dict] = []
     ctx = None
+    coarse = None
     st = G.GABP_E_NOT_CONVERGED
     rel = float("inf")
     for lev in reversed(range(levels)):
@@ -102,6 +105,10 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
         ctx = G.gabp_create_problem(p, device=device)
         if freeze_tolerance is not None:
             G.gabp_set_freeze_tolerance(ctx, *freeze_tolerance)
+        if coarse is not None:
+            G.gabp_copy_coarse_messages(coarse, ctx)
+            G.gabp_destroy(coarse)
+            coarse = None
         if pred is not None:
             G.gabp_warm_init(ctx, pred, keep_precisions=(transfer == "mean"))
         if lev == 0 and final_stop == "message_change":
@@ -123,7 +130,9 @@ def multigrid_solve(prob: I.Problem, levels: Optional[int] = None,
                           "frozen_at": G.gabp_precision_frozen(ctx)})
         if st == G.GABP_E_DIVERGED:
             break
-        if lev > 0:
+        if lev > 0 and transfer == "literal":
+            coarse = ctx          # its messages are copied into the next level's context
+        elif lev > 0:
             mean, _ = G.gabp_posterior(ctx, want_var=False)
             fine = level_problem(prob, lev - 1)
             pred = G.gabp_upsample_mean(mean, p.bc_x, p.bc_y, fine.nx, fine.ny)

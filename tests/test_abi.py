@@ -117,8 +117,9 @@ def test_st_workspace_size_rejects_invalid(G, kw, msg):
 def test_st_workspace_size_of_the_space_time_workload(G):
     n = G.gabp_st_workspace_size(_st_model(G, nx=512, ny=512, nt=64), G.GABP_F32)
     nodes = 512 * 512 * 64
-    # two buffers of 76 FP32 planes, three FP64 and two FP32 node planes
-    assert 152 * 4 * nodes + 32 * nodes <= n <= 152 * 4 * nodes + 32 * nodes + (1 << 20) + 152 * 256
+    # two buffers of 76 FP32 planes, 38 gain planes, three FP64 and two FP32
+    # node planes
+    assert 190 * 4 * nodes + 32 * nodes <= n <= 190 * 4 * nodes + 32 * nodes + (1 << 20) + 190 * 256
 
 
 def test_st_create_rejects_host_observations_before_any_device_call(G):

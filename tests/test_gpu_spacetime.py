@@ -115,7 +115,7 @@ CASES = [
     (5, 6, 1, I.BC_NEUMANN, I.BC_NEUMANN, 0.3),         # one slice: the initial field alone
     (9, 5, 2, I.BC_NEUMANN, I.BC_NEUMANN, 0.3),         # first and last slice only
     (3, 4, 7, I.BC_NEUMANN, I.BC_NEUMANN, 0.3),         # grid narrower than the stencil
-    (130, 3, 4, I.BC_NEUMANN, I.BC_PERIODIC, 0.1),
+    (130, 5, 4, I.BC_NEUMANN, I.BC_PERIODIC, 0.1),     # shortest periodic axis
 ]
 
 
@@ -218,6 +218,69 @@ def test_invalid_device_observations_rejected(G):
     with pytest.raises(G.GabpError) as ei:
         G.gabp_st_create(G.st_model(prob), cells, prob.y, prob.sigma, dtype=G.GABP_F32)
     assert ei.value.status == G.GABP_E_INVALID
+
+
+# --------------------------------------------------------------------------
+# frozen precision messages: information-only iterations
+# --------------------------------------------------------------------------
+
+FREEZE_CASES = [
+    (70, 37, 5, I.BC_NEUMANN, I.BC_NEUMANN, "f64"),
+    (67, 9, 11, I.BC_PERIODIC, I.BC_NEUMANN, "f32"),
+    (13, 11, 9, I.BC_PERIODIC, I.BC_PERIODIC, "f64"),
+    (130, 40, 6, I.BC_NEUMANN, I.BC_PERIODIC, "f32"),
+]
+
+
+@pytest.mark.parametrize("case", FREEZE_CASES, ids=lambda c: "x".join(map(str, c[:3])) + c[5])
+def test_frozen_phase_is_bitwise_the_full_iteration(G, case):
+    """A context that checks its residual every 10 iterations freezes its
+    precision messages once they stop changing and then runs the
+    information-only kernel; a context that never checks runs the full
+    kernel throughout.  Both hold bitwise the same messages and marginals."""
+    nx, ny, nt, bcx, bcy, dtype = case
+    prob = I.small_spacetime(nx, ny, nt, bc_x=bcx, bc_y=bcy, frac=0.1, sigma=0.1,
+                             seed=nx + ny + nt, dtype=dtype)
+    a = G.gabp_st_create_problem(prob)
+    b = G.gabp_st_create_problem(prob)
+    for _ in range(150):
+        G.gabp_st_iterate(a, 10, prob.damping)
+        G.gabp_st_residual(a)
+        if G.gabp_st_precision_frozen(a) >= 0:
+            break
+    fz = G.gabp_st_precision_frozen(a)
+    print("frozen at", fz, flush=True)
+    assert fz > 0
+    G.gabp_st_iterate(a, 37, prob.damping)
+    it = G.gabp_st_iteration_count(a)[0]
+    G.gabp_st_iterate(b, it, prob.damping)
+    sa, sb = gpu_state(G, a), gpu_state(G, b)
+    for u, v in zip(sa, sb):
+        assert np.array_equal(u, v)
+    assert G.gabp_st_precision_frozen(b) == -1
+
+
+def test_freeze_tolerance_converges_to_the_direct_solve(G, S, oracle_mod):
+    """A context frozen within a tolerance reaches the residual tolerance and
+    is as close to the direct solve as a context frozen bitwise (or not at
+    all) at the same residual."""
+    prob = I.spacetime(nx=64, ny=48, nt=8, dtype="f32")
+    A, b = S.posterior_system(prob)
+    exact = oracle_mod.direct_solve(A, b)
+    errs = []
+    for slots in (64, 0):
+        ctx = G.gabp_st_create_problem(prob)
+        with pytest.raises(G.GabpError):
+            G.gabp_st_set_freeze_tolerance(ctx, -1, 1e-6)
+        G.gabp_st_set_freeze_tolerance(ctx, slots, 1e-6)
+        st, it, rel = G.gabp_st_solve(ctx, 50000, prob.damping, 1e-6, 50)
+        assert st == G.GABP_OK, (slots, st, it, rel)
+        if slots:
+            assert 0 < G.gabp_st_precision_frozen(ctx) < it
+        mu, _ = G.gabp_st_posterior(ctx, want_var=False)
+        errs.append(rel_l2(mu.cpu().numpy(), exact))
+    print("errors (tolerance, bitwise)", errs)
+    assert errs[0] <= 1.5 * errs[1] + 1e-6
 
 
 # --------------------------------------------------------------------------
