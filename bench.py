@@ -48,12 +48,17 @@ def edge_count(nx, ny, alpha, bcx, bcy):
     return total
 
 
-def kernel_source_digest():
+ITER_SOURCES = ("iter.hip", "iter_node.h", "pair_tile.h", "walk_strip.h", "numerics.h", "lattice.h")
+ST_SOURCES = ("spacetime.hip", "numerics.h", "lattice.h")
+ST_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "spacetime512x512x64_traffic.md")
+
+
+def kernel_source_digest(files=ITER_SOURCES):
     """Digest of the iteration kernels' source with // comments, trailing
     blanks and empty lines removed (a comment edit leaves it unchanged; the
     files hold no block comments and no // inside literals)."""
     h = hashlib.sha256()
-    for f in ("iter.hip", "iter_node.h", "pair_tile.h", "walk_strip.h", "numerics.h", "lattice.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2404_12968_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].rstrip()
@@ -62,20 +67,28 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
+def _summary_value(path, digest, key):
+    """A per-launch figure from a committed PMC summary, if that summary was
+    taken on the current kernel source (its digest line matches)."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
+    t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return float(t.group(1))
+
+
 def measured_traffic(phase, rpt, workload="global8192"):
     """HBM bytes per launch of the timed kernel (its tile shape) from the
     committed PMC summary of the 8192 x 4096 workload, if that was taken on
     the current kernel source."""
-    if workload != "global8192" or not os.path.exists(TRAFFIC_SUMMARY):
+    if workload != "global8192":
         return None
-    text = open(TRAFFIC_SUMMARY).read()
-    m = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
     shape = {"theta2": f"pair{rpt}", "theta2w": f"walk{-rpt}"}.get(phase, f"rpt{rpt}")
     key = f"{PHASE_KERNEL[phase]}_{shape}_traffic_bytes_per_launch"
-    t = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != kernel_source_digest():
-        return None
-    return float(t.group(1))
+    return _summary_value(TRAFFIC_SUMMARY, kernel_source_digest(), key)
 
 
 def rel_err(a, b):
@@ -342,7 +355,10 @@ def bench_spacetime(G, I, torch, args):
            "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                         "iter_ms": iter_ms, "algorithmic_bytes_per_launch": alg,
-                        "traffic": None}}
+                        "traffic": (_summary_value(ST_TRAFFIC_SUMMARY,
+                                                   kernel_source_digest(ST_SOURCES),
+                                                   f"st_k_iter_{phase}_traffic_bytes_per_launch")
+                                    if (prob.nx, prob.ny, prob.nt) == (512, 512, 64) else None)}}
     if args.st_solve_tol > 0:
         progress(f"space-time solve to {args.st_solve_tol:g}")
         ctx2 = G.gabp_st_create_problem(prob)
@@ -825,7 +841,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.print_digest:
-        print(kernel_source_digest())
+        print("lattice iteration kernels:", kernel_source_digest())
+        print("space-time kernels:", kernel_source_digest(ST_SOURCES))
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
