@@ -311,6 +311,19 @@ def bench_spacetime(G, I, torch, args):
         G.gabp_st_residual(ctx)
     frozen_at = G.gabp_st_precision_frozen(ctx)
     progress(f"space-time precision messages frozen at iteration {frozen_at}")
+    best = None
+    if frozen_at >= 0:
+        # launch shape of the information-only kernel: slices per workgroup
+        for sl in (1, 2, 4):
+            G.gabp_st_set_theta_slices(ctx, sl)
+            iterate()
+            ms, _ = event_ms(iterate, 3)
+            t_ms = sum(ms) / (3 * ITERS_PER_STEP)
+            kernels[f"theta_slices{sl}"] = {"iter_ms": t_ms, "algorithmic_bytes": alg_theta,
+                                            "gbps": alg_theta / (t_ms * 1e-3) / 1e9}
+            if best is None or t_ms < kernels[f"theta_slices{best}"]["iter_ms"]:
+                best = sl
+        G.gabp_st_set_theta_slices(ctx, best)
     for _ in range(args.warmup):
         iterate()
         G.gabp_st_residual(ctx)
@@ -350,14 +363,17 @@ def bench_spacetime(G, I, torch, args):
                       "parallelism": "single GPU"},
            "iterations_run": its, "rel_residual_after": rel,
            "timed_phase": {"kernel": kname, "precision_frozen_at_iteration": frozen_at,
-                           "freeze_tolerance_slots": args.st_freeze_slots},
+                           "freeze_tolerance_slots": args.st_freeze_slots,
+                           "theta_slices_per_workgroup": best},
            "kernels": kernels,
            "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                         "iter_ms": iter_ms, "algorithmic_bytes_per_launch": alg,
                         "traffic": (_summary_value(ST_TRAFFIC_SUMMARY,
                                                    kernel_source_digest(ST_SOURCES),
-                                                   f"st_k_iter_{phase}_traffic_bytes_per_launch")
+                                                   f"st_k_iter_{phase}"
+                                                   + (f"_s{best}" if phase == "theta" else "")
+                                                   + "_traffic_bytes_per_launch")
                                     if (prob.nx, prob.ny, prob.nt) == (512, 512, 64) else None)}}
     if args.st_solve_tol > 0:
         progress(f"space-time solve to {args.st_solve_tol:g}")

@@ -120,6 +120,12 @@ gabp_status gabp_st_get_messages(gabp_st_ctx *ctx, void *prec, void *info);
  * non-finite max_rel. */
 gabp_status gabp_st_set_freeze_tolerance(gabp_st_ctx *ctx, int64_t max_slots, double max_rel);
 
+/* Launch shape of the information-only iteration: a workgroup covers one
+ * 64 x 4 tile on `slices` consecutive slices (1, 2 or 4; default 1), so the
+ * messages passing between those slices are read twice inside one
+ * workgroup.  Results do not depend on it.  INVALID for other values. */
+gabp_status gabp_st_set_theta_slices(gabp_st_ctx *ctx, int32_t slices);
+
 /* Iteration at which the precision messages froze, or -1. */
 gabp_status gabp_st_precision_frozen(gabp_st_ctx *ctx, int64_t *frozen_at);
 

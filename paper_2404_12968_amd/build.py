@@ -28,9 +28,16 @@ FLAGS = [
 ]
 
 
+# Per-file flags.  spacetime.hip: its 38-direction loops carry full-unroll
+# pragmas whose bodies (periodic wrap included) exceed the default size limit
+# for a forced unroll; a loop left rolled indexes its per-direction arrays
+# dynamically and puts them in scratch memory.
+FILE_FLAGS = {"spacetime.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     subprocess.run(cmd, check=True)
     return obj
 

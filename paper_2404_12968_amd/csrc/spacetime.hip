@@ -327,46 +327,54 @@ __device__ __forceinline__ void st_node(const Grid &G, const T *__restrict__ m_i
     }
 }
 
-// Workgroup -> (tile x, tile y, slice).  One slice per workgroup.  Tiles are
+// Workgroup -> (tile x, tile y, first slice).  A workgroup covers one 64 x 4
+// tile on SL consecutive slices (4 waves per slice): the messages that pass
+// between those slices are read twice inside one workgroup.  Tiles are
 // grouped in bands of kGroupRows tile rows; within a band the order is slice
-// by slice, each slice row by row.  With the XCD remap each XCD runs a
+// group by slice group, each row by row.  With the XCD remap each XCD runs a
 // contiguous range of this order, so a tile's vertical neighbours (same
-// slice) are at most a few tile rows away and its slice neighbours one
+// slices) are at most a few tile rows away and its slice neighbours one
 // band-slice (tiles_x * kGroupRows workgroups) away: both halos are read
 // while still in L2.
 constexpr int kGroupRows = 4;
 
-__device__ __forceinline__ void wg_tile(const Grid &G, int &tx, int &ty, int &t) {
+template <int SL>
+__device__ __forceinline__ void wg_tile(const Grid &G, int &tx, int &ty, int &t0) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int full = kGroupRows * G.tiles_x * G.nt;         // workgroups of a full band
+    const int groups = (G.nt + SL - 1) / SL;
+    const int full = kGroupRows * G.tiles_x * groups;       // workgroups of a full band
     const int g = b / full;
     const int r = b - g * full;
     const int hg = min(kGroupRows, G.tiles_y - g * kGroupRows);   // tile rows of this band
     const int per_slice = hg * G.tiles_x;
-    t = r / per_slice;
-    const int r2 = r - t * per_slice;
+    const int sg = r / per_slice;
+    const int r2 = r - sg * per_slice;
     const int tyi = r2 / G.tiles_x;
     tx = r2 - tyi * G.tiles_x;
     ty = g * kGroupRows + tyi;
+    t0 = sg * SL;
 }
 
 // One launch of a mode over the whole grid.  diverged_at[0] records the
 // first iteration whose launch met an invalid value; launches of later
 // iterations return at once (the launch that met it completes, so its output
 // buffer holds that iteration).  MODE_GAIN passes it = 0.
-template <typename T, int MODE, bool PX, bool PY>
-__global__ __launch_bounds__(256) void k_iter(Grid G, const T *__restrict__ m_in,
-                                              T *__restrict__ m_out, T *__restrict__ gain,
-                                              const T *__restrict__ aw, const T *__restrict__ bw,
-                                              T eta, uint32_t *__restrict__ diverged_at,
-                                              uint32_t it) {
+template <typename T, int MODE, bool PX, bool PY, int SL>
+__global__ __launch_bounds__(256 * SL) void k_iter(Grid G, const T *__restrict__ m_in,
+                                                   T *__restrict__ m_out, T *__restrict__ gain,
+                                                   const T *__restrict__ aw,
+                                                   const T *__restrict__ bw, T eta,
+                                                   uint32_t *__restrict__ diverged_at,
+                                                   uint32_t it) {
     const uint32_t seen = *diverged_at;
     if (MODE != MODE_GAIN && seen != 0u && seen < it) return;
-    int tx, ty, t;
-    wg_tile(G, tx, ty, t);
+    int tx, ty, t0;
+    wg_tile<SL>(G, tx, ty, t0);
     const int x = tx * 64 + (int)(threadIdx.x & 63u);
-    const int y = ty * 4 + (int)(threadIdx.x >> 6);
-    // the slice's blocks (uniform over the workgroup) in message precision
+    const int y = ty * 4 + (int)((threadIdx.x >> 6) & 3u);
+    const int t = t0 + (int)(threadIdx.x >> 8);      // one slice per four waves
+    if (t >= G.nt) return;
+    // the slice's blocks (uniform over the wave) in message precision
     const int kind = slice_kind(G, t);
     const T pq_same[3] = {(T)G.blk[kind][0], (T)G.blk[kind][1], (T)G.blk[kind][2]};
     const T pq_cross[3] = {(T)G.blk[3][0], (T)G.blk[3][1], (T)G.blk[3][2]};
@@ -707,6 +715,7 @@ struct gabp_st_ctx {
     int64_t frozen_at = -1;
     int64_t freeze_slots = 0;     // freeze tolerance (0: bitwise only)
     double freeze_rel = 0.0;
+    int theta_slices = 1;         // slices per workgroup of the information-only kernel
     std::string err;
 };
 
@@ -750,28 +759,38 @@ gabp_status st_sync(gabp_st_ctx *ctx) {
     return GABP_OK;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int SL>
 void launch_mode(const Grid &G, const void *in, void *out, void *gain, const void *aw,
                  const void *bw, T eta, uint32_t *flags, uint32_t it, hipStream_t s) {
-    const dim3 grid((unsigned)(G.tiles_x * G.tiles_y * G.nt)), block(256);
+    const dim3 grid((unsigned)(G.tiles_x * G.tiles_y * ((G.nt + SL - 1) / SL))), block(256 * SL);
     const bool px = G.bcx == GABP_BC_PERIODIC, py = G.bcy == GABP_BC_PERIODIC;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, block, 0, s, G, (const T *)in, (T *)out, (T *)gain,
                            (const T *)aw, (const T *)bw, eta, flags, it);
     };
-    if (px && py) go(gabp::st::k_iter<T, MODE, true, true>);
-    else if (px) go(gabp::st::k_iter<T, MODE, true, false>);
-    else if (py) go(gabp::st::k_iter<T, MODE, false, true>);
-    else go(gabp::st::k_iter<T, MODE, false, false>);
+    if (px && py) go(gabp::st::k_iter<T, MODE, true, true, SL>);
+    else if (px) go(gabp::st::k_iter<T, MODE, true, false, SL>);
+    else if (py) go(gabp::st::k_iter<T, MODE, false, true, SL>);
+    else go(gabp::st::k_iter<T, MODE, false, false, SL>);
 }
 
+// mode's kernel; the information-only one covers theta_slices slices per
+// workgroup (1, 2 or 4), the others one
 template <typename T>
-void launch_any(int mode, const Grid &G, const void *in, void *out, void *gain, const void *aw,
-                const void *bw, T eta, uint32_t *flags, uint32_t it, hipStream_t s) {
+void launch_any(int mode, int theta_slices, const Grid &G, const void *in, void *out, void *gain,
+                const void *aw, const void *bw, T eta, uint32_t *flags, uint32_t it,
+                hipStream_t s) {
     using namespace gabp::st;
-    if (mode == MODE_FULL) launch_mode<T, MODE_FULL>(G, in, out, gain, aw, bw, eta, flags, it, s);
-    else if (mode == MODE_GAIN) launch_mode<T, MODE_GAIN>(G, in, out, gain, aw, bw, eta, flags, it, s);
-    else launch_mode<T, MODE_THETA>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    if (mode == MODE_FULL)
+        launch_mode<T, MODE_FULL, 1>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else if (mode == MODE_GAIN)
+        launch_mode<T, MODE_GAIN, 1>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else if (theta_slices == 4)
+        launch_mode<T, MODE_THETA, 4>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else if (theta_slices == 2)
+        launch_mode<T, MODE_THETA, 2>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else
+        launch_mode<T, MODE_THETA, 1>(G, in, out, gain, aw, bw, eta, flags, it, s);
 }
 
 unsigned node_blocks(const Grid &G) {
@@ -954,11 +973,11 @@ gabp_status gabp_st_iterate(gabp_st_ctx *ctx, int32_t n_iters, double damping) {
         const uint32_t it = (uint32_t)(ctx->iter + 1);
         void *in = ctx->msg[ctx->cur], *out = ctx->msg[ctx->cur ^ 1];
         if (ctx->dtype == GABP_F32)
-            launch_any<float>(mode, G, in, out, ctx->gain, ctx->aw, ctx->bw, (float)damping,
-                              ctx->flags, it, ctx->stream);
+            launch_any<float>(mode, ctx->theta_slices, G, in, out, ctx->gain, ctx->aw, ctx->bw,
+                              (float)damping, ctx->flags, it, ctx->stream);
         else
-            launch_any<double>(mode, G, in, out, ctx->gain, ctx->aw, ctx->bw, damping, ctx->flags,
-                               it, ctx->stream);
+            launch_any<double>(mode, ctx->theta_slices, G, in, out, ctx->gain, ctx->aw, ctx->bw,
+                               damping, ctx->flags, it, ctx->stream);
         ST_HIP(ctx, hipGetLastError());
         ctx->cur ^= 1;
         ctx->iter += 1;
@@ -1030,10 +1049,10 @@ gabp_status gabp_st_residual(gabp_st_ctx *ctx, double *rel_residual, double *abs
                                    ctx->freeze_rel)) {
             // gains from the current precisions; both buffers keep them
             if (ctx->dtype == GABP_F32)
-                launch_any<float>(gabp::st::MODE_GAIN, G, ctx->msg[ctx->cur], nullptr, ctx->gain,
-                                  ctx->aw, ctx->bw, 0.0f, ctx->flags, 0u, ctx->stream);
+                launch_any<float>(gabp::st::MODE_GAIN, 1, G, ctx->msg[ctx->cur], nullptr,
+                                  ctx->gain, ctx->aw, ctx->bw, 0.0f, ctx->flags, 0u, ctx->stream);
             else
-                launch_any<double>(gabp::st::MODE_GAIN, G, ctx->msg[ctx->cur], nullptr,
+                launch_any<double>(gabp::st::MODE_GAIN, 1, G, ctx->msg[ctx->cur], nullptr,
                                    ctx->gain, ctx->aw, ctx->bw, 0.0, ctx->flags, 0u, ctx->stream);
             ST_HIP(ctx, hipGetLastError());
             const size_t esize = ctx->dtype == GABP_F32 ? 4 : 8;
@@ -1056,6 +1075,15 @@ gabp_status gabp_st_set_freeze_tolerance(gabp_st_ctx *ctx, int64_t max_slots, do
         return st_fail(ctx, GABP_E_INVALID, "max_slots must be >= 0 and max_rel finite, >= 0");
     ctx->freeze_slots = max_slots;
     ctx->freeze_rel = max_rel;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_set_theta_slices(gabp_st_ctx *ctx, int32_t slices) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (slices != 1 && slices != 2 && slices != 4)
+        return st_fail(ctx, GABP_E_INVALID, "slices must be 1, 2 or 4");
+    ctx->theta_slices = slices;
     return GABP_OK;
 }
 

@@ -142,6 +142,7 @@ _SIGS = {
     "gabp_st_iteration_count": ([_P, _P, _P], ctypes.c_int),
     "gabp_st_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_st_precision_frozen": ([_P, _P], ctypes.c_int),
+    "gabp_st_set_theta_slices": ([_P, ctypes.c_int32], ctypes.c_int),
     "gabp_st_last_error": ([_P], ctypes.c_char_p),
     "gabp_st_destroy": ([_P], None),
 }
@@ -818,6 +819,10 @@ def gabp_st_iteration_count(ctx: STContext) -> Tuple[int, int]:
 
 def gabp_st_set_freeze_tolerance(ctx: STContext, max_slots: int, max_rel: float) -> None:
     _st_check(_lib.gabp_st_set_freeze_tolerance(ctx.handle, int(max_slots), float(max_rel)), ctx)
+
+
+def gabp_st_set_theta_slices(ctx: STContext, slices: int) -> None:
+    _st_check(_lib.gabp_st_set_theta_slices(ctx.handle, int(slices)), ctx)
 
 
 def gabp_st_precision_frozen(ctx: STContext) -> int:

@@ -251,7 +251,12 @@ def test_frozen_phase_is_bitwise_the_full_iteration(G, case):
     fz = G.gabp_st_precision_frozen(a)
     print("frozen at", fz, flush=True)
     assert fz > 0
-    G.gabp_st_iterate(a, 37, prob.damping)
+    # every launch shape of the information-only kernel
+    for sl in (1, 2, 4):
+        G.gabp_st_set_theta_slices(a, sl)
+        G.gabp_st_iterate(a, 13, prob.damping)
+    with pytest.raises(G.GabpError):
+        G.gabp_st_set_theta_slices(a, 3)
     it = G.gabp_st_iteration_count(a)[0]
     G.gabp_st_iterate(b, it, prob.damping)
     sa, sb = gpu_state(G, a), gpu_state(G, b)
