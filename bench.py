@@ -390,6 +390,19 @@ def bench_spacetime(G, I, torch, args):
                               "rel_residual": r,
                               "precision_frozen_at": G.gabp_st_precision_frozen(ctx2)}
         del ctx2
+        progress(f"space-time multigrid to {args.st_solve_tol:g}")
+        from paper_2404_12968_amd import multigrid as MG
+        import dataclasses
+        pm = dataclasses.replace(prob, rel_tol=args.st_solve_tol)
+        ft = (args.st_freeze_slots, 1e-6) if args.st_freeze_slots > 0 else None
+        r = MG.st_multigrid_solve(pm, max_iters=args.solve_max_iters, freeze_tolerance=ft,
+                                  check_every=100)
+        out["multigrid"] = {"tol": args.st_solve_tol, "status": G.gabp_status_string(r["status"]),
+                            "seconds": r["seconds"], "fine_iterations": r["iterations"],
+                            "rel_residual": r["rel"],
+                            "levels": [{k: lv[k] for k in ("level", "nx", "ny", "nt",
+                                                           "iterations", "rel")}
+                                       for lv in r["levels"]]}
     del ctx
     if not args.no_cpu_baseline:
         progress("space-time CPU baseline")

@@ -120,6 +120,28 @@ gabp_status gabp_st_get_messages(gabp_st_ctx *ctx, void *prec, void *info);
  * non-finite max_rel. */
 gabp_status gabp_st_set_freeze_tolerance(gabp_st_ctx *ctx, int64_t max_slots, double max_rel);
 
+/* Multigrid transfer on the space-time lattice (Alg. 2, Upscale Messages,
+ * read as in gabp.h's gabp_upsample_mean: the finer level starts from the
+ * coarser level's marginals).  A coarse level keeps every second node of x, y
+ * and t: coarse node (X, Y, N) sits on fine node (2X, 2Y, 2N), so
+ * nxc = ceil(nx/2), nyc = ceil(ny/2), ntc = ceil(nt/2).  Writes fine
+ * [nt][ny][nx] (FP64, device) with the trilinear interpolation of coarse
+ * [ntc][nyc][nxc] (FP64, device): a fine coordinate between two coarse nodes
+ * takes their average, one past the last coarse node of a zero-flux axis or
+ * of t takes that node's value, a periodic axis wraps (and needs an even fine
+ * size).  Async on `stream`; INVALID on a size or boundary mismatch (text in
+ * gabp_st_create_error). */
+gabp_status gabp_st_upsample_mean(const double *coarse, int32_t nxc, int32_t nyc, int32_t ntc,
+                                  int32_t bc_x, int32_t bc_y, double *fine, int32_t nx,
+                                  int32_t ny, int32_t nt, void *stream);
+
+/* Warm start from a predicted posterior mean mu (device, FP64 [nt][ny][nx]):
+ * every precision message is set to zero and every information message to
+ * th_{i->j} = -(Q_ij/c) mu_i, so that the beliefs start at
+ * mu + (b - A mu) / diag(A) -- mu itself when it is the posterior mean.  The
+ * freeze test starts afresh.  DIVERGED after a divergence.  Async. */
+gabp_status gabp_st_warm_init(gabp_st_ctx *ctx, const double *mean);
+
 /* Launch shape of the information-only iteration: a workgroup covers one
  * 64 x 4 tile on `slices` consecutive slices (1, 2 or 4; default 1), so the
  * messages passing between those slices are read twice inside one

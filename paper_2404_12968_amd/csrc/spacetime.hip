@@ -593,6 +593,70 @@ __global__ __launch_bounds__(256) void k_msgs_get(Grid G, const T *__restrict__ 
     }
 }
 
+// --------------------------------------------------------------------------
+// Multigrid transfers (the paper's Algorithm 2, outer procedure, on the
+// space-time lattice).  A coarse level keeps every second node of each of
+// x, y and t, so coarse node (X, Y, N) sits on fine node (2X, 2Y, 2N).
+// k_upsample: trilinear interpolation of a coarse FP64 mean onto the fine
+// grid (dense [nt][ny][nx]); a fine coordinate between two coarse nodes takes
+// their average, one past the last coarse node of a zero-flux axis takes that
+// node's value, a periodic axis wraps.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void lerp_axis(int v, int nc, bool periodic, int &a, int &b) {
+    a = v >> 1;
+    b = (v & 1) ? a + 1 : a;
+    if (b >= nc) b = periodic ? b - nc : nc - 1;
+}
+
+__global__ __launch_bounds__(256) void k_upsample(const double *__restrict__ coarse, int nxc,
+                                                  int nyc, int ntc, int px, int py,
+                                                  double *__restrict__ fine, int nx, int ny,
+                                                  int nt) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)nx * ny * nt) return;
+    const int x = (int)(k % nx);
+    const int y = (int)((k / nx) % ny);
+    const int t = (int)(k / ((int64_t)nx * ny));
+    int xa, xb, ya, yb, ta, tb;
+    lerp_axis(x, nxc, px != 0, xa, xb);
+    lerp_axis(y, nyc, py != 0, ya, yb);
+    lerp_axis(t, ntc, false, ta, tb);
+    auto at = [&](int X, int Y, int N) {
+        return coarse[((int64_t)N * nyc + Y) * nxc + X];
+    };
+    const double v = 0.125 * (at(xa, ya, ta) + at(xb, ya, ta) + at(xa, yb, ta) + at(xb, yb, ta) +
+                              at(xa, ya, tb) + at(xb, ya, tb) + at(xa, yb, tb) + at(xb, yb, tb));
+    fine[k] = v;
+}
+
+// Warm start from a predicted mean mu (dense FP64 [nt][ny][nx]): precision
+// messages zero, information messages th_{i->j} = -(Q_ij/c) mu_i, so the
+// beliefs start at mu + (b - A mu) / diag(A) (the fixed point when mu is the
+// posterior mean).  The entries Q_ij/c are those the iteration uses.
+template <typename T, bool PX, bool PY>
+__global__ __launch_bounds__(256) void k_warm_init(Grid G, const double *__restrict__ mu,
+                                                   T *__restrict__ m) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)G.nx * G.ny * G.nt) return;
+    const int x = (int)(k % G.nx);
+    const int y = (int)((k / G.nx) % G.ny);
+    const int t = (int)(k / ((int64_t)G.nx * G.ny));
+    const uint32_t i = (uint32_t)t * (uint32_t)G.slice + (uint32_t)(y * G.pitch + x);
+    const int kind = slice_kind(G, t);
+    const T pq_same[3] = {(T)G.blk[kind][0], (T)G.blk[kind][1], (T)G.blk[kind][2]};
+    const T pq_cross[3] = {(T)G.blk[3][0], (T)G.blk[3][1], (T)G.blk[3][2]};
+    const T gi = (T)g_at<PX, PY>(G, x, y);
+    const T mi = (T)mu[k];
+    for (int d = 0; d < kDeg; ++d) {
+        int xn, yn, tn;
+        const bool ok = nbr_at<PX, PY>(G, d, x, y, t, xn, yn, tn);
+        T th = (T)0;
+        if (ok) th = -(q_dir<T, false, PX, PY>(G, d, x, y, t, gi, pq_same, pq_cross) * mi);
+        (m + (size_t)d * G.plane)[i] = (T)0;
+        (m + (size_t)(kDeg + d) * G.plane)[i] = th;
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
@@ -1075,6 +1139,61 @@ gabp_status gabp_st_set_freeze_tolerance(gabp_st_ctx *ctx, int64_t max_slots, do
         return st_fail(ctx, GABP_E_INVALID, "max_slots must be >= 0 and max_rel finite, >= 0");
     ctx->freeze_slots = max_slots;
     ctx->freeze_rel = max_rel;
+    return GABP_OK;
+}
+
+gabp_status gabp_st_upsample_mean(const double *coarse, int32_t nxc, int32_t nyc, int32_t ntc,
+                                  int32_t bc_x, int32_t bc_y, double *fine, int32_t nx,
+                                  int32_t ny, int32_t nt, void *stream) {
+    g_st_create_error.clear();
+    if (!coarse || !fine) return st_fail(nullptr, GABP_E_INVALID, "upsample: NULL array");
+    if (nx < 1 || ny < 1 || nt < 1 || (nx + 1) / 2 != nxc || (ny + 1) / 2 != nyc ||
+        (nt + 1) / 2 != ntc)
+        return st_fail(nullptr, GABP_E_INVALID,
+                       "upsample: need ceil(n/2) coarse nodes on every axis");
+    for (int32_t bc : {bc_x, bc_y})
+        if (bc != GABP_BC_NEUMANN && bc != GABP_BC_PERIODIC)
+            return st_fail(nullptr, GABP_E_INVALID, "upsample: boundary must be zero-flux or periodic");
+    if ((bc_x == GABP_BC_PERIODIC && nx % 2) || (bc_y == GABP_BC_PERIODIC && ny % 2))
+        return st_fail(nullptr, GABP_E_INVALID, "upsample: a periodic axis needs an even fine size");
+    const int64_t n = (int64_t)nx * ny * nt;
+    hipLaunchKernelGGL(gabp::st::k_upsample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, coarse, nxc, nyc, ntc,
+                       (int)(bc_x == GABP_BC_PERIODIC), (int)(bc_y == GABP_BC_PERIODIC), fine, nx,
+                       ny, nt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return st_fail(nullptr, GABP_E_DEVICE, std::string("upsample: ") + hipGetErrorString(e));
+    return GABP_OK;
+}
+
+gabp_status gabp_st_warm_init(gabp_st_ctx *ctx, const double *mean) {
+    gabp_status s = st_ok(ctx);
+    if (s != GABP_OK) return s;
+    if (!mean) return st_fail(ctx, GABP_E_INVALID, "mean is NULL");
+    if (ctx->diverged_at != 0) return st_fail(ctx, GABP_E_DIVERGED, "the run has diverged");
+    const Grid &G = ctx->G;
+    const bool px = G.bcx == GABP_BC_PERIODIC, py = G.bcy == GABP_BC_PERIODIC;
+    const dim3 grid(node_blocks(G)), block(256);
+    auto go = [&](auto kern, auto *buf) {
+        hipLaunchKernelGGL(kern, grid, block, 0, ctx->stream, G, mean, buf);
+    };
+    if (ctx->dtype == GABP_F32) {
+        float *m = (float *)ctx->msg[ctx->cur];
+        if (px && py) go(gabp::st::k_warm_init<float, true, true>, m);
+        else if (px) go(gabp::st::k_warm_init<float, true, false>, m);
+        else if (py) go(gabp::st::k_warm_init<float, false, true>, m);
+        else go(gabp::st::k_warm_init<float, false, false>, m);
+    } else {
+        double *m = (double *)ctx->msg[ctx->cur];
+        if (px && py) go(gabp::st::k_warm_init<double, true, true>, m);
+        else if (px) go(gabp::st::k_warm_init<double, true, false>, m);
+        else if (py) go(gabp::st::k_warm_init<double, false, true>, m);
+        else go(gabp::st::k_warm_init<double, false, false>, m);
+    }
+    ST_HIP(ctx, hipGetLastError());
+    ctx->frozen = false;
+    ctx->frozen_at = -1;
     return GABP_OK;
 }
 

@@ -143,6 +143,10 @@ _SIGS = {
     "gabp_st_set_freeze_tolerance": ([_P, ctypes.c_int64, ctypes.c_double], ctypes.c_int),
     "gabp_st_precision_frozen": ([_P, _P], ctypes.c_int),
     "gabp_st_set_theta_slices": ([_P, ctypes.c_int32], ctypes.c_int),
+    "gabp_st_upsample_mean": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_int32, _P], ctypes.c_int),
+    "gabp_st_warm_init": ([_P, _P], ctypes.c_int),
     "gabp_st_last_error": ([_P], ctypes.c_char_p),
     "gabp_st_destroy": ([_P], None),
 }
@@ -819,6 +823,27 @@ def gabp_st_iteration_count(ctx: STContext) -> Tuple[int, int]:
 
 def gabp_st_set_freeze_tolerance(ctx: STContext, max_slots: int, max_rel: float) -> None:
     _st_check(_lib.gabp_st_set_freeze_tolerance(ctx.handle, int(max_slots), float(max_rel)), ctx)
+
+
+def gabp_st_upsample_mean(coarse: torch.Tensor, bc_x: int, bc_y: int, nx: int, ny: int,
+                          nt: int, stream=None) -> torch.Tensor:
+    """Trilinear upsampling of a coarse (ntc, nyc, nxc) FP64 mean onto the
+    fine (nt, ny, nx) grid; returns a new device tensor."""
+    ntc, nyc, nxc = coarse.shape
+    coarse = coarse.contiguous()
+    fine = torch.empty((nt, ny, nx), dtype=torch.float64, device=coarse.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(coarse.device)
+    _st_check(_lib.gabp_st_upsample_mean(_ptr(coarse), nxc, nyc, ntc, int(bc_x), int(bc_y),
+                                         _ptr(fine), int(nx), int(ny), int(nt),
+                                         stream.cuda_stream))
+    return fine
+
+
+def gabp_st_warm_init(ctx: STContext, mean: torch.Tensor) -> None:
+    mean = mean.to(torch.float64).contiguous()
+    _st_check(_lib.gabp_st_warm_init(ctx.handle, _ptr(mean)), ctx)
+    ctx._keep = mean        # alive until the stream has used it
 
 
 def gabp_st_set_theta_slices(ctx: STContext, slices: int) -> None:

@@ -25,6 +25,7 @@ point.
 """
 from __future__ import annotations
 
+import dataclasses
 import time
 from typing import List, Optional
 
@@ -206,3 +207,88 @@ def multigrid_batch_solve(probs: List[I.Problem], levels: Optional[int] = None,
     else:
         G.gabp_batch_destroy(out["batch"])
     return res
+
+
+# --------------------------------------------------------------------------
+# space-time lattice (the heat-equation GMRF of include/gabp_st.h)
+# --------------------------------------------------------------------------
+
+def st_level_problem(prob: I.SpaceTimeProblem, level: int) -> I.SpaceTimeProblem:
+    """Level l keeps every 2^l-th node of x, y and t: the same heat equation
+    discretised with spacing 2^l h and time step 2^l dt, and the
+    observations whose space-time cell coincides with a level node.  The
+    initial condition's factor is scaled by 2^(-l/2): the initial slice's
+    precision (dt h^2 / sigma_u^2) (a0 L)^2 carries the time step, and this
+    keeps the initial field's distribution the same on every level (a CPU
+    test checks that a smooth field's prior energy agrees across levels)."""
+    if level == 0:
+        return prob
+    f = 2 ** level
+    if (prob.bc_x == I.BC_PERIODIC and prob.nx % f) or (prob.bc_y == I.BC_PERIODIC and prob.ny % f):
+        raise ValueError("a periodic axis must be divisible by 2^level")
+    nx, ny, nt = (prob.nx + f - 1) // f, (prob.ny + f - 1) // f, (prob.nt + f - 1) // f
+    t, r = np.divmod(prob.cells, prob.nx * prob.ny)
+    y, x = np.divmod(r, prob.nx)
+    keep = (x % f == 0) & (y % f == 0) & (t % f == 0)
+    cells = (t[keep] // f) * (nx * ny) + (y[keep] // f) * nx + x[keep] // f
+    return dataclasses.replace(
+        prob, name=f"{prob.name}/level{level}", nx=nx, ny=ny, nt=nt, dt=prob.dt * f,
+        h=prob.h * f, a0=prob.a0 / np.sqrt(f), cells=cells, y=prob.y[keep],
+        var=None if prob.var is None else np.asarray(prob.var)[keep], truth=None)
+
+
+def st_max_levels(prob: I.SpaceTimeProblem, coarsest: int = 32) -> int:
+    """Levels halving x, y and t while the short spatial side stays >= coarsest,
+    every slice count >= 2, and periodic axes divide evenly."""
+    L = 1
+    while True:
+        f = 2 ** L
+        if min(prob.nx, prob.ny) // f < coarsest or (prob.nt + f - 1) // f < 2:
+            return L
+        if (prob.bc_x == I.BC_PERIODIC and prob.nx % f) or (prob.bc_y == I.BC_PERIODIC and prob.ny % f):
+            return L
+        L += 1
+
+
+def st_multigrid_solve(prob: I.SpaceTimeProblem, levels: Optional[int] = None,
+                       max_iters: int = 300000, check_every: int = 50, device="cuda",
+                       keep_context: bool = False, freeze_tolerance: Optional[tuple] = (64, 1e-6),
+                       coarse_tol: Optional[float] = None) -> dict:
+    """Coarse-to-fine on the space-time lattice: each level solved to its
+    FP64 relative residual (coarse_tol on the coarse levels, default the
+    problem's own), then its mean upsampled trilinearly
+    (`gabp_st_upsample_mean`) and installed in the next finer level with
+    `gabp_st_warm_init`.  Returns the status, per-level iterations, the fine
+    iterations, the seconds and (keep_context) the fine context."""
+    if levels is None:
+        levels = st_max_levels(prob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = None
+    per_level: List[dict] = []
+    ctx = None
+    st, rel = G.GABP_E_NOT_CONVERGED, float("inf")
+    for lev in reversed(range(levels)):
+        p = st_level_problem(prob, lev)
+        ctx = G.gabp_st_create_problem(p, device=device)
+        if freeze_tolerance is not None:
+            G.gabp_st_set_freeze_tolerance(ctx, *freeze_tolerance)
+        if pred is not None:
+            G.gabp_st_warm_init(ctx, pred)
+        tol = prob.rel_tol if lev == 0 or coarse_tol is None else max(coarse_tol, prob.rel_tol)
+        st, it, rel = G.gabp_st_solve(ctx, max_iters, p.damping, tol, check_every)
+        per_level.append({"level": lev, "nx": p.nx, "ny": p.ny, "nt": p.nt, "iterations": it,
+                          "status": st, "rel": rel, "observations": int(p.cells.size)})
+        if st == G.GABP_E_DIVERGED:
+            break
+        if lev > 0:
+            mean, _ = G.gabp_st_posterior(ctx, want_var=False)
+            fine = st_level_problem(prob, lev - 1)
+            pred = G.gabp_st_upsample_mean(mean, p.bc_x, p.bc_y, fine.nx, fine.ny, fine.nt)
+            G.gabp_st_destroy(ctx)
+    torch.cuda.synchronize()
+    out = {"status": st, "levels": per_level, "iterations": per_level[-1]["iterations"],
+           "seconds": time.perf_counter() - t0, "rel": rel}
+    if keep_context:
+        out["ctx"] = ctx
+    return out

@@ -293,3 +293,122 @@ def test_multigrid_batch_solve_reaches_the_tolerance(oracle_mod):
     G.gabp_batch_upscale_precisions(b, 0, fine, 4.0)
     torch.cuda.synchronize()
     assert torch.isfinite(fine[:, :, 1:13]).any()
+
+
+# --------------------------------------------------------------------------
+# space-time lattice
+# --------------------------------------------------------------------------
+
+def test_st_level_problem_keeps_coinciding_observations_and_the_field_energy():
+    """Level 1 and 2 of a space-time problem: observations on even (x, y, t)
+    survive with their values; a smooth field's prior energy u^T Q u (the
+    discretised integral of (du/dt - nu Lap u)^2 / sigma^2 plus the initial
+    term) agrees across levels to 2 % -- it would miss by 2x per level with the
+    initial factor or the time step left unscaled."""
+    from oracle import spacetime as S
+    p = I.small_spacetime(64, 48, 32, frac=0.05, seed=4)
+    energies = []
+    for lev in range(3):
+        q = MG.st_level_problem(p, lev)
+        f = 2 ** lev
+        assert (q.nx, q.ny, q.nt) == (64 // f, 48 // f, 32 // f)
+        assert q.dt == p.dt * f and q.h == p.h * f
+        if lev:
+            t, r = np.divmod(p.cells, p.nx * p.ny)
+            y, x = np.divmod(r, p.nx)
+            keep = (x % f == 0) & (y % f == 0) & (t % f == 0)
+            np.testing.assert_array_equal(q.y, p.y[keep])
+            tq, rq = np.divmod(q.cells, q.nx * q.ny)
+            yq, xq = np.divmod(rq, q.nx)
+            np.testing.assert_array_equal(xq * f, x[keep])
+            np.testing.assert_array_equal(tq * f, t[keep])
+        Q, _ = S.prior(q.nx, q.ny, q.nt, q.dt, q.h, q.nu, q.kappa, q.sigma_u, q.a0)
+        X, Y, T = np.arange(q.nx) * q.h, np.arange(q.ny) * q.h, np.arange(q.nt) * q.dt
+        u = (np.exp(-T / 20.0)[:, None, None] * np.cos(np.pi * (X + 0.5) / 64.0)[None, None, :]
+             * np.cos(np.pi * (Y + 0.5) / 48.0)[None, :, None]).ravel()
+        energies.append(u @ (Q @ u))
+    assert abs(energies[1] / energies[0] - 1) < 0.02 and abs(energies[2] / energies[0] - 1) < 0.02
+    assert MG.st_max_levels(I.spacetime(nx=512, ny=512, nt=64)) == 5
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nx,ny,nt,bcx", [(13, 9, 7, I.BC_NEUMANN), (16, 10, 6, I.BC_PERIODIC)])
+def test_st_upsample_is_trilinear(nx, ny, nt, bcx):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_12968_amd import gabp as G
+    nxc, nyc, ntc = (nx + 1) // 2, (ny + 1) // 2, (nt + 1) // 2
+    rng = np.random.default_rng(0)
+    c = rng.standard_normal((ntc, nyc, nxc))
+    got = G.gabp_st_upsample_mean(torch.tensor(c, device="cuda"), bcx, I.BC_NEUMANN, nx, ny,
+                                  nt).cpu().numpy()
+
+    def pair(v, n, per):
+        a, b = v // 2, v // 2 + (v % 2)
+        if b >= n:
+            b = b - n if per else n - 1
+        return a, b
+
+    want = np.zeros((nt, ny, nx))
+    for t in range(nt):
+        for y in range(ny):
+            for x in range(nx):
+                xs, ys, ts = (pair(x, nxc, bcx == I.BC_PERIODIC), pair(y, nyc, False),
+                              pair(t, ntc, False))
+                want[t, y, x] = np.mean([c[k, j, i] for k in ts for j in ys for i in xs])
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-14)
+    with pytest.raises(G.GabpError):
+        G.gabp_st_upsample_mean(torch.tensor(c, device="cuda"), bcx, I.BC_NEUMANN, nx + 2, ny, nt)
+
+
+@pytest.mark.gpu
+def test_st_warm_init_from_the_posterior_mean_is_its_fixed_point(oracle_mod):
+    """Installed from the exact posterior mean, the beliefs equal it at once
+    (mu + (b - A mu)/diag(A) with b - A mu = 0), and a solve from there stops
+    at the first checks; from a perturbed mean it still reaches the direct
+    solve."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import spacetime as S
+    from paper_2404_12968_amd import gabp as G
+    prob = I.small_spacetime(24, 20, 6, frac=0.2, seed=8, dtype="f64")
+    A, b = S.posterior_system(prob)
+    exact = oracle_mod.direct_solve(A, b)
+    ctx = G.gabp_st_create_problem(prob)
+    G.gabp_st_warm_init(ctx, torch.tensor(exact.reshape(prob.nt, prob.ny, prob.nx), device="cuda"))
+    mu, _ = G.gabp_st_posterior(ctx, want_var=False)
+    np.testing.assert_allclose(mu.cpu().numpy().ravel(), exact, rtol=0, atol=1e-10 * np.abs(exact).max())
+    rel, _ = G.gabp_st_residual(ctx)
+    assert rel < 1e-10
+    pert = exact + 0.05 * np.random.default_rng(1).standard_normal(exact.size)
+    ctx2 = G.gabp_st_create_problem(prob)
+    G.gabp_st_warm_init(ctx2, torch.tensor(pert.reshape(prob.nt, prob.ny, prob.nx), device="cuda"))
+    st, it, rel = G.gabp_st_solve(ctx2, 100000, prob.damping, 1e-10, 50)
+    assert st == G.GABP_OK
+    mu2, _ = G.gabp_st_posterior(ctx2, want_var=False)
+    assert np.linalg.norm(mu2.cpu().numpy().ravel() - exact) <= 1e-6 * np.linalg.norm(exact)
+
+
+@pytest.mark.gpu
+def test_st_multigrid_reaches_the_direct_solve(oracle_mod):
+    """Two levels to a 1e-6 residual (GaBP converges slowly on this prior:
+    the oracle needs ~6000 iterations on a grid this size), then the mean is
+    within the residual-to-error ratio the oracle shows for this system (about
+    200) of the direct solve."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import spacetime as S
+    from paper_2404_12968_amd import gabp as G
+    prob = I.spacetime(nx=48, ny=40, nt=8, dtype="f64")
+    res = MG.st_multigrid_solve(prob, levels=2, keep_context=True, max_iters=100000)
+    print("levels", [(lv["level"], lv["iterations"], lv["status"]) for lv in res["levels"]])
+    assert res["status"] == G.GABP_OK and [lv["level"] for lv in res["levels"]] == [1, 0]
+    A, b = S.posterior_system(prob)
+    exact = oracle_mod.direct_solve(A, b)
+    mu, _ = G.gabp_st_posterior(res["ctx"], want_var=False)
+    mu = mu.cpu().numpy().ravel()
+    assert np.linalg.norm(b - A @ mu) <= 1.01e-6 * np.linalg.norm(b)
+    assert np.linalg.norm(mu - exact) <= 1e-3 * np.linalg.norm(exact)
