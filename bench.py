@@ -49,7 +49,7 @@ def edge_count(nx, ny, alpha, bcx, bcy):
 
 
 ITER_SOURCES = ("iter.hip", "iter_node.h", "pair_tile.h", "walk_strip.h", "numerics.h", "lattice.h")
-ST_SOURCES = ("spacetime.hip", "numerics.h", "lattice.h")
+ST_SOURCES = ("st_iter.h", "numerics.h", "lattice.h")
 ST_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "spacetime512x512x64_traffic.md")
 
 
