@@ -166,7 +166,7 @@ __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict_
         for (int d = 0; d < DEG; ++d) {
             if (ok[d]) {
                 bad2 |= !isfinite(out[d]);
-                (m_out + (size_t)(DEG + d) * L.plane)[i] = out[d];
+                __builtin_nontemporal_store(out[d], &(m_out + (size_t)(DEG + d) * L.plane)[i]);
             }
         }
     }
