@@ -998,7 +998,7 @@ def main(argv=None):
         kernels["theta"] = {"iter_ms": ms1, "algorithmic_bytes": alg_theta,
                             "gbps": alg_theta / (ms1 * 1e-3) / 1e9, "rows_per_thread": rpt}
         # tile heights, then the column-strip walker's bands (negative)
-        for p2 in ((4, 8, 16, 32, -2, -4, -8) if prob.dtype == "f32" else (4, -2)):
+        for p2 in ((4, 8, 12, 16, 32, -2, -4, -8) if prob.dtype == "f32" else (4, -2)):
             G.gabp_set_tile(ctx, rpt, p2)
             m = 10
             ms_call = event_ms(lambda: G.gabp_iterate(ctx, 2 * m + 1, prob.damping), 3)

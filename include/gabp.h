@@ -227,11 +227,11 @@ gabp_status gabp_set_messages(gabp_ctx *ctx, const void *prec, const void *info)
  * twice over, time them with HIP events on the context's stream, and keep
  * the fastest for this context and for later contexts of the same prior
  * order, dtype and size class in this process.  Once the precision messages
- * have frozen, the two-iteration tile kernel (tile heights 4, 8, 16 and 32
- * in FP32, 4 in FP64; see gabp_set_tile) is timed against the best of those,
+ * have frozen, the two-iteration tile kernel (tile heights 4, 8, 12, 16 and
+ * 32 in FP32, 4 in FP64; see gabp_set_tile) is timed against the best of those,
  * twice over, and the fastest kept (the column-strip walker is not timed).
  * Every shape computes bitwise-identical messages, so these are ordinary
- * iterations: the counter advances by 1 + 8 * trials, plus 8 * trials (FP32)
+ * iterations: the counter advances by 1 + 8 * trials, plus 10 * trials (FP32)
  * or 2 * trials (FP64) when frozen.  *chosen (may be NULL) receives the rows
  * per thread.  Synchronises. */
 gabp_status gabp_autotune(gabp_ctx *ctx, int32_t trials, double damping, int32_t *chosen);
@@ -252,9 +252,10 @@ gabp_status gabp_set_graph(gabp_ctx *ctx, int32_t enable);
  * pair_rows: once the precision messages have frozen, gabp_iterate runs
  * two information-only iterations per launch (one HBM pass per two
  * iterations) and the last one or two iterations of each call singly.
- * pair_rows > 0 (4, or 8, 16 and 32 for FP32 only): on independent 64 x
- * pair_rows tiles (iteration t+1 of the tile and a halo of the stencil
- * radius kept in LDS, iteration t+2 written out); pair_rows < 0 (-2, or -4
+ * pair_rows > 0 (4, or 8, 12, 16 and 32 for FP32 only): on independent
+ * 64 x pair_rows tiles (iteration t+1 of the tile and a halo of the stencil
+ * radius kept in LDS, iteration t+2 written out; tiles whose halo crosses
+ * the grid's edge run as 64 x 4 tiles in a second launch); pair_rows < 0 (-2, or -4
  * and -8 for FP32 only): persistent workgroups walk 64-column strips
  * downwards in bands of -pair_rows rows, keeping iteration t+1 of the rows
  * the next band needs in LDS; 0 = always one iteration per launch.

@@ -176,7 +176,8 @@ std::map<long long, std::pair<int, int>> g_tune;
 // column-strip walker with -pair rows per band; 0: one iteration per launch.
 bool pair_ok(int dtype, int pair) {
     if (pair < 0) return pair == -2 || ((pair == -4 || pair == -8) && dtype == GABP_F32);
-    return pair == 0 || pair == 4 || ((pair == 8 || pair == 16 || pair == 32) && dtype == GABP_F32);
+    return pair == 0 || pair == 4 ||
+           ((pair == 8 || pair == 12 || pair == 16 || pair == 32) && dtype == GABP_F32);
 }
 
 long long tune_key(const gabp_ctx *ctx) {
@@ -879,7 +880,7 @@ gabp_status gabp_set_tile(gabp_ctx *ctx, int32_t rows_per_thread, int32_t pair_r
     if (!rpt_ok) return fail(ctx, GABP_E_INVALID, "rows_per_thread must be 1, 2, 4 or 8");
     if (!pair_ok(ctx->dtype, pair_rows))
         return fail(ctx, GABP_E_INVALID,
-                    "pair_rows must be 0, 4, -2 or (FP32 only) 8, 16, 32, -4 or -8");
+                    "pair_rows must be 0, 4, -2 or (FP32 only) 8, 12, 16, 32, -4 or -8");
     ctx->rpt = rows_per_thread;
     ctx->pair = pair_rows;
     return GABP_OK;

@@ -27,7 +27,7 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
 // Two information-only iterations (t+1 and t+2) per launch on 64 x th tiles
 // (th = 4, 8, 16 or 32 for FP32, 4 for FP64); m_in and m_out must differ.
 // Bitwise equal to two launch_iter_theta calls.
-constexpr int kPairChoicesF32[] = {4, 8, 16, 32};
+constexpr int kPairChoicesF32[] = {4, 8, 12, 16, 32};
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
                               const void *gain, const void *bw, double eta, uint32_t *flag,
                               const uint32_t *t_base, uint32_t t_off, hipStream_t s);

@@ -139,24 +139,64 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
     if (bad) *diverged_at = t;
 }
 
+// A two-iteration pass is two launches over disjoint tiles: the interior
+// tiles (k_iter_theta2, strip order; a ring tile's workgroup returns at
+// once), then the ring as 64 x 4 tiles (k_iter_theta2_ring).  Compiled
+// without the boundary paths, the interior kernel of an FP32 tile of at most
+// 12 rows fits 80 VGPRs, 6 waves per SIMD (two 12-wave or three 8-wave
+// workgroups per CU; 16- and 32-row tiles would spill).  Both kernels return
+// only for a divergence recorded by an earlier pass (an iteration <= t), so
+// the pass that diverges is written whole.
+template <typename T, int TH>
+constexpr int theta2_waves_per_eu() {
+    return sizeof(T) == 4 && TH <= 12 ? 6 : 1;
+}
+
 template <typename T, int ALPHA, int TH, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
-                                                            T *__restrict__ m_out,
-                                                            const T *__restrict__ gain,
-                                                            const T *__restrict__ bw, T eta,
-                                                            uint32_t *__restrict__ diverged_at,
-                                                            const uint32_t *__restrict__ t_base, uint32_t t_off) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(
+    theta2_waves_per_eu<T, TH>()))) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
+                                                        T *__restrict__ m_out,
+                                                        const T *__restrict__ gain,
+                                                        const T *__restrict__ bw, T eta,
+                                                        uint32_t *__restrict__ diverged_at,
+                                                        const uint32_t *__restrict__ t_base,
+                                                        uint32_t t_off) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
     __shared__ T lds[DEG * TH * 64];
-    if (*diverged_at != 0u) return;               // uniform across the workgroup
     const uint32_t t = *t_base + t_off;           // the iteration the launch starts from
+    const uint32_t seen = *diverged_at;
+    if (seen != 0u && seen <= t) return;          // uniform across the workgroup
+    const TileRange tr = interior_tiles(L.nx, L.ny, ALPHA == 1 ? 1 : 2, TH);
     // strip-major tile order: tiles above and below share their halo rows
     // in one XCD's L2
     int tx, ty;
-    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, (L.ny + TH - 1) / TH, tx,
-                ty);
+    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, tr.rows, tx, ty);
+    if (!tr.interior(tx, ty)) return;
     bool bad1 = false, bad2 = false;
-    pair_tile<T, ALPHA, TH, WAVES>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
+    pair_tile<T, ALPHA, TH, WAVES, true>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
+    if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
+}
+
+// The ring of a tiling (ring_tiles) as 64 x 4 tiles: one workgroup per tile.
+template <typename T, int ALPHA>
+__global__ __launch_bounds__(256) void k_iter_theta2_ring(Lattice L, TileRange ring,
+                                                          const T *__restrict__ m_in,
+                                                          T *__restrict__ m_out,
+                                                          const T *__restrict__ gain,
+                                                          const T *__restrict__ bw, T eta,
+                                                          uint32_t *__restrict__ diverged_at,
+                                                          const uint32_t *__restrict__ t_base,
+                                                          uint32_t t_off) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    __shared__ T lds[DEG * kRingRows * 64];
+    const uint32_t t = *t_base + t_off;
+    const uint32_t seen = *diverged_at;
+    if (seen != 0u && seen <= t) return;
+    int tx, ty;
+    ring.ring((int)blockIdx.x, tx, ty);
+    bool bad1 = false, bad2 = false;
+    pair_tile<T, ALPHA, kRingRows, 4, false>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1,
+                                             bad2);
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 
@@ -262,16 +302,23 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
 }
 
 // tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8,
-// 32 rows on 16
+// 12 rows on 12, 32 rows on 16
 template <typename T, int ALPHA, int TH>
 static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
                             const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
                             uint32_t t_off, hipStream_t s) {
-    constexpr int WAVES = TH == 4 ? 4 : TH == 32 ? 16 : 8;
-    const int tiles = L.tiles_x * ((L.ny + TH - 1) / TH);
-    hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(tiles), dim3(64 * WAVES), 0, s,
-                       L, (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
-                       flag, t_base, t_off);
+    constexpr int WAVES = TH == 4 ? 4 : TH == 12 ? 12 : TH == 32 ? 16 : 8;
+    constexpr int R = ALPHA == 1 ? 1 : 2;
+    const TileRange in = interior_tiles(L.nx, L.ny, R, TH);
+    const TileRange ring = ring_tiles(L.nx, L.ny, R, TH);
+    if (in.hole_count() > 0)
+        hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(L.tiles_x * in.rows),
+                           dim3(64 * WAVES), 0, s, L, (const T *)m_in, (T *)m_out,
+                           (const T *)gain, (const T *)bw, (T)eta, flag, t_base, t_off);
+    if (ring.ring_count() > 0)
+        hipLaunchKernelGGL((k_iter_theta2_ring<T, ALPHA>), dim3((unsigned)ring.ring_count()),
+                           dim3(256), 0, s, L, ring, (const T *)m_in, (T *)m_out,
+                           (const T *)gain, (const T *)bw, (T)eta, flag, t_base, t_off);
 }
 
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,
@@ -281,11 +328,13 @@ hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m
         if (L.alpha == 1) {
             if (th == 32) launch_theta2_k<float, 1, 32>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
             else if (th == 16) launch_theta2_k<float, 1, 16>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (th == 12) launch_theta2_k<float, 1, 12>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
             else if (th == 8) launch_theta2_k<float, 1, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
             else launch_theta2_k<float, 1, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
         } else {
             if (th == 32) launch_theta2_k<float, 2, 32>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
             else if (th == 16) launch_theta2_k<float, 2, 16>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
+            else if (th == 12) launch_theta2_k<float, 2, 12>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
             else if (th == 8) launch_theta2_k<float, 2, 8>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
             else launch_theta2_k<float, 2, 4>(L, m_in, m_out, gain, bw, eta, flag, t_base, t_off, s);
         }

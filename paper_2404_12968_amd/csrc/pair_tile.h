@@ -47,7 +47,89 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-template <typename T, int ALPHA, int TH, int WAVES>
+// --------------------------------------------------------------------------
+// Interior tiles and the ring.  A tile is interior when it and a halo of 2R
+// (the halo nodes' own neighbours) lie inside the grid: no coordinate wraps
+// or leaves it.  Interior tiles form the index range [txa, txb] x [tya, tyb]
+// (empty when a > b).  They run in a kernel compiled without the boundary
+// paths, whose registers would otherwise cost occupancy.  The other nodes,
+// the ring, run as 64 x 4 tiles: the interior range always ends on a
+// multiple of 4 rows, so the ring is a union of such tiles, enumerated band
+// by band (top rows, bottom rows, then the left and right columns of the
+// rows between).
+// --------------------------------------------------------------------------
+constexpr int kRingRows = 4;
+
+struct TileRange {
+    int txa, txb, tya, tyb;   // interior (hole) range, inclusive
+    int cols, rows;           // tile grid
+    __host__ __device__ bool empty() const { return txa > txb || tya > tyb; }
+    __host__ __device__ int64_t hole_count() const {
+        return empty() ? 0 : (int64_t)(txb - txa + 1) * (tyb - tya + 1);
+    }
+    __host__ __device__ int64_t ring_count() const {
+        return (int64_t)cols * rows - hole_count();
+    }
+    __host__ __device__ bool interior(int tx, int ty) const {
+        return tx >= txa && tx <= txb && ty >= tya && ty <= tyb;
+    }
+    // b-th tile outside the hole, b in [0, ring_count())
+    __host__ __device__ void ring(int b, int &tx, int &ty) const {
+        if (empty()) {
+            ty = b / cols;
+            tx = b - ty * cols;
+            return;
+        }
+        const int top = tya * cols, bottom = (rows - 1 - tyb) * cols;
+        if (b < top) {
+            ty = b / cols;
+            tx = b - ty * cols;
+            return;
+        }
+        b -= top;
+        if (b < bottom) {
+            ty = tyb + 1 + b / cols;
+            tx = b - (ty - tyb - 1) * cols;
+            return;
+        }
+        b -= bottom;
+        const int side = txa + (cols - 1 - txb);
+        ty = tya + b / side;
+        const int c = b - (ty - tya) * side;
+        tx = c < txa ? c : txb + 1 + (c - txa);
+    }
+};
+
+// Interior range of the 64 x TH tile grid of an nx x ny lattice.
+__host__ __device__ inline TileRange interior_tiles(int nx, int ny, int R, int TH) {
+    TileRange r;
+    r.cols = (nx + 63) / 64;
+    r.rows = (ny + TH - 1) / TH;
+    r.txa = (2 * R + 63) / 64;
+    r.txb = nx - 64 - 2 * R >= 0 ? (nx - 64 - 2 * R) / 64 : -1;
+    r.tya = (2 * R + TH - 1) / TH;
+    r.tyb = ny - TH - 2 * R >= 0 ? (ny - TH - 2 * R) / TH : -1;
+    return r;
+}
+
+// The same hole on the 64 x kRingRows tile grid, whose other tiles are the ring.
+__host__ __device__ inline TileRange ring_tiles(int nx, int ny, int R, int TH) {
+    const TileRange in = interior_tiles(nx, ny, R, TH);
+    TileRange r = in;
+    r.rows = (ny + kRingRows - 1) / kRingRows;
+    if (in.empty()) {
+        r.txa = 1;
+        r.txb = 0;
+        return r;
+    }
+    r.tya = in.tya * (TH / kRingRows);
+    r.tyb = (in.tyb + 1) * (TH / kRingRows) - 1;
+    return r;
+}
+
+// IO: the caller guarantees an interior tile; the boundary code paths are
+// compiled out.
+template <typename T, int ALPHA, int TH, int WAVES, bool IO = false>
 __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict__ m_in,
                                           T *__restrict__ m_out, const T *__restrict__ gain,
                                           const T *__restrict__ bw, T eta, int tx, int ty,
@@ -57,6 +139,7 @@ __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict_
     constexpr int NT = 64 * WAVES;
     constexpr int RPT = TH / WAVES;
     static_assert(TH % WAVES == 0, "tile rows must be a multiple of the wave count");
+    static_assert(TH % kRingRows == 0, "tile rows must be a multiple of the ring tiles' rows");
     constexpr int LW = 64 + 2 * R;
     constexpr int NBAND = 2 * R * LW;             // R rows above and below, full width
     constexpr int NHALO = NBAND + 2 * R * TH;     // plus R columns left and right
@@ -65,8 +148,8 @@ __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict_
     const int x0 = tx * 64, y0 = ty * TH;
     const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
     const bool px = L.bcx == BC_PERIODIC, py = L.bcy == BC_PERIODIC;
-    const bool interior = x0 >= 2 * R && x0 + 64 + 2 * R <= L.nx && y0 >= 2 * R &&
-                          y0 + TH + 2 * R <= L.ny;
+    const bool interior = IO || (x0 >= 2 * R && x0 + 64 + 2 * R <= L.nx && y0 >= 2 * R &&
+                                 y0 + TH + 2 * R <= L.ny);
     const T c = (T)L.c, keep = (T)1 - eta;
     T th1[RPT][DEG], gk[RPT][DEG], bk[RPT];
 
