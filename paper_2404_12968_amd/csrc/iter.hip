@@ -142,25 +142,20 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
 // A two-iteration pass is two launches over disjoint tiles: the interior
 // tiles (k_iter_theta2, strip order; a ring tile's workgroup returns at
 // once), then the ring as 64 x 4 tiles (k_iter_theta2_ring).  Compiled
-// without the boundary paths, the interior kernel of an FP32 tile of at most
-// 12 rows fits 80 VGPRs, 6 waves per SIMD (two 12-wave or three 8-wave
-// workgroups per CU; 16- and 32-row tiles would spill).  Both kernels return
-// only for a divergence recorded by an earlier pass (an iteration <= t), so
-// the pass that diverges is written whole.
-template <typename T, int TH>
-constexpr int theta2_waves_per_eu() {
-    return sizeof(T) == 4 && TH <= 12 ? 6 : 1;
-}
-
+// without the boundary paths, and with the halo bands' direction sets fixed
+// at compile time, the interior kernel of an FP32 12-row tile takes 68 VGPRs
+// (two 12-wave workgroups per CU) and of an 8-row tile 66 (three 8-wave
+// workgroups).  Both kernels return only for a divergence recorded by an
+// earlier pass (an iteration <= t), so the pass that diverges is written
+// whole.
 template <typename T, int ALPHA, int TH, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(
-    theta2_waves_per_eu<T, TH>()))) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
-                                                        T *__restrict__ m_out,
-                                                        const T *__restrict__ gain,
-                                                        const T *__restrict__ bw, T eta,
-                                                        uint32_t *__restrict__ diverged_at,
-                                                        const uint32_t *__restrict__ t_base,
-                                                        uint32_t t_off) {
+__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
+                                                            T *__restrict__ m_out,
+                                                            const T *__restrict__ gain,
+                                                            const T *__restrict__ bw, T eta,
+                                                            uint32_t *__restrict__ diverged_at,
+                                                            const uint32_t *__restrict__ t_base,
+                                                            uint32_t t_off) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
     __shared__ T lds[DEG * TH * 64];
     const uint32_t t = *t_base + t_off;           // the iteration the launch starts from

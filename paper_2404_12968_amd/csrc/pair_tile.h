@@ -127,6 +127,96 @@ __host__ __device__ inline TileRange ring_tiles(int nx, int ny, int R, int TH) {
     return r;
 }
 
+// --------------------------------------------------------------------------
+// Halo jobs.  A band of halo nodes sends into the tile along a fixed set of
+// directions (bit d of a mask), so its gather loads the previous outgoing
+// messages and gains of those directions only and its update computes only
+// those messages (same arithmetic, in the same order, as theta_update):
+//   5-point:  row -1 {2}, row TH {3}, column -1 {0}, column 64 {1};
+//   13-point: row -2 {6}, row -1 {2, 6, 8, 11}, row TH {3, 7, 9, 10},
+//             row TH+1 {7}, columns -1 and -2 with the corners (-1, -1),
+//             (-1, TH) {0, 4, 8, 10}, columns 64 and 65 with the corners
+//             (64, -1), (64, TH) {1, 5, 9, 11}.
+// A lane whose receiver in one of its directions lies outside the tile
+// computes that message but does not store it.
+// --------------------------------------------------------------------------
+template <int ALPHA>
+struct HaloMasks;
+template <>
+struct HaloMasks<1> {
+    static constexpr int kRows = 2;
+    static constexpr unsigned row(int j) { return j == 0 ? 1u << 2 : 1u << 3; }
+    static constexpr unsigned kLeft = 1u << 0, kRight = 1u << 1;
+};
+template <>
+struct HaloMasks<2> {
+    static constexpr int kRows = 4;
+    static constexpr unsigned row(int j) {
+        return j == 0 ? 1u << 6
+             : j == 1 ? (1u << 2) | (1u << 6) | (1u << 8) | (1u << 11)
+             : j == 2 ? (1u << 3) | (1u << 7) | (1u << 9) | (1u << 10)
+                      : 1u << 7;
+    }
+    static constexpr unsigned kLeft = (1u << 0) | (1u << 4) | (1u << 8) | (1u << 10);
+    static constexpr unsigned kRight = (1u << 1) | (1u << 5) | (1u << 9) | (1u << 11);
+};
+
+// Halo node (lx, ly) of the tile at (x0, y0): its messages of MASK at t+1,
+// stored into the receivers' LDS slots.
+template <typename T, int ALPHA, int TH, unsigned MASK, bool IO>
+__device__ __forceinline__ void halo_node(const Lattice &L, const T *__restrict__ m_in,
+                                          const T *__restrict__ gain, const T *__restrict__ bw,
+                                          T c, T eta, T keep, int x0, int y0, int lx, int ly,
+                                          bool interior, T *lds, bool &bad1) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    int gx = x0 + lx, gy = y0 + ly;
+    if (!IO && !interior) {
+        if (gx < 0 || gx >= L.nx) {
+            if (L.bcx != BC_PERIODIC) return;
+            gx = wrap_coord(gx, L.nx);
+        }
+        if (gy < 0 || gy >= L.ny) {
+            if (L.bcy != BC_PERIODIC) return;
+            gy = wrap_coord(gy, L.ny);
+        }
+    }
+    const uint32_t i = (uint32_t)(gy * L.pitch + gx);
+    uint32_t j[DEG];
+    int xs[DEG], ys[DEG];
+    bool ok[DEG];
+    T tin[DEG], ot[DEG], g[DEG];
+    if (IO || interior)
+        node_nbrs<DEG, true>(L, gx, gy, j, xs, ys, ok);
+    else
+        node_nbrs<DEG, false>(L, gx, gy, j, xs, ys, ok);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) tin[d] = (m_in + (size_t)(DEG + (d ^ 1)) * L.plane)[j[d]];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        if (!(MASK & (1u << d))) continue;
+        ot[d] = (m_in + (size_t)(DEG + d) * L.plane)[i];
+        g[d] = (gain + (size_t)d * L.plane)[i];
+    }
+    const T b = bw[i];
+    if (!IO && !interior) {
+#pragma unroll
+        for (int d = 0; d < DEG; ++d) tin[d] = ok[d] ? tin[d] : (T)0;
+    }
+    T st = 0;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) st += tin[d];
+    const T bt = fmadd(c, st, b);
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+        if (!(MASK & (1u << d))) continue;
+        const int rx = lx + dir_dx(d), ry = ly + dir_dy(d);
+        if (rx < 0 || rx >= 64 || ry < 0 || ry >= TH) continue;
+        const T out = fmadd(eta, g[d] * (bt - tin[d]), keep * ot[d]);
+        lds[((d ^ 1) * TH + ry) * 64 + rx] = out;
+        if (ok[d]) bad1 |= !isfinite(out);
+    }
+}
+
 // IO: the caller guarantees an interior tile; the boundary code paths are
 // compiled out.
 template <typename T, int ALPHA, int TH, int WAVES, bool IO = false>
@@ -136,13 +226,9 @@ __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict_
                                           T *lds, bool &bad1, bool &bad2) {
     constexpr int DEG = ALPHA == 1 ? 4 : 12;
     constexpr int R = ALPHA == 1 ? 1 : 2;
-    constexpr int NT = 64 * WAVES;
     constexpr int RPT = TH / WAVES;
     static_assert(TH % WAVES == 0, "tile rows must be a multiple of the wave count");
     static_assert(TH % kRingRows == 0, "tile rows must be a multiple of the ring tiles' rows");
-    constexpr int LW = 64 + 2 * R;
-    constexpr int NBAND = 2 * R * LW;             // R rows above and below, full width
-    constexpr int NHALO = NBAND + 2 * R * TH;     // plus R columns left and right
     // lds[(d * TH + y) * 64 + x]: incoming message of tile node (x, y) from
     // direction d at t+1 (receiver-indexed)
     const int x0 = tx * 64, y0 = ty * TH;
@@ -185,46 +271,47 @@ __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict_
             }
         }
     }
-    // step 1: halo positions
+    // step 1: halo jobs (row bands, then left and right column chunks of
+    // 64 positions), one wave each
+    {
+        using HM = HaloMasks<ALPHA>;
+        constexpr int NL = R * TH + (R == 2 ? 2 : 0);   // positions of one side
+        constexpr int NC = (NL + 63) / 64;
+        constexpr int NJOBS = HM::kRows + 2 * NC;
 #pragma unroll 1
-    for (int h = (int)threadIdx.x; h < NHALO; h += NT) {
-        int lx, ly;
-        if (h < NBAND) {
-            const int r = h / LW;
-            lx = h % LW - R;
-            ly = r < R ? r - R : TH + r - R;
-        } else {
-            const int s = h - NBAND, col = s % (2 * R);
-            ly = s / (2 * R);
-            lx = col < R ? col - R : 64 + col - R;
-        }
-        int gx = x0 + lx, gy = y0 + ly;
-        // only the messages this halo node sends into the tile are used
-        bool need[DEG];
-#pragma unroll
-        for (int d = 0; d < DEG; ++d) {
-            const int rx = lx + dir_dx(d), ry = ly + dir_dy(d);
-            need[d] = rx >= 0 && rx < 64 && ry >= 0 && ry < TH;
-        }
-        T tin[DEG], ot[DEG], g[DEG], out[DEG], b;
-        bool ok[DEG];
-        bool here = true;
-        if (interior) {
-            theta_gather_some<T, ALPHA, true>(L, m_in, gain, bw, gx, gy, need, tin, ot, g, b, ok);
-        } else {
-            if (gx < 0 || gx >= L.nx) { if (px) gx = wrap_coord(gx, L.nx); else here = false; }
-            if (gy < 0 || gy >= L.ny) { if (py) gy = wrap_coord(gy, L.ny); else here = false; }
-            if (here)
-                theta_gather_some<T, ALPHA, false>(L, m_in, gain, bw, gx, gy, need, tin, ot, g, b,
-                                                   ok);
-        }
-        if (here) {
-            theta_update<T, DEG>(tin, ot, g, b, c, eta, keep, out);
-#pragma unroll
-            for (int d = 0; d < DEG; ++d) {
-                if (!need[d]) continue;
-                lds[((d ^ 1) * TH + ly + dir_dy(d)) * 64 + lx + dir_dx(d)] = out[d];
-                if (ok[d]) bad1 |= !isfinite(out[d]);
+        for (int jb = w; jb < NJOBS; jb += WAVES) {
+            if (jb < HM::kRows) {
+                const int ly = jb < HM::kRows / 2 ? jb - HM::kRows / 2 : TH + jb - HM::kRows / 2;
+                switch (jb) {
+                    case 0: halo_node<T, ALPHA, TH, HM::row(0), IO>(L, m_in, gain, bw, c, eta, keep, x0, y0, lane, ly, interior, lds, bad1); break;
+                    case 1: halo_node<T, ALPHA, TH, HM::row(1), IO>(L, m_in, gain, bw, c, eta, keep, x0, y0, lane, ly, interior, lds, bad1); break;
+                    case 2: halo_node<T, ALPHA, TH, HM::row(2), IO>(L, m_in, gain, bw, c, eta, keep, x0, y0, lane, ly, interior, lds, bad1); break;
+                    default: halo_node<T, ALPHA, TH, HM::row(3), IO>(L, m_in, gain, bw, c, eta, keep, x0, y0, lane, ly, interior, lds, bad1); break;
+                }
+            } else {
+                const int cj = jb - HM::kRows;
+                const bool right = cj >= NC;
+                const int p = (right ? cj - NC : cj) * 64 + lane;
+                if (p < NL) {
+                    // p < TH: column -1 (64); p < 2 TH: column -2 (65); then
+                    // the corners of row -1 and row TH
+                    int lx, ly;
+                    if (p < TH) {
+                        lx = -1;
+                        ly = p;
+                    } else if (p < R * TH) {
+                        lx = -2;
+                        ly = p - TH;
+                    } else {
+                        lx = -1;
+                        ly = p == R * TH ? -1 : TH;
+                    }
+                    if (right) lx = 63 - lx;
+                    if (right)
+                        halo_node<T, ALPHA, TH, HM::kRight, IO>(L, m_in, gain, bw, c, eta, keep, x0, y0, lx, ly, interior, lds, bad1);
+                    else
+                        halo_node<T, ALPHA, TH, HM::kLeft, IO>(L, m_in, gain, bw, c, eta, keep, x0, y0, lx, ly, interior, lds, bad1);
+                }
             }
         }
     }
