@@ -510,11 +510,11 @@ gabp_status launch_pair(gabp_batch *b, int s0, int second, double eta) {
         const int *act = b->d_actf[q], *pre = b->d_wpreff[q];
         if (b->dtype == GABP_F32) {
             if (q == 0)
-                hipLaunchKernelGGL((gabp::k_batch_pair<float, 1, 16, 8>), grid, dim3(512), 0,
+                hipLaunchKernelGGL((gabp::k_batch_pair<float, 1, 12, 12>), grid, dim3(768), 0,
                                    b->stream, b->d_inst, act, pre, b->nf[q], b->d_t, s0, second,
                                    (float)eta, b->d_div);
             else
-                hipLaunchKernelGGL((gabp::k_batch_pair<float, 2, 16, 8>), grid, dim3(512), 0,
+                hipLaunchKernelGGL((gabp::k_batch_pair<float, 2, 12, 12>), grid, dim3(768), 0,
                                    b->stream, b->d_inst, act, pre, b->nf[q], b->d_t, s0, second,
                                    (float)eta, b->d_div);
         } else {
@@ -756,7 +756,7 @@ gabp_status gabp_batch_create(int32_t n, const gabp_instance *inst, const gabp_o
     };
     b->n = n;
     b->dtype = dtype;
-    b->pair = dtype == GABP_F32 ? 16 : 4;   // matches the k_batch_pair instances launched
+    b->pair = dtype == GABP_F32 ? 12 : 4;   // matches the k_batch_pair instances launched
     b->esize = dtype == GABP_F32 ? 4 : 8;
     b->h = hs;
     b->partial_cap = pc;
