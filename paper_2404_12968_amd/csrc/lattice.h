@@ -136,6 +136,88 @@ __device__ __forceinline__ void strip_order(int t, int tiles_x, int rows, int &t
     tx = strip * kStrip + r % width;
 }
 
+// --------------------------------------------------------------------------
+// Interior tiles and the ring of a tiling by 64 x TH tiles.  A tile is
+// interior when it and a halo of 2R lie inside the grid: no coordinate wraps
+// or leaves it (R: the stencil radius for a two-iteration pass, whose halo
+// nodes need their own neighbours; 2R = 2 covers a single iteration of a
+// radius-2 stencil).  Interior tiles form the index range [txa, txb] x
+// [tya, tyb] (empty when a > b).  They run in kernels compiled without the
+// boundary paths, whose registers would otherwise cost occupancy.  The other
+// tiles, the ring, are enumerated band by band (top rows, bottom rows, then
+// the left and right columns of the rows between); ring_tiles gives the same
+// hole on the 64 x 4 grid (the interior range always ends on a multiple of 4
+// rows).
+// --------------------------------------------------------------------------
+constexpr int kRingRows = 4;
+
+struct TileRange {
+    int txa, txb, tya, tyb;   // interior (hole) range, inclusive
+    int cols, rows;           // tile grid
+    __host__ __device__ bool empty() const { return txa > txb || tya > tyb; }
+    __host__ __device__ int64_t hole_count() const {
+        return empty() ? 0 : (int64_t)(txb - txa + 1) * (tyb - tya + 1);
+    }
+    __host__ __device__ int64_t ring_count() const {
+        return (int64_t)cols * rows - hole_count();
+    }
+    __host__ __device__ bool interior(int tx, int ty) const {
+        return tx >= txa && tx <= txb && ty >= tya && ty <= tyb;
+    }
+    // b-th tile outside the hole, b in [0, ring_count())
+    __host__ __device__ void ring(int b, int &tx, int &ty) const {
+        if (empty()) {
+            ty = b / cols;
+            tx = b - ty * cols;
+            return;
+        }
+        const int top = tya * cols, bottom = (rows - 1 - tyb) * cols;
+        if (b < top) {
+            ty = b / cols;
+            tx = b - ty * cols;
+            return;
+        }
+        b -= top;
+        if (b < bottom) {
+            ty = tyb + 1 + b / cols;
+            tx = b - (ty - tyb - 1) * cols;
+            return;
+        }
+        b -= bottom;
+        const int side = txa + (cols - 1 - txb);
+        ty = tya + b / side;
+        const int c = b - (ty - tya) * side;
+        tx = c < txa ? c : txb + 1 + (c - txa);
+    }
+};
+
+// Interior range of the 64 x TH tile grid of an nx x ny lattice.
+__host__ __device__ inline TileRange interior_tiles(int nx, int ny, int R, int TH) {
+    TileRange r;
+    r.cols = (nx + 63) / 64;
+    r.rows = (ny + TH - 1) / TH;
+    r.txa = (2 * R + 63) / 64;
+    r.txb = nx - 64 - 2 * R >= 0 ? (nx - 64 - 2 * R) / 64 : -1;
+    r.tya = (2 * R + TH - 1) / TH;
+    r.tyb = ny - TH - 2 * R >= 0 ? (ny - TH - 2 * R) / TH : -1;
+    return r;
+}
+
+// The same hole on the 64 x kRingRows tile grid, whose other tiles are the ring.
+__host__ __device__ inline TileRange ring_tiles(int nx, int ny, int R, int TH) {
+    const TileRange in = interior_tiles(nx, ny, R, TH);
+    TileRange r = in;
+    r.rows = (ny + kRingRows - 1) / kRingRows;
+    if (in.empty()) {
+        r.txa = 1;
+        r.txb = 0;
+        return r;
+    }
+    r.tya = in.tya * (TH / kRingRows);
+    r.tyb = (in.tyb + 1) * (TH / kRingRows) - 1;
+    return r;
+}
+
 // Wave64 sum in a fixed order (butterfly over lane masks 32..1).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -426,19 +426,43 @@ gabp_status st_sync(gabp_st_ctx *ctx) {
     return GABP_OK;
 }
 
+// One iteration of a mode: the information-only iteration in one launch
+// over every tile; the others as the interior launch (tiles of the hole on
+// slices 1 .. nt - 2), then the boundary launch.
+template <typename T, int MODE, int SL, bool PX, bool PY>
+void launch_parts(const Grid &G, const void *in, void *out, void *gain, const void *aw,
+                  const void *bw, T eta, uint32_t *flags, uint32_t it, hipStream_t s) {
+    using namespace gabp::st;
+    if constexpr (MODE == MODE_THETA) {
+        const unsigned n = (unsigned)(G.tiles_x * G.tiles_y * ((G.nt + SL - 1) / SL));
+        hipLaunchKernelGGL((k_iter<T, MODE, PX, PY, SL, PART_ALL>), dim3(n), dim3(256 * SL), 0, s,
+                           G, (const T *)in, (T *)out, (T *)gain, (const T *)aw, (const T *)bw,
+                           eta, flags, it);
+        return;
+    } else {
+        const gabp::TileRange h = st_hole(G);
+        if (!h.empty() && G.nt >= 3) {
+            const unsigned n = (unsigned)(h.hole_count() * ((G.nt - 2 + SL - 1) / SL));
+            hipLaunchKernelGGL((k_iter<T, MODE, PX, PY, SL, PART_INTERIOR>), dim3(n), dim3(256 * SL),
+                               0, s, G, (const T *)in, (T *)out, (T *)gain, (const T *)aw,
+                               (const T *)bw, eta, flags, it);
+        }
+        const unsigned nb = (unsigned)st_boundary_count(G);
+        if (nb > 0)
+            hipLaunchKernelGGL((k_iter<T, MODE, PX, PY, 1, PART_BOUNDARY>), dim3(nb), dim3(256), 0, s,
+                               G, (const T *)in, (T *)out, (T *)gain, (const T *)aw, (const T *)bw,
+                               eta, flags, it);
+    }
+}
+
 template <typename T, int MODE, int SL>
 void launch_mode(const Grid &G, const void *in, void *out, void *gain, const void *aw,
                  const void *bw, T eta, uint32_t *flags, uint32_t it, hipStream_t s) {
-    const dim3 grid((unsigned)(G.tiles_x * G.tiles_y * ((G.nt + SL - 1) / SL))), block(256 * SL);
     const bool px = G.bcx == GABP_BC_PERIODIC, py = G.bcy == GABP_BC_PERIODIC;
-    auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, grid, block, 0, s, G, (const T *)in, (T *)out, (T *)gain,
-                           (const T *)aw, (const T *)bw, eta, flags, it);
-    };
-    if (px && py) go(gabp::st::k_iter<T, MODE, true, true, SL>);
-    else if (px) go(gabp::st::k_iter<T, MODE, true, false, SL>);
-    else if (py) go(gabp::st::k_iter<T, MODE, false, true, SL>);
-    else go(gabp::st::k_iter<T, MODE, false, false, SL>);
+    if (px && py) launch_parts<T, MODE, SL, true, true>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else if (px) launch_parts<T, MODE, SL, true, false>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else if (py) launch_parts<T, MODE, SL, false, true>(G, in, out, gain, aw, bw, eta, flags, it, s);
+    else launch_parts<T, MODE, SL, false, false>(G, in, out, gain, aw, bw, eta, flags, it, s);
 }
 
 // mode's kernel; the information-only one covers theta_slices slices per

@@ -336,28 +336,78 @@ __device__ __forceinline__ void st_node(const Grid &G, const T *__restrict__ m_i
 // while still in L2.
 constexpr int kGroupRows = 4;
 
+// Band and slice-group order over a box of tiles_x x tiles_y tiles and nt
+// slices: workgroup b -> (tx, ty, first slice) relative to the box.
 template <int SL>
-__device__ __forceinline__ void wg_tile(const Grid &G, int &tx, int &ty, int &t0) {
-    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int groups = (G.nt + SL - 1) / SL;
-    const int full = kGroupRows * G.tiles_x * groups;       // workgroups of a full band
+__device__ __forceinline__ void wg_tile(int b, int tiles_x, int tiles_y, int nt, int &tx, int &ty,
+                                        int &t0) {
+    const int groups = (nt + SL - 1) / SL;
+    const int full = kGroupRows * tiles_x * groups;         // workgroups of a full band
     const int g = b / full;
     const int r = b - g * full;
-    const int hg = min(kGroupRows, G.tiles_y - g * kGroupRows);   // tile rows of this band
-    const int per_slice = hg * G.tiles_x;
+    const int hg = min(kGroupRows, tiles_y - g * kGroupRows);   // tile rows of this band
+    const int per_slice = hg * tiles_x;
     const int sg = r / per_slice;
     const int r2 = r - sg * per_slice;
-    const int tyi = r2 / G.tiles_x;
-    tx = r2 - tyi * G.tiles_x;
+    const int tyi = r2 / tiles_x;
+    tx = r2 - tyi * tiles_x;
     ty = g * kGroupRows + tyi;
     t0 = sg * SL;
 }
 
-// One launch of a mode over the whole grid.  diverged_at[0] records the
-// first iteration whose launch met an invalid value; launches of later
-// iterations return at once (the launch that met it completes, so its output
-// buffer holds that iteration).  MODE_GAIN passes it = 0.
-template <typename T, int MODE, bool PX, bool PY, int SL>
+// Interior tiles of a slice grid (a halo of 2 inside the slice: every
+// in-slice and cross-slice neighbour exists and none wraps); with the first
+// and last slice excluded they are the tiles the interior kernel runs.
+__host__ __device__ inline TileRange st_hole(const Grid &G) {
+    return interior_tiles(G.nx, G.ny, 1, 4);
+}
+
+// Boundary tiles: every tile of the first and last slice, then the ring of
+// each slice between (all tiles when the hole is empty or nt < 3).
+__host__ __device__ inline int64_t st_boundary_count(const Grid &G) {
+    const TileRange h = st_hole(G);
+    const int64_t all = (int64_t)G.tiles_x * G.tiles_y;
+    if (h.empty() || G.nt < 3) return all * G.nt;
+    return 2 * all + (int64_t)(G.nt - 2) * h.ring_count();
+}
+
+__device__ __forceinline__ void st_boundary_tile(const Grid &G, int b, int &tx, int &ty, int &t) {
+    const TileRange h = st_hole(G);
+    const int all = G.tiles_x * G.tiles_y;
+    int tile;
+    if (h.empty() || G.nt < 3) {
+        t = b / all;
+        tile = b - t * all;
+    } else if (b < 2 * all) {
+        t = b < all ? 0 : G.nt - 1;
+        tile = b < all ? b : b - all;
+    } else {
+        const int ring = (int)h.ring_count();
+        const int q = (b - 2 * all) / ring;
+        t = 1 + q;
+        h.ring(b - 2 * all - q * ring, tx, ty);
+        return;
+    }
+    ty = tile / G.tiles_x;
+    tx = tile - ty * G.tiles_x;
+}
+
+// One launch of a mode over the grid or part of it: PART_ALL every tile
+// (interior tiles through the interior path, in one kernel), PART_INTERIOR
+// the interior tiles of slices 1 .. nt - 2 (compiled without the boundary
+// paths: fewer registers, more waves per SIMD), PART_BOUNDARY the other tiles
+// (one slice per workgroup); an iteration is then the two launches.  The
+// full iteration runs split (3.07 -> 2.78 ms per iteration at 512 x 512 x 64:
+// 96 instead of 121 VGPRs); the information-only one, already streaming
+// near the copy rate, runs whole (split, its boundary sweep costs more than
+// the occupancy gains: 1.47 -> 1.53 ms).  diverged_at[0] records the first
+// iteration whose launches met an invalid value; launches of later
+// iterations return at once (the launches of the iteration that met it
+// complete, so its output buffer holds that iteration).  MODE_GAIN passes
+// it = 0.
+enum { PART_ALL = 0, PART_INTERIOR = 1, PART_BOUNDARY = 2 };
+
+template <typename T, int MODE, bool PX, bool PY, int SL, int PART>
 __global__ __launch_bounds__(256 * SL) void k_iter(Grid G, const T *__restrict__ m_in,
                                                    T *__restrict__ m_out, T *__restrict__ gain,
                                                    const T *__restrict__ aw,
@@ -366,18 +416,33 @@ __global__ __launch_bounds__(256 * SL) void k_iter(Grid G, const T *__restrict__
                                                    uint32_t it) {
     const uint32_t seen = *diverged_at;
     if (MODE != MODE_GAIN && seen != 0u && seen < it) return;
-    int tx, ty, t0;
-    wg_tile<SL>(G, tx, ty, t0);
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    int tx, ty, t;
+    if (PART == PART_ALL) {
+        int t0;
+        wg_tile<SL>(b, G.tiles_x, G.tiles_y, G.nt, tx, ty, t0);
+        t = t0 + (int)(threadIdx.x >> 8);          // one slice per four waves
+        if (t >= G.nt) return;
+    } else if (PART == PART_INTERIOR) {
+        const TileRange h = st_hole(G);
+        int t0;
+        wg_tile<SL>(b, h.txb - h.txa + 1, h.tyb - h.tya + 1, G.nt - 2, tx, ty, t0);
+        tx += h.txa;
+        ty += h.tya;
+        t = 1 + t0 + (int)(threadIdx.x >> 8);      // one slice per four waves
+        if (t > G.nt - 2) return;
+    } else {
+        st_boundary_tile(G, b, tx, ty, t);
+    }
     const int x = tx * 64 + (int)(threadIdx.x & 63u);
     const int y = ty * 4 + (int)((threadIdx.x >> 6) & 3u);
-    const int t = t0 + (int)(threadIdx.x >> 8);      // one slice per four waves
-    if (t >= G.nt) return;
     // the slice's blocks (uniform over the wave) in message precision
     const int kind = slice_kind(G, t);
     const T pq_same[3] = {(T)G.blk[kind][0], (T)G.blk[kind][1], (T)G.blk[kind][2]};
     const T pq_cross[3] = {(T)G.blk[3][0], (T)G.blk[3][1], (T)G.blk[3][2]};
-    const bool inner = tx * 64 >= 2 && tx * 64 + 66 <= G.nx && ty * 4 >= 2 &&
-                       ty * 4 + 6 <= G.ny && t > 0 && t < G.nt - 1;
+    const bool inner = PART == PART_INTERIOR ||
+                       (PART == PART_ALL && tx * 64 >= 2 && tx * 64 + 66 <= G.nx && ty * 4 >= 2 &&
+                        ty * 4 + 6 <= G.ny && t > 0 && t < G.nt - 1);
     bool bad = false;
     if (inner)
         st_node<T, MODE, true, PX, PY>(G, m_in, m_out, gain, aw, bw, eta, pq_same, pq_cross, bad,
