@@ -19,11 +19,11 @@ namespace gabp {
 // workgroup owns a 64 x TH tile (the caller passes LDS for deg x TH x 64
 // values and synchronises before reusing it).  Step 1 computes iteration
 // t+1 for the tile and for a halo of R = stencil radius nodes around it
-// (inputs from HBM/L2; a halo node only computes the messages it sends into
-// the tile), and leaves in LDS, for every tile node and direction d, its
-// incoming message from
-// the node at + off_d (receiver-indexed, 64 x TH x deg values; the tile
-// nodes' own new messages stay in registers with their gains).  Step 2
+// (inputs from HBM/L2; the halo runs as band jobs, each node computing only
+// the messages it sends into the tile), and leaves in LDS, for every tile
+// node and direction d, its incoming message from the node at + off_d
+// (receiver-indexed, 64 x TH x deg values; the tile nodes' own new messages
+// stay in registers with their gains).  Step 2
 // computes iteration t+2 for the tile from LDS and writes it out.  HBM then
 // sees one read of the inputs and one write of the outputs per two
 // iterations.  Every node goes through theta_update, so the result is bitwise
