@@ -551,6 +551,7 @@ def _freeze(G, ctx):
     ("f32", 2, 16, 150, 70, I.BC_NEUMANN, I.BC_DIRICHLET),
     ("f32", 2, 32, 140, 75, I.BC_PERIODIC, I.BC_NEUMANN),
     ("f32", 2, 12, 150, 70, I.BC_NEUMANN, I.BC_DIRICHLET),
+    ("f32", 2, 12, 132, 28, I.BC_NEUMANN, I.BC_PERIODIC),   # one interior tile
     ("f32", 2, 12, 200, 41, I.BC_PERIODIC, I.BC_PERIODIC),
     ("f32", 2, 12, 300, 130, I.BC_NEUMANN, I.BC_NEUMANN),
     ("f32", 2, 12, 67, 23, I.BC_DIRICHLET, I.BC_PERIODIC),

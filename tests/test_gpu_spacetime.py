@@ -116,6 +116,7 @@ CASES = [
     (9, 5, 2, I.BC_NEUMANN, I.BC_NEUMANN, 0.3),         # first and last slice only
     (3, 4, 7, I.BC_NEUMANN, I.BC_NEUMANN, 0.3),         # grid narrower than the stencil
     (130, 5, 4, I.BC_NEUMANN, I.BC_PERIODIC, 0.1),     # shortest periodic axis
+    (132, 14, 3, I.BC_NEUMANN, I.BC_NEUMANN, 0.2),     # interior launch: one tile column, one slice
 ]
 
 
