@@ -1,12 +1,17 @@
 // Host-side checks of the library's host logic, compiled and run by
 // tests/test_host_logic.py: the precision-freeze decision
-// (gabp::host::freeze_now) and the device workspace layout
-// (gabp::host::make_layout).  Exit status 0 and "ok" when every case holds.
+// (gabp::host::freeze_now), the device workspace layout
+// (gabp::host::make_layout) and the tile ranges of the split launches
+// (gabp::interior_tiles, gabp::ring_tiles, TileRange::ring).  Exit status 0
+// and "ok" when every case holds.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 
+#include <vector>
+
 #include "host_common.h"
+#include "lattice.h"
 
 using gabp::host::freeze_now;
 using gabp::host::held_after_batch_run;
@@ -104,6 +109,58 @@ int main() {
                 CHECK(l.mu64 + node * 8 <= l.bel64 && l.bel64 + node * 8 <= l.partials);
                 if (f32) CHECK(l.adiag_w >= l.bel64 + node * 8 && l.b_w >= l.adiag_w + node * 4);
                 CHECK(l.flags + 8 * sizeof(uint32_t) <= l.total);
+            }
+        }
+    }
+    // tile ranges: the interior range is exactly the tiles whose halo of 2R
+    // lies inside the grid; ring() visits every other tile once; the hole
+    // tiles plus the 64 x 4 ring tiles cover every node once
+    const int dims_x[] = {1, 5, 63, 64, 67, 68, 69, 131, 132, 133, 200, 1000};
+    const int dims_y[] = {1, 3, 5, 7, 12, 13, 16, 17, 23, 28, 40, 97, 301};
+    for (int nx : dims_x) {
+        for (int ny : dims_y) {
+            for (int R : {1, 2}) {
+                for (int TH : {4, 8, 12, 16, 32}) {
+                    const gabp::TileRange in = gabp::interior_tiles(nx, ny, R, TH);
+                    CHECK(in.cols == (nx + 63) / 64 && in.rows == (ny + TH - 1) / TH);
+                    int64_t inside = 0;
+                    for (int ty = 0; ty < in.rows; ++ty)
+                        for (int tx = 0; tx < in.cols; ++tx) {
+                            const int x0 = 64 * tx, y0 = TH * ty;
+                            const bool want = x0 >= 2 * R && x0 + 64 + 2 * R <= nx &&
+                                              y0 >= 2 * R && y0 + TH + 2 * R <= ny;
+                            CHECK(in.interior(tx, ty) == want);
+                            inside += want;
+                        }
+                    CHECK(in.hole_count() == inside);
+                    std::vector<int> seen((size_t)in.cols * in.rows, 0);
+                    for (int b = 0; b < (int)in.ring_count(); ++b) {
+                        int tx = -1, ty = -1;
+                        in.ring(b, tx, ty);
+                        CHECK(tx >= 0 && tx < in.cols && ty >= 0 && ty < in.rows);
+                        CHECK(!in.interior(tx, ty));
+                        CHECK(seen[(size_t)ty * in.cols + tx]++ == 0);
+                    }
+                    // nodes written: hole tiles (64 x TH) and ring tiles (64 x 4)
+                    const gabp::TileRange rg = gabp::ring_tiles(nx, ny, R, TH);
+                    std::vector<int> cover((size_t)nx * ny, 0);
+                    for (int ty = 0; ty < in.rows; ++ty)
+                        for (int tx = 0; tx < in.cols; ++tx) {
+                            if (!in.interior(tx, ty)) continue;
+                            for (int y = TH * ty; y < std::min(ny, TH * ty + TH); ++y)
+                                for (int x = 64 * tx; x < std::min(nx, 64 * tx + 64); ++x)
+                                    ++cover[(size_t)y * nx + x];
+                        }
+                    for (int b = 0; b < (int)rg.ring_count(); ++b) {
+                        int tx = -1, ty = -1;
+                        rg.ring(b, tx, ty);
+                        CHECK(tx >= 0 && tx < rg.cols && ty >= 0 && ty < rg.rows);
+                        for (int y = 4 * ty; y < std::min(ny, 4 * ty + 4); ++y)
+                            for (int x = 64 * tx; x < std::min(nx, 64 * tx + 64); ++x)
+                                ++cover[(size_t)y * nx + x];
+                    }
+                    for (int c : cover) CHECK(c == 1);
+                }
             }
         }
     }
