@@ -172,6 +172,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 
+// Every tile in one launch (strip order; each tile takes the interior path
+// when its halo is inside the grid): on small lattices, where the ring is a
+// large share of the nodes and a second launch's latency counts, this beats
+// the interior + ring pair (launch_theta2_k chooses).
+template <typename T, int ALPHA, int TH, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2_all(Lattice L,
+                                                                const T *__restrict__ m_in,
+                                                                T *__restrict__ m_out,
+                                                                const T *__restrict__ gain,
+                                                                const T *__restrict__ bw, T eta,
+                                                                uint32_t *__restrict__ diverged_at,
+                                                                const uint32_t *__restrict__ t_base,
+                                                                uint32_t t_off) {
+    constexpr int DEG = ALPHA == 1 ? 4 : 12;
+    __shared__ T lds[DEG * TH * 64];
+    const uint32_t t = *t_base + t_off;
+    const uint32_t seen = *diverged_at;
+    if (seen != 0u && seen <= t) return;
+    int tx, ty;
+    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, (L.ny + TH - 1) / TH, tx,
+                ty);
+    bool bad1 = false, bad2 = false;
+    pair_tile<T, ALPHA, TH, WAVES, false>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
+    if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
+}
+
 // The ring of a tiling (ring_tiles) as 64 x 4 tiles: one workgroup per tile.
 template <typename T, int ALPHA>
 __global__ __launch_bounds__(256) void k_iter_theta2_ring(Lattice L, TileRange ring,
@@ -298,6 +324,11 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
 
 // tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8,
 // 12 rows on 12, 32 rows on 16
+#ifndef GABP_RING_SHARE_SPLIT
+#define GABP_RING_SHARE_SPLIT 20
+#endif
+constexpr int64_t kRingShareSplit = GABP_RING_SHARE_SPLIT;
+
 template <typename T, int ALPHA, int TH>
 static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
                             const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
@@ -306,6 +337,15 @@ static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, con
     constexpr int R = ALPHA == 1 ? 1 : 2;
     const TileRange in = interior_tiles(L.nx, L.ny, R, TH);
     const TileRange ring = ring_tiles(L.nx, L.ny, R, TH);
+    // one launch over every tile when the ring (64 x 4 tiles) holds more than
+    // 1/kRingShareSplit of the nodes
+    if (ring.ring_count() * 256 * kRingShareSplit > (int64_t)L.nx * L.ny) {
+        hipLaunchKernelGGL((k_iter_theta2_all<T, ALPHA, TH, WAVES>),
+                           dim3(L.tiles_x * ((L.ny + TH - 1) / TH)), dim3(64 * WAVES), 0, s, L,
+                           (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
+                           flag, t_base, t_off);
+        return;
+    }
     if (in.hole_count() > 0)
         hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(L.tiles_x * in.rows),
                            dim3(64 * WAVES), 0, s, L, (const T *)m_in, (T *)m_out,
