@@ -552,6 +552,10 @@ def _freeze(G, ctx):
     ("f32", 2, 32, 140, 75, I.BC_PERIODIC, I.BC_NEUMANN),
     ("f32", 2, 12, 150, 70, I.BC_NEUMANN, I.BC_DIRICHLET),
     ("f32", 2, 12, 132, 28, I.BC_NEUMANN, I.BC_PERIODIC),   # one interior tile
+    # lattices whose ring holds under 5 % of the nodes: the pass is the
+    # interior launch plus the ring launch (smaller ones run as one launch)
+    ("f32", 2, 16, 4096, 2048, I.BC_NEUMANN, I.BC_DIRICHLET),
+    ("f32", 2, 12, 4100, 2060, I.BC_PERIODIC, I.BC_PERIODIC),
     ("f32", 2, 12, 200, 41, I.BC_PERIODIC, I.BC_PERIODIC),
     ("f32", 2, 12, 300, 130, I.BC_NEUMANN, I.BC_NEUMANN),
     ("f32", 2, 12, 67, 23, I.BC_DIRICHLET, I.BC_PERIODIC),
