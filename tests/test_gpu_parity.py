@@ -556,6 +556,7 @@ def _freeze(G, ctx):
     # interior launch plus the ring launch (smaller ones run as one launch)
     ("f32", 2, 16, 4096, 2048, I.BC_NEUMANN, I.BC_DIRICHLET),
     ("f32", 2, 12, 4100, 2060, I.BC_PERIODIC, I.BC_PERIODIC),
+    ("f64", 2, 4, 4096, 2048, I.BC_NEUMANN, I.BC_NEUMANN),
     ("f32", 2, 12, 200, 41, I.BC_PERIODIC, I.BC_PERIODIC),
     ("f32", 2, 12, 300, 130, I.BC_NEUMANN, I.BC_NEUMANN),
     ("f32", 2, 12, 67, 23, I.BC_DIRICHLET, I.BC_PERIODIC),
