@@ -151,6 +151,41 @@ def test_residual_matches_the_oracle_system(G, oracle_mod, nx, ny, alpha, bcx, b
     assert rel == pytest.approx(want_rel, rel=1e-11)
 
 
+@pytest.mark.parametrize("dtype,alpha,nx,ny,bcx,bcy", [
+    ("f32", 2, 200, 60, I.BC_NEUMANN, I.BC_NEUMANN),
+    ("f32", 2, 261, 53, I.BC_PERIODIC, I.BC_DIRICHLET),
+    ("f32", 2, 70, 37, I.BC_DIRICHLET, I.BC_PERIODIC),
+    ("f32", 2, 9, 9, I.BC_PERIODIC, I.BC_PERIODIC),
+    ("f32", 1, 150, 45, I.BC_NEUMANN, I.BC_PERIODIC),
+    ("f64", 2, 140, 40, I.BC_NEUMANN, I.BC_DIRICHLET),
+    ("f64", 1, 120, 30, I.BC_PERIODIC, I.BC_NEUMANN),
+])
+def test_frozen_check_matches_the_oracle_system(G, oracle_mod, dtype, alpha, nx, ny, bcx, bcy):
+    """The check once the precision messages froze (means from the frozen
+    belief precisions, then the windowed residual): gabp_residual against
+    |A mu - b| / |b| with the oracle's assembled A and b and the GPU's FP64
+    mean, on lattices with interior tiles, ragged and wrapped tiles, and a
+    periodic lattice narrower than the residual's window."""
+    if (dtype, alpha) == ("f64", 1):
+        prob = I.small_lattice(nx, ny, alpha, bc_x=bcx, bc_y=bcy, kappa=0.1, tracks=5, run=4,
+                               sigma=0.05, seed=77, dtype=dtype)
+    else:
+        prob = I.small_lattice(nx, ny, alpha, bc_x=bcx, bc_y=bcy, kappa=0.12, frac=0.08,
+                               sigma=0.05, seed=nx + ny, dtype=dtype)
+    ctx = G.gabp_create_problem(prob)
+    assert _freeze(G, ctx) > 0
+    G.gabp_iterate(ctx, 3, 0.5)
+    rel, ab = G.gabp_residual(ctx)
+    mu, _ = G.gabp_posterior(ctx, want_var=False)
+    A, b = oracle_mod.posterior_system(prob)
+    r = A @ mu.cpu().numpy().ravel() - b
+    want_abs, bn = np.linalg.norm(r), np.linalg.norm(b)
+    assert want_abs / bn > 1e-9      # far above the rounding of A mu - b
+    assert abs(ab - want_abs) <= 1e-10 * want_abs + 1e-14 * bn
+    assert abs(rel - want_abs / bn) <= 1e-10 * want_abs / bn + 1e-14
+    G.gabp_destroy(ctx)
+
+
 FP32_CASES = [
     (200, 150, 1, I.BC_NEUMANN, I.BC_NEUMANN, 1.0, 0.5, 0.2, 300),
     (193, 130, 2, I.BC_PERIODIC, I.BC_NEUMANN, 10.0, 0.5, 0.05, 1000),
