@@ -1021,9 +1021,7 @@ def main(argv=None):
         # two iterations per launch with the intermediate one kept on chip:
         # the launch must read its inputs and write its outputs once, the
         # bytes of one single-iteration pass
-        # a tile pass is two launches over disjoint tiles (interior, then
-        # the ring of 64 x 4 tiles), timed together
-        kname = "k_iter_theta2+k_iter_theta2_ring" if pair > 0 else "k_iter_theta2w"
+        kname = "k_iter_theta2" if pair > 0 else "k_iter_theta2w"
         launch_ms = kernels[f"theta_pair{pair}" if pair > 0 else f"theta_walk{-pair}"]["launch_ms"]
         alg_launch = alg_theta
         traffic = measured_traffic("theta2" if pair > 0 else "theta2w", pair, prob.name)

@@ -255,7 +255,7 @@ gabp_status gabp_set_graph(gabp_ctx *ctx, int32_t enable);
  * pair_rows > 0 (4, or 8, 12, 16 and 32 for FP32 only): on independent
  * 64 x pair_rows tiles (iteration t+1 of the tile and a halo of the stencil
  * radius kept in LDS, iteration t+2 written out; tiles whose halo crosses
- * the grid's edge run as 64 x 4 tiles in a second launch); pair_rows < 0 (-2, or -4
+ * the grid's edge take the general code path, in the same launch); pair_rows < 0 (-2, or -4
  * and -8 for FP32 only): persistent workgroups walk 64-column strips
  * downwards in bands of -pair_rows rows, keeping iteration t+1 of the rows
  * the next band needs in LDS; 0 = always one iteration per launch.

@@ -139,17 +139,21 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
     if (bad) *diverged_at = t;
 }
 
-// A two-iteration pass is two launches over disjoint tiles: the interior
-// tiles (k_iter_theta2, strip order; a ring tile's workgroup returns at
-// once), then the ring as 64 x 4 tiles (k_iter_theta2_ring).  Compiled
-// without the boundary paths, and with the halo bands' direction sets fixed
-// at compile time, the interior kernel of an FP32 12-row tile takes 68 VGPRs
-// (two 12-wave workgroups per CU) and of an 8-row tile 66 (three 8-wave
-// workgroups).  Both kernels return only for a divergence recorded by an
-// earlier pass (an iteration <= t), so the pass that diverges is written
-// whole.
+// A two-iteration pass on a lattice with a large interior is one launch over
+// two sets of 64 x TH tiles: the first nring workgroups take the ring (the
+// tiles whose halo reaches a boundary, TileRange::ring order) on the
+// boundary code path; the others walk the tile grid in strip order and take
+// the interior tiles (a ring tile there returns at once) on a path compiled
+// without boundary code, with the halo bands' direction sets fixed at compile
+// time.  The ring runs alongside the first interior tiles instead of as a
+// second launch after them.  The interior path of an FP32 16-row tile takes
+// 97 VGPRs and the ring path 110, both four waves per SIMD (two 8-wave
+// workgroups per CU); 12-row tiles take 74 (two 12-wave workgroups).  Both
+// paths return only for a divergence recorded by an earlier pass (an
+// iteration <= t), so the pass that diverges is written whole.
 template <typename T, int ALPHA, int TH, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *__restrict__ m_in,
+__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, TileRange in, int nring,
+                                                            const T *__restrict__ m_in,
                                                             T *__restrict__ m_out,
                                                             const T *__restrict__ gain,
                                                             const T *__restrict__ bw, T eta,
@@ -161,21 +165,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, const T *
     const uint32_t t = *t_base + t_off;           // the iteration the launch starts from
     const uint32_t seen = *diverged_at;
     if (seen != 0u && seen <= t) return;          // uniform across the workgroup
-    const TileRange tr = interior_tiles(L.nx, L.ny, ALPHA == 1 ? 1 : 2, TH);
-    // strip-major tile order: tiles above and below share their halo rows
-    // in one XCD's L2
-    int tx, ty;
-    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, tr.rows, tx, ty);
-    if (!tr.interior(tx, ty)) return;
     bool bad1 = false, bad2 = false;
-    pair_tile<T, ALPHA, TH, WAVES, true>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
+    int tx, ty;
+    const int b = (int)blockIdx.x;
+    if (b < nring) {
+        if ((int64_t)b >= in.ring_count()) return;   // nring is rounded up to the XCD count
+        in.ring(b, tx, ty);
+        pair_tile<T, ALPHA, TH, WAVES, false>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1,
+                                              bad2);
+    } else {
+        // strip-major tile order: tiles above and below share their halo
+        // rows in one XCD's L2
+        strip_order(xcd_remap(b - nring, (int)gridDim.x - nring), L.tiles_x, in.rows, tx, ty);
+        if (!in.interior(tx, ty)) return;
+        pair_tile<T, ALPHA, TH, WAVES, true>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1,
+                                             bad2);
+    }
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 
-// Every tile in one launch (strip order; each tile takes the interior path
-// when its halo is inside the grid): on small lattices, where the ring is a
-// large share of the nodes and a second launch's latency counts, this beats
-// the interior + ring pair (launch_theta2_k chooses).
+// Every tile in one launch, all on the boundary code path (strip order): on
+// small lattices, where the ring is a large share of the nodes, this beats
+// splitting the tiles by path (launch_theta2_k chooses).
 template <typename T, int ALPHA, int TH, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2_all(Lattice L,
                                                                 const T *__restrict__ m_in,
@@ -195,29 +206,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2_all(Lattice L,
                 ty);
     bool bad1 = false, bad2 = false;
     pair_tile<T, ALPHA, TH, WAVES, false>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
-    if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
-}
-
-// The ring of a tiling (ring_tiles) as 64 x 4 tiles: one workgroup per tile.
-template <typename T, int ALPHA>
-__global__ __launch_bounds__(256) void k_iter_theta2_ring(Lattice L, TileRange ring,
-                                                          const T *__restrict__ m_in,
-                                                          T *__restrict__ m_out,
-                                                          const T *__restrict__ gain,
-                                                          const T *__restrict__ bw, T eta,
-                                                          uint32_t *__restrict__ diverged_at,
-                                                          const uint32_t *__restrict__ t_base,
-                                                          uint32_t t_off) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
-    __shared__ T lds[DEG * kRingRows * 64];
-    const uint32_t t = *t_base + t_off;
-    const uint32_t seen = *diverged_at;
-    if (seen != 0u && seen <= t) return;
-    int tx, ty;
-    ring.ring((int)blockIdx.x, tx, ty);
-    bool bad1 = false, bad2 = false;
-    pair_tile<T, ALPHA, kRingRows, 4, false>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1,
-                                             bad2);
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 
@@ -322,13 +310,12 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
     return hipGetLastError();
 }
 
+// A lattice whose ring holds more than 1/kRingShareSplit of the nodes runs
+// its passes as k_iter_theta2_all.
+constexpr int64_t kRingShareSplit = 20;
+
 // tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8,
 // 12 rows on 12, 32 rows on 16
-#ifndef GABP_RING_SHARE_SPLIT
-#define GABP_RING_SHARE_SPLIT 20
-#endif
-constexpr int64_t kRingShareSplit = GABP_RING_SHARE_SPLIT;
-
 template <typename T, int ALPHA, int TH>
 static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, const void *gain,
                             const void *bw, double eta, uint32_t *flag, const uint32_t *t_base,
@@ -336,24 +323,22 @@ static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, con
     constexpr int WAVES = TH == 4 ? 4 : TH == 12 ? 12 : TH == 32 ? 16 : 8;
     constexpr int R = ALPHA == 1 ? 1 : 2;
     const TileRange in = interior_tiles(L.nx, L.ny, R, TH);
-    const TileRange ring = ring_tiles(L.nx, L.ny, R, TH);
-    // one launch over every tile when the ring (64 x 4 tiles) holds more than
-    // 1/kRingShareSplit of the nodes
-    if (ring.ring_count() * 256 * kRingShareSplit > (int64_t)L.nx * L.ny) {
+    // one launch over every tile on the boundary path when the ring holds
+    // more than 1/kRingShareSplit of the nodes
+    if (in.ring_count() * 64 * TH * kRingShareSplit > (int64_t)L.nx * L.ny) {
         hipLaunchKernelGGL((k_iter_theta2_all<T, ALPHA, TH, WAVES>),
                            dim3(L.tiles_x * ((L.ny + TH - 1) / TH)), dim3(64 * WAVES), 0, s, L,
                            (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
                            flag, t_base, t_off);
         return;
     }
-    if (in.hole_count() > 0)
-        hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>), dim3(L.tiles_x * in.rows),
-                           dim3(64 * WAVES), 0, s, L, (const T *)m_in, (T *)m_out,
-                           (const T *)gain, (const T *)bw, (T)eta, flag, t_base, t_off);
-    if (ring.ring_count() > 0)
-        hipLaunchKernelGGL((k_iter_theta2_ring<T, ALPHA>), dim3((unsigned)ring.ring_count()),
-                           dim3(256), 0, s, L, ring, (const T *)m_in, (T *)m_out,
-                           (const T *)gain, (const T *)bw, (T)eta, flag, t_base, t_off);
+    // the ring's workgroups first, their count rounded up to a multiple of
+    // the 8 XCDs so that the interior tiles keep xcd_remap's mapping
+    const int nring = (int)((in.ring_count() + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>),
+                       dim3((unsigned)(nring + L.tiles_x * in.rows)), dim3(64 * WAVES), 0, s, L,
+                       in, nring, (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw,
+                       (T)eta, flag, t_base, t_off);
 }
 
 hipError_t launch_iter_theta2(int dtype, int th, const Lattice &L, const void *m_in, void *m_out,

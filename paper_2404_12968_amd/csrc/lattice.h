@@ -142,15 +142,11 @@ __device__ __forceinline__ void strip_order(int t, int tiles_x, int rows, int &t
 // or leaves it (R: the stencil radius for a two-iteration pass, whose halo
 // nodes need their own neighbours; 2R = 2 covers a single iteration of a
 // radius-2 stencil).  Interior tiles form the index range [txa, txb] x
-// [tya, tyb] (empty when a > b).  They run in kernels compiled without the
-// boundary paths, whose registers would otherwise cost occupancy.  The other
-// tiles, the ring, are enumerated band by band (top rows, bottom rows, then
-// the left and right columns of the rows between); ring_tiles gives the same
-// hole on the 64 x 4 grid (the interior range always ends on a multiple of 4
-// rows).
+// [tya, tyb] (empty when a > b).  They run on code paths compiled without
+// the boundary handling, whose registers would otherwise cost occupancy.
+// The other tiles, the ring, are enumerated band by band (top rows, bottom
+// rows, then the left and right columns of the rows between).
 // --------------------------------------------------------------------------
-constexpr int kRingRows = 4;
-
 struct TileRange {
     int txa, txb, tya, tyb;   // interior (hole) range, inclusive
     int cols, rows;           // tile grid
@@ -200,21 +196,6 @@ __host__ __device__ inline TileRange interior_tiles(int nx, int ny, int R, int T
     r.txb = nx - 64 - 2 * R >= 0 ? (nx - 64 - 2 * R) / 64 : -1;
     r.tya = (2 * R + TH - 1) / TH;
     r.tyb = ny - TH - 2 * R >= 0 ? (ny - TH - 2 * R) / TH : -1;
-    return r;
-}
-
-// The same hole on the 64 x kRingRows tile grid, whose other tiles are the ring.
-__host__ __device__ inline TileRange ring_tiles(int nx, int ny, int R, int TH) {
-    const TileRange in = interior_tiles(nx, ny, R, TH);
-    TileRange r = in;
-    r.rows = (ny + kRingRows - 1) / kRingRows;
-    if (in.empty()) {
-        r.txa = 1;
-        r.txb = 0;
-        return r;
-    }
-    r.tya = in.tya * (TH / kRingRows);
-    r.tyb = (in.tyb + 1) * (TH / kRingRows) - 1;
     return r;
 }
 

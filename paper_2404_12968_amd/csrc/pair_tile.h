@@ -148,7 +148,6 @@ __device__ __forceinline__ void pair_tile(const Lattice &L, const T *__restrict_
     constexpr int R = ALPHA == 1 ? 1 : 2;
     constexpr int RPT = TH / WAVES;
     static_assert(TH % WAVES == 0, "tile rows must be a multiple of the wave count");
-    static_assert(TH % kRingRows == 0, "tile rows must be a multiple of the ring tiles' rows");
     // lds[(d * TH + y) * 64 + x]: incoming message of tile node (x, y) from
     // direction d at t+1 (receiver-indexed)
     const int x0 = tx * 64, y0 = ty * TH;

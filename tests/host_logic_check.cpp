@@ -1,8 +1,8 @@
 // Host-side checks of the library's host logic, compiled and run by
 // tests/test_host_logic.py: the precision-freeze decision
 // (gabp::host::freeze_now), the device workspace layout
-// (gabp::host::make_layout) and the tile ranges of the split launches
-// (gabp::interior_tiles, gabp::ring_tiles, TileRange::ring).  Exit status 0
+// (gabp::host::make_layout) and the tile ranges of the two-iteration pass
+// (gabp::interior_tiles, TileRange::ring).  Exit status 0
 // and "ok" when every case holds.
 #include <cmath>
 #include <cstdio>
@@ -141,8 +141,7 @@ int main() {
                         CHECK(!in.interior(tx, ty));
                         CHECK(seen[(size_t)ty * in.cols + tx]++ == 0);
                     }
-                    // nodes written: hole tiles (64 x TH) and ring tiles (64 x 4)
-                    const gabp::TileRange rg = gabp::ring_tiles(nx, ny, R, TH);
+                    // nodes written: hole tiles and ring tiles, each node once
                     std::vector<int> cover((size_t)nx * ny, 0);
                     for (int ty = 0; ty < in.rows; ++ty)
                         for (int tx = 0; tx < in.cols; ++tx) {
@@ -151,11 +150,10 @@ int main() {
                                 for (int x = 64 * tx; x < std::min(nx, 64 * tx + 64); ++x)
                                     ++cover[(size_t)y * nx + x];
                         }
-                    for (int b = 0; b < (int)rg.ring_count(); ++b) {
+                    for (int b = 0; b < (int)in.ring_count(); ++b) {
                         int tx = -1, ty = -1;
-                        rg.ring(b, tx, ty);
-                        CHECK(tx >= 0 && tx < rg.cols && ty >= 0 && ty < rg.rows);
-                        for (int y = 4 * ty; y < std::min(ny, 4 * ty + 4); ++y)
+                        in.ring(b, tx, ty);
+                        for (int y = TH * ty; y < std::min(ny, TH * ty + TH); ++y)
                             for (int x = 64 * tx; x < std::min(nx, 64 * tx + 64); ++x)
                                 ++cover[(size_t)y * nx + x];
                     }
