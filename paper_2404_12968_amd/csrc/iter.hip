@@ -139,8 +139,9 @@ __global__ __launch_bounds__(256) void k_iter_theta(Lattice L, const T *__restri
     if (bad) *diverged_at = t;
 }
 
-// A two-iteration pass on a lattice with a large interior is one launch over
-// two sets of 64 x TH tiles: the first nring workgroups take the ring (the
+// A two-iteration pass is one launch over two sets of 64 x TH tiles (on any
+// lattice; a small one may have no interior tiles): the first nring
+// workgroups take the ring (the
 // tiles whose halo reaches a boundary, TileRange::ring order) on the
 // boundary code path; the others walk the tile grid in strip order and take
 // the interior tiles (a ring tile there returns at once) on a path compiled
@@ -181,31 +182,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_iter_theta2(Lattice L, TileRange
         pair_tile<T, ALPHA, TH, WAVES, true>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1,
                                              bad2);
     }
-    if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
-}
-
-// Every tile in one launch, all on the boundary code path (strip order): on
-// small lattices, where the ring is a large share of the nodes, this beats
-// splitting the tiles by path (launch_theta2_k chooses).
-template <typename T, int ALPHA, int TH, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_iter_theta2_all(Lattice L,
-                                                                const T *__restrict__ m_in,
-                                                                T *__restrict__ m_out,
-                                                                const T *__restrict__ gain,
-                                                                const T *__restrict__ bw, T eta,
-                                                                uint32_t *__restrict__ diverged_at,
-                                                                const uint32_t *__restrict__ t_base,
-                                                                uint32_t t_off) {
-    constexpr int DEG = ALPHA == 1 ? 4 : 12;
-    __shared__ T lds[DEG * TH * 64];
-    const uint32_t t = *t_base + t_off;
-    const uint32_t seen = *diverged_at;
-    if (seen != 0u && seen <= t) return;
-    int tx, ty;
-    strip_order(xcd_remap((int)blockIdx.x, (int)gridDim.x), L.tiles_x, (L.ny + TH - 1) / TH, tx,
-                ty);
-    bool bad1 = false, bad2 = false;
-    pair_tile<T, ALPHA, TH, WAVES, false>(L, m_in, m_out, gain, bw, eta, tx, ty, lds, bad1, bad2);
     if (bad1 || bad2) record_divergence(diverged_at, bad1 ? t + 1u : t + 2u);
 }
 
@@ -310,10 +286,6 @@ hipError_t launch_iter_theta(int dtype, int rpt, const Lattice &L, const void *m
     return hipGetLastError();
 }
 
-// A lattice whose ring holds more than 1/kRingShareSplit of the nodes runs
-// its passes as k_iter_theta2_all.
-constexpr int64_t kRingShareSplit = 20;
-
 // tile height -> waves per workgroup: 4 rows on 4 waves, 8 and 16 rows on 8,
 // 12 rows on 12, 32 rows on 16
 template <typename T, int ALPHA, int TH>
@@ -323,20 +295,12 @@ static void launch_theta2_k(const Lattice &L, const void *m_in, void *m_out, con
     constexpr int WAVES = TH == 4 ? 4 : TH == 12 ? 12 : TH == 32 ? 16 : 8;
     constexpr int R = ALPHA == 1 ? 1 : 2;
     const TileRange in = interior_tiles(L.nx, L.ny, R, TH);
-    // one launch over every tile on the boundary path when the ring holds
-    // more than 1/kRingShareSplit of the nodes
-    if (in.ring_count() * 64 * TH * kRingShareSplit > (int64_t)L.nx * L.ny) {
-        hipLaunchKernelGGL((k_iter_theta2_all<T, ALPHA, TH, WAVES>),
-                           dim3(L.tiles_x * ((L.ny + TH - 1) / TH)), dim3(64 * WAVES), 0, s, L,
-                           (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw, (T)eta,
-                           flag, t_base, t_off);
-        return;
-    }
     // the ring's workgroups first, their count rounded up to a multiple of
     // the 8 XCDs so that the interior tiles keep xcd_remap's mapping
     const int nring = (int)((in.ring_count() + 7) / 8 * 8);
+    const int ninner = in.hole_count() > 0 ? L.tiles_x * in.rows : 0;
     hipLaunchKernelGGL((k_iter_theta2<T, ALPHA, TH, WAVES>),
-                       dim3((unsigned)(nring + L.tiles_x * in.rows)), dim3(64 * WAVES), 0, s, L,
+                       dim3((unsigned)(nring + ninner)), dim3(64 * WAVES), 0, s, L,
                        in, nring, (const T *)m_in, (T *)m_out, (const T *)gain, (const T *)bw,
                        (T)eta, flag, t_base, t_off);
 }
