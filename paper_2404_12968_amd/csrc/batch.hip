@@ -149,8 +149,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch_pair(const BatchInst *__re
     const T *m_in = (const T *)B.msg[second ? own ^ 1u : own];
     T *m_out = (T *)B.msg[second ? own : own ^ 1u];
     bool bad1 = false, bad2 = false;
-    pair_tile<T, ALPHA, TH, WAVES>(L, m_in, m_out, (const T *)B.gain, (const T *)B.b_w, eta, tx,
-                                   ty, lds, bad1, bad2);
+    // interior tiles on the path compiled without boundary code (uniform
+    // across the workgroup)
+    if (interior_tiles(L.nx, L.ny, ALPHA == 1 ? 1 : 2, TH).interior(tx, ty))
+        pair_tile<T, ALPHA, TH, WAVES, true>(L, m_in, m_out, (const T *)B.gain, (const T *)B.b_w,
+                                             eta, tx, ty, lds, bad1, bad2);
+    else
+        pair_tile<T, ALPHA, TH, WAVES, false>(L, m_in, m_out, (const T *)B.gain,
+                                              (const T *)B.b_w, eta, tx, ty, lds, bad1, bad2);
     if (bad1 || bad2) record_divergence(&diverged_at[I], bad1 ? t + 1u : t + 2u);
 }
 
