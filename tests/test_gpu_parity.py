@@ -491,7 +491,7 @@ def test_global8192_sampled_windows_match_oracle(G, oracle_mod):
 @pytest.mark.parametrize("pair", [12, 16])
 def test_global8192_two_iteration_kernel_is_bitwise_identical(G, pair):
     """The 8192 x 4096 workload in the configurations the benchmark times
-    (12- and 16-row two-iteration tiles, interior and ring launches, once the
+    (12- and 16-row two-iteration tiles, ring and interior paths, once the
     precision messages froze): every message equals the single-iteration
     kernel's after the same iterations."""
     prob = I.global8192()
@@ -587,8 +587,8 @@ def _freeze(G, ctx):
     ("f32", 2, 32, 140, 75, I.BC_PERIODIC, I.BC_NEUMANN),
     ("f32", 2, 12, 150, 70, I.BC_NEUMANN, I.BC_DIRICHLET),
     ("f32", 2, 12, 132, 28, I.BC_NEUMANN, I.BC_PERIODIC),   # one interior tile
-    # lattices whose ring holds under 5 % of the nodes: the pass is the
-    # interior launch plus the ring launch (smaller ones run as one launch)
+    # large lattices: most workgroups on the interior path, the ring a few
+    # per cent of the nodes
     ("f32", 2, 16, 4096, 2048, I.BC_NEUMANN, I.BC_DIRICHLET),
     ("f32", 2, 12, 4100, 2060, I.BC_PERIODIC, I.BC_PERIODIC),
     ("f64", 2, 4, 4096, 2048, I.BC_NEUMANN, I.BC_NEUMANN),
