@@ -113,8 +113,8 @@ int main() {
         }
     }
     // tile ranges: the interior range is exactly the tiles whose halo of 2R
-    // lies inside the grid; ring() visits every other tile once; the hole
-    // tiles plus the 64 x 4 ring tiles cover every node once
+    // lies inside the grid; ring() visits every other tile once; hole and
+    // ring tiles together cover every node once
     const int dims_x[] = {1, 5, 63, 64, 67, 68, 69, 131, 132, 133, 200, 1000};
     const int dims_y[] = {1, 3, 5, 7, 12, 13, 16, 17, 23, 28, 40, 97, 301};
     for (int nx : dims_x) {
